@@ -1,0 +1,122 @@
+"""Pins of the grid judge: textbook Laplacian away from the interface,
+symmetry, patch test (linear solutions, planar interface, with and without a
+coefficient contrast) and second-order convergence on manufactured problems."""
+import numpy as np
+import pytest
+
+import nbm_inputs as I
+from oracle import grid as GR
+from oracle import nbm as N
+from oracle import scheme as S
+
+
+def test_uncut_rows_are_textbook_laplacian():
+    gs = GR.GridSystem(I.C2, 16)
+    rng = np.random.default_rng(0)
+    u = rng.normal(size=gs.N)
+    u[~gs.interior] = 0.0
+    Au = GR.apply_A(3, 16, gs.cface, u)
+    n = 16
+    U = u.reshape(n + 1, n + 1, n + 1)    # [i2, i1, i0]
+    lap = np.zeros_like(U)
+    lap[1:-1, 1:-1, 1:-1] = (6 * U[1:-1, 1:-1, 1:-1] - U[2:, 1:-1, 1:-1] - U[:-2, 1:-1, 1:-1]
+                             - U[1:-1, 2:, 1:-1] - U[1:-1, :-2, 1:-1]
+                             - U[1:-1, 1:-1, 2:] - U[1:-1, 1:-1, :-2])
+    lap = lap.ravel()
+    mu = np.where(gs.side, I.C2.mu_minus, I.C2.mu_plus)
+    # uncut nodes whose neighbours are uncut too
+    ok = np.zeros(gs.N, dtype=bool)
+    ok[gs.uncut] = True
+    cut = np.zeros(gs.N, dtype=bool)
+    cut[gs.cut] = True
+    far = ok.copy()
+    for a in range(3):
+        for sg in (1, -1):
+            idx = np.nonzero(ok)[0]
+            far[idx] &= ~cut[idx + sg * gs.stride[a]]
+    assert far.sum() > 500
+    assert np.allclose(Au[far], mu[far] * lap[far], rtol=0, atol=1e-12)
+
+
+def test_operator_symmetric():
+    gs = GR.GridSystem(I.C4, 16)
+    rng = np.random.default_rng(1)
+    u, v = rng.normal(size=(2, gs.N))
+    u[~gs.interior] = 0
+    v[~gs.interior] = 0
+    a = GR.apply_A(3, 16, gs.cface, u) @ v
+    b = GR.apply_A(3, 16, gs.cface, v) @ u
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+@pytest.mark.parametrize("dim,mu", [(2, (1.0, 1.0)), (3, (1.0, 1.0)), (3, (1.0, 10.0)), (3, (100.0, 1.0))])
+def test_patch_test_linear_planar(dim, mu):
+    """Linear u^+- across a planar interface, constant mu^+- of any contrast,
+    consistent alpha (linear) and beta (constant): the exact nodal values
+    satisfy every row and the solver returns them."""
+    base = I.C1 if dim == 2 else I.C2
+    nv = (0.6, 0.8, 0.0) if dim == 2 else (0.6, 0.48, 0.64)
+    wl = base.replace(interface=I.IFACE_PLANE, plane_n=nv, plane_c=0.07, problem=I.PROB_LINEAR,
+                      mu_minus=mu[0], mu_plus=mu[1])
+    n = 16
+    gs = GR.GridSystem(wl, n)
+    assert gs.cut.size > 10
+    lo = S.lo_side(wl)
+    glo_fn = None if lo < 0 else (lambda y: gs.prob.grad_u_side(lo, y))
+    U = gs.solve(tol=1e-13, glo_fn=glo_fn)
+    ex = gs.prob.u_exact(gs.x)
+    assert np.abs(U - ex).max() < 1e-10
+
+
+def test_collocation_residual_equals_grid_rows():
+    """Grid-table provider: the collocation residual at grid nodes, with the
+    nodal values taken from a grid array, equals the assembled grid row
+    (A U - b)/(h^2 mubar) (equal coefficients)."""
+    wl = I.C1
+    n = 32
+    gs = GR.GridSystem(wl, n)
+    rng = np.random.default_rng(2)
+    Ufull = gs.prob.u_exact(gs.x) + 0.01 * rng.normal(size=gs.N)
+    Ufull[~gs.interior] = gs.prob.g(gs.x[~gs.interior])
+    rows = gs.row_residual(Ufull)
+
+    def table(s, X):
+        i = np.rint((X + 1.0) / gs.h).astype(np.int64)
+        return Ufull[i[:, 0] + (n + 1) * i[:, 1]]
+
+    ip = np.nonzero(gs.interior)[0]
+    res = N.residuals(wl, None, gs.x[ip], np.zeros((0, 2)), h=gs.h, provider=table)
+    assert np.allclose(res["r"], rows[ip], rtol=1e-9, atol=1e-7)
+
+
+def test_exact_provider_uncut_residual_second_order():
+    wl = I.C2
+    pts, _ = I.collocation_batch(wl, 4000, 0, seed=4)
+    rms = []
+    for h in (1 / 16, 1 / 32, 1 / 64):
+        res = N.residuals(wl, None, pts, np.zeros((0, 3)), h=h, provider=N.exact_provider(wl))
+        m = res["cls"] != S.CLASS_CUT
+        rms.append(np.sqrt(np.mean(res["r"][m] ** 2)))
+    assert rms[1] / rms[2] > 3.5 and rms[0] / rms[1] > 3.5
+
+
+def test_convergence_2d_second_order():
+    errs = []
+    for n in (32, 64, 128):
+        gs = GR.GridSystem(I.C1, n)
+        U = gs.solve()
+        errs.append(np.abs(U - gs.prob.u_exact(gs.x))[gs.interior].max())
+        assert gs.relres <= 1e-12
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert orders[-1] > 1.8, orders
+
+
+def test_convergence_3d_contrast():
+    errs = []
+    for n in (32, 64):
+        gs = GR.GridSystem(I.C2, n)
+        U = gs.solve()
+        errs.append(np.abs(U - gs.prob.u_exact(gs.x))[gs.interior].max())
+        assert gs.picard_iters < 30
+    order = np.log2(errs[0] / errs[1])
+    assert order > 1.5 and errs[1] < 6e-4, (errs, order)
