@@ -1,0 +1,161 @@
+/*
+ * nbm.h — C ABI of the MI355X (gfx950) Neural Bootstrapping Method library.
+ *
+ * The Neural Bootstrapping Method (paper: "Neuro-Symbolic Partial Differential
+ * Equation Solver", Sec. 3) trains two networks u^- and u^+, one per side of a
+ * level-set interface, by minimising the locally preconditioned residual of a
+ * finite-volume discretisation of the interface problem of Sec. 2,
+ *     k u - div(mu grad u) = f in Omega^+-,  [u] = alpha, [mu d_n u] = beta on Gamma,
+ * evaluated on implicit cells centred at random collocation points, with
+ * automatic differentiation through the residual kernels and Adam.
+ * The paper's loss equation is missing from its text; the residual computed
+ * here is the cut-cell reading stated in the design doc (vertex-centred cell of
+ * side h at each point, face/volume fractions of the piecewise-linear level
+ * set, jump extension J = alpha + dist * [d_n u], Jacobi preconditioning,
+ * loss = mean of squared point residuals, interior and boundary points).
+ *
+ * Conventions shared by every entry point
+ *   - Device memory is owned by the caller (e.g. torch tensors passed as raw
+ *     pointers).  The library owns only the host-side context; it never
+ *     allocates device memory.  Every pointer marked "device" must point to
+ *     memory on the current HIP device.
+ *   - Every call is asynchronous on the given stream and never synchronises
+ *     the device.  A NULL stream means the default stream.
+ *   - Return 0 on success or a negative NBM_E* code.  Arguments are validated
+ *     before any launch; on error nothing is enqueued and nbm_last_error()
+ *     describes the problem.  No C++ exception crosses the ABI.
+ *   - NaN/Inf propagate.  If a batch holds more cut cells than the context's
+ *     cut capacity, the loss is written as NaN.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Parameters are FP32, packed net^- then net^+; per net: W1[W][d], b1[W],
+ *     then for l = 2..L: W_l[W][W], b_l[W], then w_out[W], b_out (matrices
+ *     row-major, row = output neuron).
+ *   - Points are FP32 [n][d] row-major.  Interior points must lie in
+ *     [-1+h, 1-h]^d, boundary points on the faces of [-1,1]^d.
+ */
+#ifndef NBM_H
+#define NBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NBM_OK 0
+#define NBM_EINVAL -1       /* invalid argument or configuration */
+#define NBM_EWORKSPACE -2   /* workspace missing, too small, or not prepared */
+#define NBM_EUNSUPPORTED -3 /* configuration not compiled into this library */
+#define NBM_EHIP -4         /* a HIP runtime call failed */
+
+#define NBM_ACT_TANH 0
+#define NBM_ACT_SIN 1
+#define NBM_PREC_FP32 0     /* FP32 MFMA operands, FP32 accumulation */
+#define NBM_PREC_BF16 1     /* BF16 MFMA operands, FP32 accumulation */
+#define NBM_IFACE_SPHERE 0  /* |x| - radius (circle in 2-D) */
+#define NBM_IFACE_STAR 1    /* |x| - radius - amp sin(5 theta) sin(4 psi) */
+#define NBM_IFACE_PLANE 2   /* plane_n . x - plane_c */
+#define NBM_PROB_MMS_2D 0   /* u^- = exp(x+y), u^+ = sin(pi x) cos(pi y) */
+#define NBM_PROB_MMS_SPHERE 1 /* u^- = exp(z), u^+ = cos x sin y (paper Sec. 4.1) */
+#define NBM_PROB_FOURIER 2  /* f^- = f^+ = sum_k a_k cos(pi k.x) + b_k sin(pi k.x) */
+#define NBM_PROB_LINEAR 3   /* u^- = a.x + a0, u^+ = b.x + b0 */
+
+/* Problem and network description (paper Sec. 2 problem statement; Sec. 3
+ * two networks; Sec. 4.1 workload).  Host memory, copied by nbm_create. */
+typedef struct nbm_config {
+  int32_t dim;        /* 2 or 3 */
+  int32_t width;      /* W, hidden width */
+  int32_t depth;      /* L >= 2 hidden layers (L-1 hidden->hidden matrices) */
+  int32_t act;        /* NBM_ACT_* */
+  int32_t prec;       /* NBM_PREC_* */
+  double h;           /* implicit cell spacing, a power of two in [2^-20, 2^-2] */
+  int32_t interface_kind; /* NBM_IFACE_* */
+  double radius;      /* sphere / star radius */
+  double star_amp;    /* star amplitude */
+  double plane_n[3];  /* plane normal (unit) */
+  double plane_c;     /* plane offset */
+  double mu_minus, mu_plus; /* piecewise-constant diffusion coefficients > 0 */
+  double k_minus, k_plus;   /* Helmholtz coefficients: must be 0 (not compiled) */
+  int32_t problem;    /* NBM_PROB_* */
+  double alpha_const, beta_const; /* jump data of NBM_PROB_FOURIER */
+  double lin_a[4], lin_b[4];      /* NBM_PROB_LINEAR coefficients */
+  int32_t n_modes;    /* NBM_PROB_FOURIER: number of modes */
+  const int32_t* mode_k; /* host [n_modes][3] integer wave vectors */
+  const double* mode_a;  /* host [n_modes] cosine amplitudes */
+  const double* mode_b;  /* host [n_modes] sine amplitudes */
+  int64_t max_points;    /* largest interior batch n the workspace must hold */
+  int64_t max_boundary;  /* largest boundary batch nb */
+  int64_t cut_capacity;  /* max cut cells per batch; 0 -> max_points/8 + 64 */
+} nbm_config;
+
+typedef struct nbm_ctx nbm_ctx;
+
+/* Validate cfg and create a host-side context.  No device work. */
+int nbm_create(const nbm_config* cfg, nbm_ctx** out);
+void nbm_destroy(nbm_ctx* ctx);
+
+/* Number of FP32 parameters (both networks). */
+int64_t nbm_param_count(const nbm_ctx* ctx);
+
+/* Device workspace bytes needed for batches up to (max_points, max_boundary)
+ * and for nbm_eval tiles up to max_points queries. */
+size_t nbm_workspace_bytes(const nbm_ctx* ctx);
+
+/* Copy the problem tables (Fourier modes) into the workspace.  Must be called
+ * once for each workspace before the other workspace-using calls; blocks the
+ * host until the copy is done. */
+int nbm_prepare(nbm_ctx* ctx, void* stream, void* ws, size_t ws_bytes);
+
+/* Random collocation points (paper Sec. 3: residuals minimised on randomly
+ * sampled points).  Philox4x32-10, interior point i of step s uses counter
+ * (i, s_lo, s_hi, 0), boundary point b (b, s_lo, s_hi, 1), key = seed.
+ * Interior points on the 2^-22 lattice in [-1+h, 1-h]^d, boundary points on
+ * the lattice of the faces of [-1,1]^d.  pts [n][d], bpts [nb][d] device. */
+int nbm_sample_points(nbm_ctx* ctx, void* stream, uint64_t seed, int64_t step, float* pts,
+                      int64_t n, float* bpts, int64_t nb);
+
+/* Forward pass: residual of every interior and boundary point and the loss
+ * L = (sum_p r_p^2 + sum_b r_b^2) / (n + nb), accumulated in FP64
+ * (paper Sec. 3: point residuals r_p = |M^-1 A u - M^-1 b| aggregated into a
+ * global loss).  params [P] device; pts [n][d], bpts [nb][d] device;
+ * residual [n + nb] device or NULL; loss: one device double.
+ * If grad is not NULL the same pass also writes dL/dtheta [P] (FP32, reduced
+ * in FP64 in a fixed order): the fused forward + residual + backward step. */
+int nbm_forward_residual(nbm_ctx* ctx, void* stream, const float* params, const float* pts,
+                         int64_t n, const float* bpts, int64_t nb, float* residual,
+                         double* loss, float* grad, void* ws, size_t ws_bytes);
+
+/* Backward pass (paper Sec. 3: automatic differentiation across the NBM
+ * kernels): recomputes the forward pass and writes dL * dL/dtheta into
+ * grad [P] (device FP32).  Holds no state between calls. */
+int nbm_backward(nbm_ctx* ctx, void* stream, const float* params, const float* pts, int64_t n,
+                 const float* bpts, int64_t nb, double dL, float* grad, void* ws,
+                 size_t ws_bytes);
+
+/* Adam (paper Sec. 3), bias-corrected, FP32, in place on params, m, v [P]
+ * (device); grad [P] device; step is 1-based. */
+int nbm_adam_step(nbm_ctx* ctx, void* stream, float* params, float* m, float* v,
+                  const float* grad, int64_t step, float lr, float beta1, float beta2,
+                  float eps);
+
+/* Evaluate the surrogate u(x) = u^{sigma(x)}(x) (network of the side of x).
+ * With query != NULL: query [m][d] device points.  With query == NULL: the
+ * points of tile `tile_index` of the grid_n^d lattice x = -1 + 2 i / grid_n
+ * (i = 0..grid_n-1 per axis, axis 0 fastest, tiles of m consecutive points)
+ * are generated in the kernel.  u_out [m] device FP32.  m <= max_points. */
+int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const float* query, int64_t m,
+             int64_t tile_index, int32_t grid_n, float* u_out, void* ws, size_t ws_bytes);
+
+/* Classes of the last batch seen by nbm_forward_residual / nbm_backward on
+ * this workspace, written to counts[8] (device int32): interior A^-, A^+,
+ * cut, boundary^-, boundary^+, overflow flag, 0, 0. */
+int nbm_batch_counts(nbm_ctx* ctx, void* stream, int32_t* counts, void* ws, size_t ws_bytes);
+
+/* Thread-local description of the last error. */
+const char* nbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBM_H */

@@ -1,0 +1,184 @@
+"""Thin ctypes binding of libnbm.so (argument marshalling only).
+
+Every step of the NBM path runs in the library's gfx950 kernels; PyTorch only
+provides device memory and the current HIP stream.  Loading fails loudly if
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+import torch
+
+import nbm_inputs as I
+
+LIB_PATH = Path(__file__).resolve().parent / "libnbm.so"
+_lib = None
+
+EXPORTS = ["nbm_create", "nbm_destroy", "nbm_param_count", "nbm_workspace_bytes", "nbm_prepare",
+           "nbm_sample_points", "nbm_forward_residual", "nbm_backward", "nbm_adam_step", "nbm_eval",
+           "nbm_batch_counts", "nbm_last_error"]
+
+
+class NbmConfig(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("width", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("act", ctypes.c_int32), ("prec", ctypes.c_int32), ("h", ctypes.c_double),
+                ("interface_kind", ctypes.c_int32), ("radius", ctypes.c_double),
+                ("star_amp", ctypes.c_double), ("plane_n", ctypes.c_double * 3),
+                ("plane_c", ctypes.c_double), ("mu_minus", ctypes.c_double),
+                ("mu_plus", ctypes.c_double), ("k_minus", ctypes.c_double),
+                ("k_plus", ctypes.c_double), ("problem", ctypes.c_int32),
+                ("alpha_const", ctypes.c_double), ("beta_const", ctypes.c_double),
+                ("lin_a", ctypes.c_double * 4), ("lin_b", ctypes.c_double * 4),
+                ("n_modes", ctypes.c_int32), ("mode_k", ctypes.POINTER(ctypes.c_int32)),
+                ("mode_a", ctypes.POINTER(ctypes.c_double)), ("mode_b", ctypes.POINTER(ctypes.c_double)),
+                ("max_points", ctypes.c_int64), ("max_boundary", ctypes.c_int64),
+                ("cut_capacity", ctypes.c_int64)]
+
+
+class NbmError(RuntimeError):
+    pass
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise NbmError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(there is no CPU fallback)")
+        L = ctypes.CDLL(str(LIB_PATH))
+        vp, i64, f32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+        L.nbm_create.argtypes = [ctypes.POINTER(NbmConfig), ctypes.POINTER(vp)]
+        L.nbm_destroy.argtypes = [vp]
+        L.nbm_destroy.restype = None
+        L.nbm_param_count.argtypes = [vp]
+        L.nbm_param_count.restype = i64
+        L.nbm_workspace_bytes.argtypes = [vp]
+        L.nbm_workspace_bytes.restype = ctypes.c_size_t
+        L.nbm_prepare.argtypes = [vp, vp, vp, ctypes.c_size_t]
+        L.nbm_sample_points.argtypes = [vp, vp, ctypes.c_uint64, i64, vp, i64, vp, i64]
+        L.nbm_forward_residual.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, ctypes.c_size_t]
+        L.nbm_backward.argtypes = [vp, vp, vp, vp, i64, vp, i64, f64, vp, vp, ctypes.c_size_t]
+        L.nbm_adam_step.argtypes = [vp, vp, vp, vp, vp, vp, i64, f32, f32, f32, f32]
+        L.nbm_eval.argtypes = [vp, vp, vp, vp, i64, i64, ctypes.c_int32, vp, vp, ctypes.c_size_t]
+        L.nbm_batch_counts.argtypes = [vp, vp, vp, vp, ctypes.c_size_t]
+        L.nbm_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise NbmError(f"nbm error {rc}: {lib().nbm_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class NBM:
+    """One NBM problem/network configuration with its device workspace."""
+
+    def __init__(self, wl: I.Workload, max_points: int = None, max_boundary: int = None,
+                 cut_capacity: int = 0, device: str = "cuda:0"):
+        self.wl = wl
+        self.device = torch.device(device)
+        cfg = NbmConfig()
+        cfg.dim, cfg.width, cfg.depth = wl.dim, wl.width, wl.depth
+        cfg.act, cfg.prec, cfg.h = wl.act, wl.prec, wl.h
+        cfg.interface_kind, cfg.radius, cfg.star_amp = wl.interface, wl.radius, wl.star_amp
+        for i in range(3):
+            cfg.plane_n[i] = wl.plane_n[i]
+        cfg.plane_c = wl.plane_c
+        cfg.mu_minus, cfg.mu_plus = wl.mu_minus, wl.mu_plus
+        cfg.k_minus = cfg.k_plus = 0.0
+        cfg.problem = wl.problem
+        cfg.alpha_const, cfg.beta_const = wl.alpha_const, wl.beta_const
+        for i in range(4):
+            cfg.lin_a[i], cfg.lin_b[i] = wl.lin_a[i], wl.lin_b[i]
+        if wl.problem == I.PROB_FOURIER:
+            k, a, b = I.fourier_modes(wl)
+            self._k = np.ascontiguousarray(k, dtype=np.int32)
+            self._a = np.ascontiguousarray(a, dtype=np.float64)
+            self._b = np.ascontiguousarray(b, dtype=np.float64)
+            cfg.n_modes = len(k)
+            cfg.mode_k = self._k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            cfg.mode_a = self._a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            cfg.mode_b = self._b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        cfg.max_points = wl.n_points if max_points is None else max_points
+        cfg.max_boundary = wl.n_boundary if max_boundary is None else max_boundary
+        cfg.cut_capacity = cut_capacity
+        self.cfg = cfg
+        h = ctypes.c_void_p()
+        _check(lib().nbm_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.ctx = h
+        self.P = lib().nbm_param_count(h)
+        self.ws_bytes = lib().nbm_workspace_bytes(h)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_view = self.ws[off:off + self.ws_bytes]
+        with torch.cuda.device(self.device):
+            _check(lib().nbm_prepare(h, _stream(), _ptr(self.ws_view), self.ws_bytes))
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                lib().nbm_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    # -- entry points --------------------------------------------------------
+    def sample_points(self, seed: int, step: int, n: int = None, nb: int = None):
+        n = self.wl.n_points if n is None else n
+        nb = self.wl.n_boundary if nb is None else nb
+        pts = torch.empty((n, self.wl.dim), dtype=torch.float32, device=self.device)
+        bpts = torch.empty((nb, self.wl.dim), dtype=torch.float32, device=self.device)
+        _check(lib().nbm_sample_points(self.ctx, _stream(), seed, step, _ptr(pts), n, _ptr(bpts), nb))
+        return pts, bpts
+
+    def forward_residual(self, params, pts, bpts, want_residual=False, want_grad=False,
+                         loss=None, grad=None, residual=None):
+        n, nb = pts.shape[0], bpts.shape[0]
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        if want_residual and residual is None:
+            residual = torch.empty(n + nb, dtype=torch.float32, device=self.device)
+        if want_grad and grad is None:
+            grad = torch.empty(self.P, dtype=torch.float32, device=self.device)
+        _check(lib().nbm_forward_residual(self.ctx, _stream(), _ptr(params), _ptr(pts), n, _ptr(bpts), nb,
+                                          _ptr(residual) if want_residual else None, _ptr(loss),
+                                          _ptr(grad) if want_grad else None, _ptr(self.ws_view),
+                                          self.ws_bytes))
+        return loss, (residual if want_residual else None), (grad if want_grad else None)
+
+    def backward(self, params, pts, bpts, dL=1.0, grad=None):
+        if grad is None:
+            grad = torch.empty(self.P, dtype=torch.float32, device=self.device)
+        _check(lib().nbm_backward(self.ctx, _stream(), _ptr(params), _ptr(pts), pts.shape[0], _ptr(bpts),
+                                  bpts.shape[0], float(dL), _ptr(grad), _ptr(self.ws_view), self.ws_bytes))
+        return grad
+
+    def adam_step(self, params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(lib().nbm_adam_step(self.ctx, _stream(), _ptr(params), _ptr(m), _ptr(v), _ptr(grad),
+                                   int(step), lr, beta1, beta2, eps))
+
+    def eval(self, params, query=None, m=None, tile_index=0, grid_n=0, out=None):
+        if query is not None:
+            m = query.shape[0]
+        if out is None:
+            out = torch.empty(m, dtype=torch.float32, device=self.device)
+        _check(lib().nbm_eval(self.ctx, _stream(), _ptr(params), _ptr(query), m, tile_index, grid_n,
+                              _ptr(out), _ptr(self.ws_view), self.ws_bytes))
+        return out
+
+    def batch_counts(self):
+        c = torch.zeros(8, dtype=torch.int32, device=self.device)
+        _check(lib().nbm_batch_counts(self.ctx, _stream(), _ptr(c), _ptr(self.ws_view), self.ws_bytes))
+        return c

@@ -1,0 +1,445 @@
+// C ABI of the NBM library (see include/nbm.h for the contract).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nbm.h"
+#include "nbm_internal.hpp"
+#include "nbm_launch.hpp"
+
+using namespace nbm;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                            \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess) return fail(NBM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+struct Layout {
+  size_t modes32, modes64, meta, blockcnt, off, blockcnt_b, off_b, cls, rank, bcls, brank, cutidx,
+      centres, src, outputs, adj, Zst, Ast, ALst, dZ, shadow, partial, lossp, resid, lossbuf, total;
+};
+}  // namespace
+
+struct nbm_ctx {
+  nbm_config cfg;
+  std::vector<float> modes32;
+  std::vector<double> modes64;
+  Problem P;
+  MlpFn mlp;
+  int D, W, L, S, opbytes;
+  int64_t per_net, Ptot;
+  NetLayout lay;
+  int64_t cap_n, cap_nb, cut_cap, cap_slots, cap_tiles, lstride;
+  int G;
+  Layout lo;
+  void* prepared_ws;
+};
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static void make_layout(nbm_ctx* c) {
+  Layout& L = c->lo;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  int64_t nblk = (c->cap_n + 255) / 256 + 1, nblkb = (c->cap_nb + 255) / 256 + 1;
+  int64_t nblkc = (c->cut_cap + 255) / 256 + 1;
+  L.modes32 = take(sizeof(float) * 8 * (c->cfg.n_modes + 1));
+  L.modes64 = take(sizeof(double) * 5 * (c->cfg.n_modes + 1));
+  L.meta = take(sizeof(Meta));
+  L.blockcnt = take(sizeof(int) * 4 * nblk);
+  L.off = take(sizeof(int) * 4 * nblk);
+  L.blockcnt_b = take(sizeof(int) * 4 * nblkb);
+  L.off_b = take(sizeof(int) * 4 * nblkb);
+  L.cls = take(sizeof(int) * c->cap_n);
+  L.rank = take(sizeof(int) * c->cap_n);
+  L.bcls = take(sizeof(int) * c->cap_nb);
+  L.brank = take(sizeof(int) * c->cap_nb);
+  L.cutidx = take(sizeof(int) * c->cut_cap);
+  L.centres = take(sizeof(float) * 4 * c->cap_slots);
+  L.src = take(sizeof(int) * c->cap_slots);
+  L.outputs = take(sizeof(float) * 8 * c->cap_slots);
+  L.adj = take(sizeof(float) * 8 * c->cap_slots);
+  L.Zst = take(sizeof(float) * c->L * c->lstride);
+  L.Ast = take((size_t)c->opbytes * (c->L - 1) * c->lstride);
+  L.ALst = take(sizeof(float) * c->lstride);
+  L.dZ = take(sizeof(float) * c->lstride);
+  L.shadow = take((size_t)c->opbytes * 2 * (c->L - 1) * 2 * c->W * c->W);
+  L.partial = take(sizeof(float) * (size_t)c->G * c->Ptot);
+  L.lossp = take(sizeof(double) * (nblk + nblkb + nblkc + 4));
+  L.resid = take(sizeof(float) * (c->cap_n + c->cap_nb));
+  L.lossbuf = take(sizeof(double) * 4);
+  L.total = o;
+}
+
+extern "C" const char* nbm_last_error(void) { return g_err.c_str(); }
+
+extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
+  if (!cfg || !out) return fail(NBM_EINVAL, "null argument");
+  const nbm_config& c = *cfg;
+  if (c.dim != 2 && c.dim != 3) return fail(NBM_EINVAL, "dim must be 2 or 3");
+  if (c.depth < 2 || c.depth > kMaxDepth) return fail(NBM_EINVAL, "depth must be in [2, 8]");
+  if (c.act != NBM_ACT_TANH && c.act != NBM_ACT_SIN) return fail(NBM_EINVAL, "bad activation");
+  if (c.prec != NBM_PREC_FP32 && c.prec != NBM_PREC_BF16) return fail(NBM_EINVAL, "bad precision");
+  int h_exp = 0;
+  if (!(c.h > 0.0) || c.h > 0.25 || c.h < std::ldexp(1.0, -20) || std::frexp(c.h, &h_exp) != 0.5)
+    return fail(NBM_EINVAL, "h must be a power of two in [2^-20, 2^-2]");
+  if (c.interface_kind < 0 || c.interface_kind > 2) return fail(NBM_EINVAL, "bad interface kind");
+  if (c.interface_kind == NBM_IFACE_STAR && c.dim != 3) return fail(NBM_EINVAL, "star needs dim 3");
+  if (!(c.mu_minus > 0.0) || !(c.mu_plus > 0.0)) return fail(NBM_EINVAL, "mu must be positive");
+  if (c.k_minus != 0.0 || c.k_plus != 0.0)
+    return fail(NBM_EUNSUPPORTED, "Helmholtz term k != 0 is not compiled into this library");
+  if (c.problem < 0 || c.problem > 3) return fail(NBM_EINVAL, "bad problem kind");
+  if (c.problem == NBM_PROB_MMS_SPHERE && c.dim != 3) return fail(NBM_EINVAL, "problem needs dim 3");
+  if (c.problem == NBM_PROB_FOURIER) {
+    if (c.n_modes <= 0 || !c.mode_k || !c.mode_a || !c.mode_b)
+      return fail(NBM_EINVAL, "Fourier problem needs a mode table");
+    for (int m = 0; m < c.n_modes; ++m)
+      for (int a = 0; a < 3; ++a)
+        if (c.mode_k[3 * m + a] < -8 || c.mode_k[3 * m + a] > 8)
+          return fail(NBM_EINVAL, "Fourier wave numbers must lie in [-8, 8]");
+  }
+  if (c.max_points < 1 || c.max_points > (1LL << 26) || c.max_boundary < 0 || c.max_boundary > (1LL << 24))
+    return fail(NBM_EINVAL, "max_points must be in [1, 2^26], max_boundary in [0, 2^24]");
+  MlpFn fn = find_mlp(c.dim, c.width, c.act, c.prec);
+  if (!fn)
+    return fail(NBM_EUNSUPPORTED, "no kernel compiled for (dim, width, act, prec) = (" +
+                                      std::to_string(c.dim) + ", " + std::to_string(c.width) + ", " +
+                                      std::to_string(c.act) + ", " + std::to_string(c.prec) + ")");
+  nbm_ctx* x = new (std::nothrow) nbm_ctx();
+  if (!x) return fail(NBM_EINVAL, "out of host memory");
+  x->cfg = c;
+  x->cfg.mode_k = nullptr;
+  x->cfg.mode_a = x->cfg.mode_b = nullptr;
+  x->mlp = fn;
+  x->D = c.dim; x->W = c.width; x->L = c.depth; x->S = 2 * c.dim + 1;
+  x->opbytes = c.prec == NBM_PREC_BF16 ? 2 : 4;
+  // parameter layout of one net
+  NetLayout& ly = x->lay;
+  int64_t o = 0, W = c.width, D = c.dim;
+  ly.W1 = o; o += W * D;
+  ly.b1 = o; o += W;
+  for (int l = 0; l < kMaxDepth; ++l) { ly.Wl[l] = 0; ly.bl[l] = 0; }
+  for (int l = 0; l < c.depth - 1; ++l) { ly.Wl[l] = o; o += W * W; ly.bl[l] = o; o += W; }
+  ly.wout = o; o += W;
+  ly.bout = o; o += 1;
+  ly.per_net = o;
+  x->per_net = o;
+  x->Ptot = 2 * o;
+  // problem
+  Problem& P = x->P;
+  std::memset(&P, 0, sizeof(P));
+  P.dim = c.dim; P.iface = c.interface_kind; P.kind = c.problem;
+  P.R = c.radius; P.amp = c.star_amp;
+  for (int a = 0; a < 3; ++a) P.pn[a] = c.plane_n[a];
+  P.pc = c.plane_c;
+  P.mu[0] = c.mu_minus; P.mu[1] = c.mu_plus;
+  P.lo = c.mu_minus == c.mu_plus ? -1 : (c.mu_minus < c.mu_plus ? 0 : 1);
+  P.alpha_c = c.alpha_const; P.beta_c = c.beta_const;
+  for (int a = 0; a < 4; ++a) { P.lin_a[a] = c.lin_a[a]; P.lin_b[a] = c.lin_b[a]; }
+  P.h = c.h;
+  P.n_modes = c.problem == NBM_PROB_FOURIER ? c.n_modes : 0;
+  if (P.n_modes) {
+    x->modes32.assign(8 * (size_t)P.n_modes, 0.0f);
+    x->modes64.assign(5 * (size_t)P.n_modes, 0.0);
+    for (int m = 0; m < P.n_modes; ++m) {
+      for (int a = 0; a < 3; ++a) {
+        x->modes32[8 * m + a] = (float)c.mode_k[3 * m + a];
+        x->modes64[5 * m + a] = (double)c.mode_k[3 * m + a];
+      }
+      x->modes32[8 * m + 3] = (float)c.mode_a[m];
+      x->modes32[8 * m + 4] = (float)c.mode_b[m];
+      x->modes64[5 * m + 3] = c.mode_a[m];
+      x->modes64[5 * m + 4] = c.mode_b[m];
+    }
+  }
+  x->cfg.n_modes = P.n_modes;
+  // capacities
+  x->cap_n = c.max_points;
+  x->cap_nb = c.max_boundary;
+  x->cut_cap = c.cut_capacity > 0 ? c.cut_capacity : c.max_points / 8 + 64;
+  if (x->cut_cap > x->cap_n) x->cut_cap = x->cap_n;
+  int nbr = P.lo >= 0 ? 2 * c.dim : 0;
+  x->cap_slots = x->cap_n + (2 + nbr) * x->cut_cap + x->cap_nb + 2 * kTile;
+  x->cap_tiles = (x->cap_slots + kTile - 1) / kTile + 2;
+  x->cap_slots = x->cap_tiles * kTile;
+  x->lstride = x->cap_tiles * (int64_t)x->S * x->W * kTile;
+  x->G = 512;
+  x->prepared_ws = nullptr;
+  make_layout(x);
+  *out = x;
+  return NBM_OK;
+}
+
+extern "C" void nbm_destroy(nbm_ctx* ctx) { delete ctx; }
+
+extern "C" int64_t nbm_param_count(const nbm_ctx* ctx) { return ctx ? ctx->Ptot : -1; }
+
+extern "C" size_t nbm_workspace_bytes(const nbm_ctx* ctx) { return ctx ? ctx->lo.total : 0; }
+
+template <class T>
+static T* at(void* ws, size_t off) {
+  return (T*)((char*)ws + off);
+}
+
+static int check_ws(nbm_ctx* ctx, void* ws, size_t bytes) {
+  if (!ws) return fail(NBM_EWORKSPACE, "workspace is null");
+  if (bytes < ctx->lo.total) return fail(NBM_EWORKSPACE, "workspace too small: need " + std::to_string(ctx->lo.total));
+  if (ctx->prepared_ws != ws) return fail(NBM_EWORKSPACE, "workspace not prepared (call nbm_prepare)");
+  if (((uintptr_t)ws & 255) != 0) return fail(NBM_EWORKSPACE, "workspace must be 256-byte aligned");
+  return NBM_OK;
+}
+
+extern "C" int nbm_prepare(nbm_ctx* ctx, void* stream, void* ws, size_t ws_bytes) {
+  if (!ctx || !ws) return fail(NBM_EINVAL, "null argument");
+  if (ws_bytes < ctx->lo.total) return fail(NBM_EWORKSPACE, "workspace too small: need " + std::to_string(ctx->lo.total));
+  if (((uintptr_t)ws & 255) != 0) return fail(NBM_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  if (ctx->P.n_modes) {
+    HIPCHK(hipMemcpyAsync(at<char>(ws, ctx->lo.modes32), ctx->modes32.data(), sizeof(float) * ctx->modes32.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(at<char>(ws, ctx->lo.modes64), ctx->modes64.data(), sizeof(double) * ctx->modes64.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  ctx->prepared_ws = ws;
+  return NBM_OK;
+}
+
+static Problem problem_for(nbm_ctx* ctx, void* ws) {
+  Problem P = ctx->P;
+  P.modes32 = at<float>(ws, ctx->lo.modes32);
+  P.modes64 = at<double>(ws, ctx->lo.modes64);
+  return P;
+}
+
+static Nets nets_for(nbm_ctx* ctx, const float* params, void* ws) {
+  Nets N;
+  std::memset(&N, 0, sizeof(N));
+  size_t wsz = (size_t)ctx->W * ctx->W * ctx->opbytes;
+  char* sh = at<char>(ws, ctx->lo.shadow);
+  for (int net = 0; net < 2; ++net) {
+    const float* p = params + net * ctx->per_net;
+    NetPtrs& np = N.net[net];
+    np.W1 = p + ctx->lay.W1;
+    np.b1 = p + ctx->lay.b1;
+    np.wout = p + ctx->lay.wout;
+    np.bout = p + ctx->lay.bout;
+    for (int l = 0; l < ctx->L - 1; ++l) {
+      np.bl[l] = p + ctx->lay.bl[l];
+      np.Wl[l] = sh + ((size_t)(net * (ctx->L - 1) + l) * 2 + 0) * wsz;
+      np.WlT[l] = sh + ((size_t)(net * (ctx->L - 1) + l) * 2 + 1) * wsz;
+    }
+  }
+  return N;
+}
+
+static int check_points(nbm_ctx* ctx, const float* pts, int64_t n, const float* bpts, int64_t nb) {
+  if (n < 0 || nb < 0) return fail(NBM_EINVAL, "negative batch size");
+  if (n + nb == 0) return fail(NBM_EINVAL, "empty batch");
+  if (n > ctx->cap_n || nb > ctx->cap_nb) return fail(NBM_EINVAL, "batch exceeds max_points / max_boundary");
+  if (n > 0 && !pts) return fail(NBM_EINVAL, "pts is null");
+  if (nb > 0 && !bpts) return fail(NBM_EINVAL, "bpts is null");
+  return NBM_OK;
+}
+
+// forward (+ optional backward) of one batch
+static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const float* pts, int64_t n,
+                    const float* bpts, int64_t nb, float* residual, double* loss, float* grad,
+                    double dL, void* ws) {
+  const Layout& Lo = ctx->lo;
+  Problem P = problem_for(ctx, ws);
+  // operand shadows of the hidden matrices
+  Nets N = nets_for(ctx, params, ws);
+  for (int net = 0; net < 2; ++net)
+    for (int l = 0; l < ctx->L - 1; ++l) {
+      hipError_t e = launch_shadow(st, ctx->cfg.prec, params, net * ctx->per_net + ctx->lay.Wl[l], ctx->W,
+                                   (void*)N.net[net].Wl[l], (void*)N.net[net].WlT[l]);
+      if (e != hipSuccess) return fail(NBM_EHIP, std::string("shadow: ") + hipGetErrorString(e));
+    }
+  // classification and centre lists
+  PrepCall pc;
+  std::memset(&pc, 0, sizeof(pc));
+  pc.stream = st; pc.P = P; pc.pts = pts; pc.n = n; pc.bpts = bpts; pc.nb = nb; pc.eval = false;
+  pc.cut_cap = (int)ctx->cut_cap;
+  pc.cls = at<int>(ws, Lo.cls); pc.rank = at<int>(ws, Lo.rank);
+  pc.blockcnt = at<int>(ws, Lo.blockcnt); pc.off = at<int>(ws, Lo.off);
+  pc.bcls = at<int>(ws, Lo.bcls); pc.brank = at<int>(ws, Lo.brank);
+  pc.blockcnt_b = at<int>(ws, Lo.blockcnt_b); pc.off_b = at<int>(ws, Lo.off_b);
+  pc.meta = at<Meta>(ws, Lo.meta);
+  pc.centres = at<float4>(ws, Lo.centres);
+  pc.src = at<int>(ws, Lo.src);
+  pc.cutidx = at<int>(ws, Lo.cutidx);
+  hipError_t e = launch_prep(pc);
+  if (e != hipSuccess) return fail(NBM_EHIP, std::string("prep: ") + hipGetErrorString(e));
+  // network streams at every centre
+  int nbr = P.lo >= 0 ? 2 * ctx->D : 0;
+  int64_t cut_here = std::min<int64_t>(ctx->cut_cap, n);
+  int64_t slots = n + (2 + nbr) * cut_here + nb + 2 * kTile;
+  int grid = (int)((slots + kTile - 1) / kTile + 2);
+  MlpCall mc;
+  std::memset(&mc, 0, sizeof(mc));
+  mc.op = MlpCall::FORWARD; mc.stream = st; mc.grid = grid; mc.meta = pc.meta;
+  mc.centres = pc.centres; mc.nets = &N; mc.L = ctx->L; mc.h = (float)ctx->cfg.h;
+  mc.outputs = at<float>(ws, Lo.outputs);
+  mc.Zst = at<float>(ws, Lo.Zst); mc.Ast = at<void>(ws, Lo.Ast); mc.ALst = at<float>(ws, Lo.ALst);
+  mc.dZ = at<float>(ws, Lo.dZ); mc.lstride = ctx->lstride;
+  mc.store = grad != nullptr; mc.streams = true;
+  e = ctx->mlp(mc);
+  if (e != hipSuccess) return fail(NBM_EHIP, std::string("forward: ") + hipGetErrorString(e));
+  // residuals, loss and output adjoints
+  float* adj = at<float>(ws, Lo.adj);
+  if (grad) {
+    e = launch_fill(st, adj, (int64_t)grid * kTile * 8, 0.0f);
+    if (e != hipSuccess) return fail(NBM_EHIP, std::string("fill: ") + hipGetErrorString(e));
+  }
+  ResCall rc;
+  std::memset(&rc, 0, sizeof(rc));
+  rc.stream = st; rc.P = P; rc.meta = pc.meta; rc.pts = pts; rc.n = n; rc.bpts = bpts; rc.nb = nb;
+  rc.cls = pc.cls; rc.rank = pc.rank; rc.bcls = pc.bcls; rc.brank = pc.brank; rc.cutidx = pc.cutidx;
+  rc.cut_cap = (int)cut_here;
+  rc.outputs = mc.outputs; rc.adj = adj;
+  rc.resid = residual ? residual : at<float>(ws, Lo.resid);
+  rc.lossp = at<double>(ws, Lo.lossp);
+  rc.loss = loss ? loss : at<double>(ws, Lo.lossbuf);
+  rc.scale = 2.0 * dL / (double)(n + nb);
+  e = launch_residuals(rc);
+  if (e != hipSuccess) return fail(NBM_EHIP, std::string("residual: ") + hipGetErrorString(e));
+  if (!grad) return NBM_OK;
+  // backward through the hidden layers, gradient partials, FP64 reduction
+  mc.op = MlpCall::BACKWARD;
+  mc.grid = ctx->G;
+  mc.adj = adj;
+  mc.partial = at<float>(ws, Lo.partial);
+  mc.Ptot = ctx->Ptot;
+  mc.lay = &ctx->lay;
+  mc.off1 = ctx->per_net;
+  for (int l = ctx->L; l >= 2; --l) {
+    mc.l = l;
+    e = ctx->mlp(mc);
+    if (e != hipSuccess) return fail(NBM_EHIP, std::string("backward: ") + hipGetErrorString(e));
+  }
+  e = launch_reduce_grad(st, mc.partial, ctx->G, ctx->Ptot, grad, 1.0);
+  if (e != hipSuccess) return fail(NBM_EHIP, std::string("reduce: ") + hipGetErrorString(e));
+  return NBM_OK;
+}
+
+extern "C" int nbm_forward_residual(nbm_ctx* ctx, void* stream, const float* params, const float* pts,
+                                    int64_t n, const float* bpts, int64_t nb, float* residual,
+                                    double* loss, float* grad, void* ws, size_t ws_bytes) {
+  if (!ctx || !params || !loss) return fail(NBM_EINVAL, "null argument");
+  int rc = check_ws(ctx, ws, ws_bytes);
+  if (rc) return rc;
+  rc = check_points(ctx, pts, n, bpts, nb);
+  if (rc) return rc;
+  return run_step(ctx, (hipStream_t)stream, params, pts, n, bpts, nb, residual, loss, grad, 1.0, ws);
+}
+
+extern "C" int nbm_backward(nbm_ctx* ctx, void* stream, const float* params, const float* pts, int64_t n,
+                            const float* bpts, int64_t nb, double dL, float* grad, void* ws,
+                            size_t ws_bytes) {
+  if (!ctx || !params || !grad) return fail(NBM_EINVAL, "null argument");
+  int rc = check_ws(ctx, ws, ws_bytes);
+  if (rc) return rc;
+  rc = check_points(ctx, pts, n, bpts, nb);
+  if (rc) return rc;
+  return run_step(ctx, (hipStream_t)stream, params, pts, n, bpts, nb, nullptr, nullptr, grad, dL, ws);
+}
+
+extern "C" int nbm_adam_step(nbm_ctx* ctx, void* stream, float* params, float* m, float* v,
+                             const float* grad, int64_t step, float lr, float beta1, float beta2,
+                             float eps) {
+  if (!ctx || !params || !m || !v || !grad) return fail(NBM_EINVAL, "null argument");
+  if (step < 1) return fail(NBM_EINVAL, "step is 1-based");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
+    return fail(NBM_EINVAL, "bad Adam hyper-parameters");
+  double c1 = 1.0 - std::pow((double)beta1, (double)step), c2 = 1.0 - std::pow((double)beta2, (double)step);
+  hipError_t e = launch_adam((hipStream_t)stream, params, m, v, grad, ctx->Ptot, lr, beta1, beta2, eps,
+                             (float)c1, (float)c2);
+  if (e != hipSuccess) return fail(NBM_EHIP, std::string("adam: ") + hipGetErrorString(e));
+  return NBM_OK;
+}
+
+extern "C" int nbm_sample_points(nbm_ctx* ctx, void* stream, uint64_t seed, int64_t step, float* pts,
+                                 int64_t n, float* bpts, int64_t nb) {
+  if (!ctx) return fail(NBM_EINVAL, "null context");
+  if (n < 0 || nb < 0 || (n && !pts) || (nb && !bpts)) return fail(NBM_EINVAL, "bad point buffers");
+  if (step < 0) return fail(NBM_EINVAL, "negative step");
+  int64_t jh = (int64_t)std::llround(ctx->cfg.h * (double)(1 << 22));
+  hipError_t e = launch_sample_points((hipStream_t)stream, ctx->D, seed, step, jh, pts, n, bpts, nb);
+  if (e != hipSuccess) return fail(NBM_EHIP, std::string("sample: ") + hipGetErrorString(e));
+  return NBM_OK;
+}
+
+extern "C" int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const float* query, int64_t m,
+                        int64_t tile_index, int32_t grid_n, float* u_out, void* ws, size_t ws_bytes) {
+  if (!ctx || !params || !u_out) return fail(NBM_EINVAL, "null argument");
+  int rc = check_ws(ctx, ws, ws_bytes);
+  if (rc) return rc;
+  if (m < 1 || m > ctx->cap_n) return fail(NBM_EINVAL, "m must be in [1, max_points]");
+  if (!query) {
+    if (grid_n < 2 || (grid_n & (grid_n - 1)) != 0 || grid_n > (1 << 14))
+      return fail(NBM_EINVAL, "grid_n must be a power of two in [2, 2^14]");
+    double tot = std::pow((double)grid_n, ctx->D);
+    if (tile_index < 0 || (double)(tile_index + 1) * (double)m > tot)
+      return fail(NBM_EINVAL, "tile outside the grid");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const Layout& Lo = ctx->lo;
+  Problem P = problem_for(ctx, ws);
+  Nets N = nets_for(ctx, params, ws);
+  for (int net = 0; net < 2; ++net)
+    for (int l = 0; l < ctx->L - 1; ++l) {
+      hipError_t e = launch_shadow(st, ctx->cfg.prec, params, net * ctx->per_net + ctx->lay.Wl[l], ctx->W,
+                                   (void*)N.net[net].Wl[l], (void*)N.net[net].WlT[l]);
+      if (e != hipSuccess) return fail(NBM_EHIP, std::string("shadow: ") + hipGetErrorString(e));
+    }
+  PrepCall pc;
+  std::memset(&pc, 0, sizeof(pc));
+  pc.stream = st; pc.P = P; pc.pts = query; pc.n = m; pc.bpts = nullptr; pc.nb = 0; pc.eval = true;
+  pc.tile_index = tile_index; pc.grid_n = grid_n;
+  pc.cut_cap = 0;
+  pc.cls = at<int>(ws, Lo.cls); pc.rank = at<int>(ws, Lo.rank);
+  pc.blockcnt = at<int>(ws, Lo.blockcnt); pc.off = at<int>(ws, Lo.off);
+  pc.bcls = at<int>(ws, Lo.bcls); pc.brank = at<int>(ws, Lo.brank);
+  pc.blockcnt_b = at<int>(ws, Lo.blockcnt_b); pc.off_b = at<int>(ws, Lo.off_b);
+  pc.meta = at<Meta>(ws, Lo.meta);
+  pc.centres = at<float4>(ws, Lo.centres);
+  pc.src = at<int>(ws, Lo.src);
+  pc.cutidx = at<int>(ws, Lo.cutidx);
+  hipError_t e = launch_prep(pc);
+  if (e != hipSuccess) return fail(NBM_EHIP, std::string("prep: ") + hipGetErrorString(e));
+  int64_t slots = m + 2 * kTile;
+  int grid = (int)((slots + kTile - 1) / kTile + 2);
+  MlpCall mc;
+  std::memset(&mc, 0, sizeof(mc));
+  mc.op = MlpCall::FORWARD; mc.stream = st; mc.grid = grid; mc.meta = pc.meta;
+  mc.centres = pc.centres; mc.nets = &N; mc.L = ctx->L; mc.h = (float)ctx->cfg.h;
+  mc.outputs = at<float>(ws, Lo.outputs);
+  mc.lstride = ctx->lstride;
+  mc.store = false; mc.streams = false;
+  e = ctx->mlp(mc);
+  if (e != hipSuccess) return fail(NBM_EHIP, std::string("eval: ") + hipGetErrorString(e));
+  e = launch_eval_out(st, (int64_t)grid * kTile, pc.meta, mc.outputs, pc.src, u_out);
+  if (e != hipSuccess) return fail(NBM_EHIP, std::string("eval out: ") + hipGetErrorString(e));
+  return NBM_OK;
+}
+
+extern "C" int nbm_batch_counts(nbm_ctx* ctx, void* stream, int32_t* counts, void* ws, size_t ws_bytes) {
+  if (!ctx || !counts) return fail(NBM_EINVAL, "null argument");
+  int rc = check_ws(ctx, ws, ws_bytes);
+  if (rc) return rc;
+  hipError_t e = launch_counts((hipStream_t)stream, at<Meta>(ws, ctx->lo.meta), counts);
+  if (e != hipSuccess) return fail(NBM_EHIP, std::string("counts: ") + hipGetErrorString(e));
+  return NBM_OK;
+}

@@ -1,0 +1,355 @@
+// Device-side building blocks for gfx950: MFMA wrappers, activation
+// difference streams, level sets, cut-cell clipping and problem data.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "nbm_internal.hpp"
+
+namespace nbm {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f32_16x16x4f32: lane l supplies A[l%16][k], B[k][l%16] with k = l/16;
+// result lane l holds C[4*(l/16)+r][l%16], r = 0..3.
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// v_mfma_f32_16x16x32_bf16: lane l supplies 8 consecutive K values of row
+// (A) / column (B) l%16 for K group l/16; result layout as above.
+__device__ __forceinline__ f4 mfma32(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int PREC> struct Op;
+template <> struct Op<0> { typedef float T; static constexpr int bytes = 4; };
+template <> struct Op<1> { typedef __bf16 T; static constexpr int bytes = 2; };
+
+__device__ __forceinline__ float to_f(float x) { return x; }
+__device__ __forceinline__ float to_f(__bf16 x) { return (float)x; }
+template <class T> __device__ __forceinline__ T from_f(float x);
+template <> __device__ __forceinline__ float from_f<float>(float x) { return x; }
+template <> __device__ __forceinline__ __bf16 from_f<__bf16>(float x) { return (__bf16)x; }
+
+// ---------------------------------------------------------------------------
+// Activation difference streams.
+// A point and its 2d stencil neighbours are propagated as a base stream
+// a = s(z) and, per axis, D = s(z+p) - s(z) and E = s(z+p) - 2 s(z) + s(z-m),
+// where p and e are the pre-activation differences and m = p - e.  This is an
+// exact rewriting of evaluating the network at x and x +- h e_i; the forms
+// below avoid the cancellation of forming those differences from point values
+// (sum-to-product identities for sin, addition theorems for tanh).
+// ---------------------------------------------------------------------------
+struct TanhBase { float t, q; };   // t = tanh z, q = 1 - t^2
+
+__device__ __forceinline__ TanhBase tanh_base(float z) {
+  float az = fabsf(z);
+  float ez = expf(-2.0f * az);
+  float em1 = expm1f(-2.0f * az);
+  float t = -em1 / (1.0f + ez);
+  t = z < 0.0f ? -t : t;
+  float q = 4.0f * ez / ((1.0f + ez) * (1.0f + ez));
+  return {t, q};
+}
+
+template <int ACT>
+__device__ __forceinline__ float act_base(float z) {
+  if (ACT == 0) return tanh_base(z).t;
+  return sinf(z);
+}
+
+// forward: base a, and per-axis D, E from (z, p, e)
+template <int ACT, int D>
+__device__ __forceinline__ void act_fwd(float z, const float* p, const float* e, float& a,
+                                        float* Dv, float* Ev) {
+  if (ACT == 1) {
+    float S, C;
+    sincosf(z, &S, &C);
+    a = S;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      float hp = 0.5f * p[i], m = p[i] - e[i], hm = 0.5f * m, he = 0.5f * e[i];
+      float sp, cp, sm, cm;
+      sincosf(hp, &sp, &cp);
+      sincosf(hm, &sm, &cm);
+      float se = sinf(he);
+      float cs2 = cp * cm - sp * sm;  // cos((p+m)/2)
+      Dv[i] = 2.0f * sp * (C * cp - S * sp);
+      Ev[i] = -2.0f * S * (sp * sp + sm * sm) + 2.0f * C * cs2 * se;
+    }
+  } else {
+    TanhBase tb = tanh_base(z);
+    float t = tb.t, q = tb.q;
+    a = t;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      float m = p[i] - e[i];
+      float Tp = tanhf(p[i]), Tm = tanhf(m), Te = tanhf(e[i]), Ts = tanhf(p[i] + m);
+      float P = 1.0f + t * Tp, M = 1.0f - t * Tm;
+      Dv[i] = Tp * q / P;
+      Ev[i] = (q / P) * (Te * (1.0f - Tp * Tm) - t * Tm * Ts * (1.0f + Tp * Tm) / M);
+    }
+  }
+}
+
+// backward: given stream adjoints (ab, Db, Eb) return (zb, pb, eb)
+template <int ACT, int D>
+__device__ __forceinline__ void act_bwd(float z, const float* p, const float* e, float ab,
+                                        const float* Db, const float* Eb, float& zb, float* pb,
+                                        float* eb) {
+  if (ACT == 1) {
+    float S, C;
+    sincosf(z, &S, &C);
+    zb = ab * C;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      float hp = 0.5f * p[i], m = p[i] - e[i], hm = 0.5f * m, he = 0.5f * e[i];
+      float sp, cp, sm, cm, se, ce;
+      sincosf(hp, &sp, &cp);
+      sincosf(hm, &sm, &cm);
+      sincosf(he, &se, &ce);
+      float cs2 = cp * cm - sp * sm;        // cos(s/2), s = p + m
+      float ss2 = sp * cm + cp * sm;        // sin(s/2)
+      float sq = sp * sp + sm * sm;
+      float dDdz = -2.0f * sp * (S * cp + C * sp);             // cos(z+p) - cos z
+      float dDdp = C * (1.0f - 2.0f * sp * sp) - S * (2.0f * sp * cp);   // cos(z+p)
+      float dEdz = -2.0f * C * sq - 2.0f * S * cs2 * se;
+      float dEdp = -2.0f * (S * ce + C * se) * ss2;              // -2 sin(z+e/2) sin(s/2)
+      float dEde = C * (1.0f - 2.0f * sm * sm) + S * (2.0f * sm * cm);   // cos(z-m)
+      zb += Db[i] * dDdz + Eb[i] * dEdz;
+      pb[i] = Db[i] * dDdp + Eb[i] * dEdp;
+      eb[i] = Eb[i] * dEde;
+    }
+  } else {
+    TanhBase tb = tanh_base(z);
+    float t = tb.t, q = tb.q;
+    zb = ab * q;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      float m = p[i] - e[i];
+      float Tp = tanhf(p[i]), Tm = tanhf(m), Te = tanhf(e[i]), Ts = tanhf(p[i] + m);
+      float P = 1.0f + t * Tp, M = 1.0f - t * Tm;
+      float Dd = Tp * q / P;
+      float Bd = Tm * q / M;
+      float Ed = (q / P) * (Te * (1.0f - Tp * Tm) - t * Tm * Ts * (1.0f + Tp * Tm) / M);
+      float dDdz = -Dd * (2.0f * t + Dd);
+      float dDdp = q * (1.0f - Tp * Tp) / (P * P);
+      float dEdz = -2.0f * t * Ed - Dd * Dd - Bd * Bd;
+      float dEdp = -(Dd + Bd) * (2.0f * t + Ed);
+      float dEde = q * (1.0f - Tm * Tm) / (M * M);
+      zb += Db[i] * dDdz + Eb[i] * dEdz;
+      pb[i] = Db[i] * dDdp + Eb[i] * dEdp;
+      eb[i] = Eb[i] * dEde;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Level sets (FP64).  Omega^- = {phi < 0}; phi = 0 belongs to Omega^+.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ inline double phi_at(const Problem& P, const double* x) {
+  if (P.iface == 2) {
+    double s = -P.pc;
+    for (int i = 0; i < D; ++i) s += P.pn[i] * x[i];
+    return s;
+  }
+  double r2 = 0.0;
+  for (int i = 0; i < D; ++i) r2 += x[i] * x[i];
+  double r = sqrt(r2);
+  if (P.iface == 0) return r - P.R;
+  // star, written as a rational function of the coordinates:
+  // sin(5 theta) sin(4 psi) = 4 z (z^2 - rho^2) Im((x + i y)^5) / (rho^4 r^4)
+  if (r2 == 0.0) return -P.R;
+  double X = x[0], Y = x[1], Z = (D > 2) ? x[2] : 0.0;
+  double rho2 = X * X + Y * Y;
+  if (rho2 == 0.0) return r - P.R;
+  double x2 = X * X, y2 = Y * Y;
+  double im5 = Y * (5.0 * x2 * x2 - 10.0 * x2 * y2 + y2 * y2);
+  double ang = 4.0 * Z * (Z * Z - rho2) * im5 / (rho2 * rho2 * r2 * r2);
+  return r - P.R - P.amp * ang;
+}
+
+template <int D>
+__device__ inline bool is_minus(const Problem& P, const double* x) {
+  if (P.iface == 0) {
+    double r2 = 0.0;
+    for (int i = 0; i < D; ++i) r2 += x[i] * x[i];
+    return r2 < P.R * P.R;
+  }
+  return phi_at<D>(P, x) < 0.0;
+}
+
+template <int D>
+__device__ inline void grad_phi(const Problem& P, const double* x, double* g) {
+  if (P.iface == 2) {
+    for (int i = 0; i < D; ++i) g[i] = P.pn[i];
+    return;
+  }
+  if (P.iface == 0) {
+    double r2 = 0.0;
+    for (int i = 0; i < D; ++i) r2 += x[i] * x[i];
+    double r = sqrt(r2);
+    for (int i = 0; i < D; ++i) g[i] = r > 0.0 ? x[i] / r : 0.0;
+    return;
+  }
+  const double st = 1e-6;
+  for (int i = 0; i < D; ++i) {
+    double xp[3], xm[3];
+    for (int j = 0; j < D; ++j) { xp[j] = x[j]; xm[j] = x[j]; }
+    xp[i] += st;
+    xm[i] -= st;
+    g[i] = (phi_at<D>(P, xp) - phi_at<D>(P, xm)) / (2.0 * st);
+  }
+}
+
+// one Newton step onto Gamma: pi, signed distance, unit normal at pi
+template <int D>
+__device__ inline void project(const Problem& P, const double* y, double* pi, double& dist,
+                               double* nrm) {
+  double ph = phi_at<D>(P, y);
+  double g[3];
+  grad_phi<D>(P, y, g);
+  double g2 = 0.0;
+  for (int i = 0; i < D; ++i) g2 += g[i] * g[i];
+  if (g2 <= 0.0) g2 = 1.0;
+  for (int i = 0; i < D; ++i) pi[i] = y[i] - ph / g2 * g[i];
+  dist = ph / sqrt(g2);
+  double gn[3];
+  grad_phi<D>(P, pi, gn);
+  double nn = 0.0;
+  for (int i = 0; i < D; ++i) nn += gn[i] * gn[i];
+  nn = sqrt(nn);
+  for (int i = 0; i < D; ++i) nrm[i] = nn > 0.0 ? gn[i] / nn : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Problem data (paper Sec. 2 and 4.1).  T = float for uncut cells, double
+// for cut cells.
+// ---------------------------------------------------------------------------
+template <class T, int D>
+__device__ inline T u_side(const Problem& P, int s, const T* x) {
+  if (P.kind == 0) return s == 0 ? exp(x[0] + x[1]) : sin(T(M_PI) * x[0]) * cos(T(M_PI) * x[1]);
+  if (P.kind == 1) return s == 0 ? exp(x[2]) : cos(x[0]) * sin(x[1]);
+  if (P.kind == 3) {
+    const double* c = s == 0 ? P.lin_a : P.lin_b;
+    T v = T(c[3]);
+    for (int i = 0; i < D; ++i) v += T(c[i]) * x[i];
+    return v;
+  }
+  return T(0);
+}
+
+template <class T, int D>
+__device__ inline void grad_u_side(const Problem& P, int s, const T* x, T* g) {
+  for (int i = 0; i < D; ++i) g[i] = T(0);
+  if (P.kind == 0) {
+    if (s == 0) {
+      T e = exp(x[0] + x[1]);
+      g[0] = e;
+      g[1] = e;
+    } else {
+      g[0] = T(M_PI) * cos(T(M_PI) * x[0]) * cos(T(M_PI) * x[1]);
+      g[1] = -T(M_PI) * sin(T(M_PI) * x[0]) * sin(T(M_PI) * x[1]);
+    }
+  } else if (P.kind == 1) {
+    if (s == 0) {
+      g[2] = exp(x[2]);
+    } else {
+      g[0] = -sin(x[0]) * sin(x[1]);
+      g[1] = cos(x[0]) * cos(x[1]);
+    }
+  } else if (P.kind == 3) {
+    const double* c = s == 0 ? P.lin_a : P.lin_b;
+    for (int i = 0; i < D; ++i) g[i] = T(c[i]);
+  }
+}
+
+// Fourier forcing f(x) = sum_k a_k cos(pi k.x) + b_k sin(pi k.x), built from
+// per-axis phase factors exp(i pi k_a x_a), k_a in [-8, 8].
+template <class T, int D>
+__device__ inline T fourier_f(const Problem& P, const T* x) {
+  T cr[D][9], ci[D][9];
+  for (int a = 0; a < D; ++a)
+    for (int k = 0; k <= 8; ++k) {
+      T sv, cv;
+      if (sizeof(T) == 4) {
+        float s_, c_;
+        sincospif((float)(k * (float)x[a]), &s_, &c_);
+        sv = T(s_); cv = T(c_);
+      } else {
+        double s_, c_;
+        sincospi((double)k * (double)x[a], &s_, &c_);
+        sv = T(s_); cv = T(c_);
+      }
+      cr[a][k] = cv;
+      ci[a][k] = sv;
+    }
+  T acc = T(0);
+  for (int m = 0; m < P.n_modes; ++m) {
+    T re = T(1), im = T(0), ka, aa, bb;
+    int kk[3];
+    if (sizeof(T) == 4) {
+      const float* md = P.modes32 + 8 * m;
+      kk[0] = (int)md[0]; kk[1] = (int)md[1]; kk[2] = (int)md[2];
+      aa = T(md[3]); bb = T(md[4]);
+    } else {
+      const double* md = P.modes64 + 5 * m;
+      kk[0] = (int)md[0]; kk[1] = (int)md[1]; kk[2] = (int)md[2];
+      aa = T(md[3]); bb = T(md[4]);
+    }
+    (void)ka;
+    for (int a = 0; a < D; ++a) {
+      int k = kk[a];
+      T fr = cr[a][k < 0 ? -k : k];
+      T fi = k < 0 ? -ci[a][-k] : ci[a][k];
+      T nr = re * fr - im * fi;
+      T ni = re * fi + im * fr;
+      re = nr;
+      im = ni;
+    }
+    acc += aa * re + bb * im;
+  }
+  return acc;
+}
+
+template <class T, int D>
+__device__ inline T f_side(const Problem& P, int s, const T* x) {
+  T mu = T(P.mu[s]);
+  if (P.kind == 0)
+    return s == 0 ? -mu * T(2) * exp(x[0] + x[1])
+                  : mu * T(2) * T(M_PI * M_PI) * sin(T(M_PI) * x[0]) * cos(T(M_PI) * x[1]);
+  if (P.kind == 1) return s == 0 ? -mu * exp(x[2]) : mu * T(2) * cos(x[0]) * sin(x[1]);
+  if (P.kind == 3) return T(0);
+  return fourier_f<T, D>(P, x);
+}
+
+template <int D>
+__device__ inline double alpha_at(const Problem& P, const double* y) {
+  if (P.kind == 2) return P.alpha_c;
+  return u_side<double, D>(P, 1, y) - u_side<double, D>(P, 0, y);
+}
+
+template <int D>
+__device__ inline double beta_at(const Problem& P, const double* y, const double* n) {
+  if (P.kind == 2) return P.beta_c;
+  double gp[3], gm[3];
+  grad_u_side<double, D>(P, 1, y, gp);
+  grad_u_side<double, D>(P, 0, y, gm);
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < D; ++i) { a += gp[i] * n[i]; b += gm[i] * n[i]; }
+  return P.mu[1] * a - P.mu[0] * b;
+}
+
+template <int D>
+__device__ inline float g_dirichlet(const Problem& P, const float* x) {
+  if (P.kind == 2) return 0.0f;
+  double xd[3];
+  for (int i = 0; i < D; ++i) xd[i] = x[i];
+  bool m = is_minus<D>(P, xd);
+  return u_side<float, D>(P, m ? 0 : 1, x);
+}
+
+}  // namespace nbm

@@ -1,0 +1,61 @@
+// Internal types shared by the host launchers and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nbm {
+
+constexpr int kMaxDepth = 8;   // hidden layers supported
+constexpr int kTile = 16;      // collocation centres per tile (MFMA M = 16)
+constexpr int kBlock = 256;    // threads per work-group (4 wavefronts)
+
+enum Kind { KIND_A = 0, KIND_B = 1, KIND_NBR = 2, KIND_BND = 3 };
+
+// Problem description passed by value to kernels (paper Sec. 2).
+struct Problem {
+  int dim, iface, kind, lo;   // lo: side with the smaller mu (0 minus, 1 plus), -1 if equal
+  double R, amp, pn[3], pc;
+  double mu[2];
+  double alpha_c, beta_c;
+  double lin_a[4], lin_b[4];
+  double h;
+  int n_modes;
+  const float* modes32;   // [n_modes][8]: k0 k1 k2 a b - - -
+  const double* modes64;  // [n_modes][5]: k0 k1 k2 a b
+};
+
+// Batch bookkeeping written on the device by the scan kernel.
+struct Meta {
+  int32_t cnt[2][4];   // centres per net and kind
+  int32_t base[2][4];  // global slot of the first centre of (net, kind)
+  int32_t total[2];    // centres per net
+  int32_t tiles[2];    // tiles per net
+  int32_t tile0[2];    // first global tile of each net
+  int32_t ncls[3];     // interior points per class: A-, A+, cut
+  int32_t nbside[2];   // boundary points per side
+  int32_t nB;          // cut cells kept
+  int32_t overflow;    // 1 if the cut capacity was exceeded
+  int32_t n, nb;       // batch sizes
+};
+
+// Per-net parameter pointers (FP32 master copy) and operand shadows.
+struct NetPtrs {
+  const float* W1;
+  const float* b1;
+  const float* bl[kMaxDepth];
+  const float* wout;
+  const float* bout;
+  const void* Wl[kMaxDepth];    // shadow W_l [W][W] (operand dtype), l = 1..L-1 index = l-1
+  const void* WlT[kMaxDepth];   // shadow W_l^T
+};
+
+struct Nets {
+  NetPtrs net[2];
+};
+
+// Offsets (floats) of each parameter block inside one net.
+struct NetLayout {
+  int64_t W1, b1, Wl[kMaxDepth], bl[kMaxDepth], wout, bout, per_net;
+};
+
+}  // namespace nbm

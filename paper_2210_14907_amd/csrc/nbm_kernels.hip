@@ -1,0 +1,1084 @@
+// gfx950 kernels of the NBM training step and evaluation.
+//
+// Data layout in HBM (all caller-owned workspace):
+//   centres      float4 [slots]           cell centres of the per-net batches
+//   outputs/adj  float [slots][8]         per centre: u, du_i, eu_i (streams)
+//   Zst[l]       float [tiles][S][W][16]  pre-activation streams of layer l
+//   Ast[l]       op    [tiles][S][W][16]  activation streams (GEMM operands)
+//   dZ           float [tiles][S][W][16]  adjoint of the pre-activations
+//   partial      float [G][P]             per-work-group gradient partials
+// Streams: plane 0 = base value, 1..d = first differences D_i,
+// d+1..2d = second differences E_i along each axis (see nbm_device.hpp).
+#include <hip/hip_runtime.h>
+
+#include "nbm_cutcell.hpp"
+#include "nbm_device.hpp"
+#include "nbm_internal.hpp"
+#include "nbm_launch.hpp"
+
+namespace nbm {
+
+// ===========================================================================
+// Philox4x32-10 (Salmon et al., SC'11) and point sampling
+// ===========================================================================
+__device__ inline void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+    uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ inline int64_t range_u32(uint32_t r, uint64_t m) { return (int64_t)(((uint64_t)r * m) >> 32); }
+
+template <int D>
+__global__ void k_sample(uint64_t seed, int64_t step, int64_t jh, float* pts, int64_t n, float* bpts,
+                         int64_t nb) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t Q = 1 << 22;
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  if (i < n) {
+    uint32_t c[4] = {(uint32_t)i, (uint32_t)step, (uint32_t)((uint64_t)step >> 32), 0u};
+    philox(c, k0, k1);
+    uint64_t m = (uint64_t)(2 * Q - 2 * jh + 1);
+    for (int a = 0; a < D; ++a) pts[i * D + a] = (float)(range_u32(c[a], m) + jh - Q) / (float)Q;
+  } else if (i < n + nb) {
+    int64_t b = i - n;
+    uint32_t c[4] = {(uint32_t)b, (uint32_t)step, (uint32_t)((uint64_t)step >> 32), 1u};
+    philox(c, k0, k1);
+    uint64_t m = (uint64_t)(2 * Q + 1);
+    float x[3];
+    for (int a = 0; a < D; ++a) x[a] = (float)(range_u32(c[a], m) - Q) / (float)Q;
+    int face = (int)range_u32(c[3], 2 * D);
+    x[face / 2] = (face % 2 == 0) ? -1.0f : 1.0f;
+    for (int a = 0; a < D; ++a) bpts[b * D + a] = x[a];
+  }
+}
+
+// ===========================================================================
+// Classification and order-preserving compaction
+// ===========================================================================
+// class of an interior point: 0 = all nodes and corners in Omega^-,
+// 1 = all in Omega^+, 2 = cut.  Boundary points: 0 / 1 by side.
+template <int D>
+__device__ inline int classify_point(const Problem& P, const float* xf, double h) {
+  double x[3] = {0, 0, 0}, y[3];
+  for (int a = 0; a < D; ++a) x[a] = xf[a];
+  bool m0 = is_minus<D>(P, x);
+  bool same = true;
+  for (int a = 0; a < D && same; ++a)
+    for (int sg = -1; sg <= 1; sg += 2) {
+      for (int b = 0; b < D; ++b) y[b] = x[b];
+      y[a] += sg * h;
+      if (is_minus<D>(P, y) != m0) same = false;
+    }
+  for (int c = 0; c < (1 << D) && same; ++c) {
+    for (int a = 0; a < D; ++a) y[a] = x[a] + h * (((c >> a) & 1) ? 0.5 : -0.5);
+    if (is_minus<D>(P, y) != m0) same = false;
+  }
+  return same ? (m0 ? 0 : 1) : 2;
+}
+
+// per-block class counts and block-local ranks (wave ballots)
+// mode 0: interior points (3 classes), 1: boundary / eval points (2 sides),
+// eval points are either given (pts) or generated from a grid tile.
+template <int D>
+__global__ __launch_bounds__(256) void k_classify(Problem P, const float* pts, int64_t n, int mode,
+                                                  int64_t tile_index, int grid_n, int* cls, int* rank,
+                                                  int* blockcnt) {
+  __shared__ int wcnt[4][4];
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int c = 3;  // 3 = no point
+  if (i < n) {
+    float xf[3];
+    if (pts) {
+      for (int a = 0; a < D; ++a) xf[a] = pts[i * D + a];
+    } else {
+      int64_t q = tile_index * n + i, gn = grid_n;
+      for (int a = 0; a < D; ++a) { xf[a] = -1.0f + 2.0f * (float)(q % gn) / (float)gn; q /= gn; }
+    }
+    if (mode == 0) c = classify_point<D>(P, xf, P.h);
+    else {
+      double x[3] = {0, 0, 0};
+      for (int a = 0; a < D; ++a) x[a] = xf[a];
+      c = is_minus<D>(P, x) ? 0 : 1;
+    }
+  }
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int myrank = 0;
+  for (int k = 0; k < 3; ++k) {
+    uint64_t m = __ballot(c == k);
+    if (c == k) myrank = __popcll(m & lt);
+    if (lane == 0) wcnt[w][k] = __popcll(m);
+  }
+  __syncthreads();
+  if (c < 3) {
+    int off = 0;
+    for (int v = 0; v < w; ++v) off += wcnt[v][c];
+    cls[i] = c;
+    rank[i] = off + myrank;
+  }
+  if (threadIdx.x < 3) {
+    int s = 0;
+    for (int v = 0; v < 4; ++v) s += wcnt[v][threadIdx.x];
+    blockcnt[blockIdx.x * 4 + threadIdx.x] = s;
+  }
+}
+
+// exclusive scans of the block counts and the batch bookkeeping
+__global__ __launch_bounds__(256) void k_scan(const int* bc_in, int nblk_in, const int* bc_bnd,
+                                              int nblk_bnd, int* off_in, int* off_bnd, Meta* meta,
+                                              int n, int nb, int cut_cap, int dim, int lo,
+                                              int eval_mode) {
+  __shared__ int part[256];
+  __shared__ int totals[8];
+  for (int arr = 0; arr < 2; ++arr) {
+    const int* bc = arr == 0 ? bc_in : bc_bnd;
+    int* off = arr == 0 ? off_in : off_bnd;
+    int nblk = arr == 0 ? nblk_in : nblk_bnd;
+    for (int k = 0; k < (arr == 0 ? 3 : 2); ++k) {
+      int carry = 0;
+      for (int base = 0; base < nblk; base += 256) {
+        int idx = base + threadIdx.x;
+        int v = idx < nblk ? bc[idx * 4 + k] : 0;
+        part[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = 1; s < 256; s <<= 1) {
+          int t = threadIdx.x >= s ? part[threadIdx.x - s] : 0;
+          __syncthreads();
+          part[threadIdx.x] += t;
+          __syncthreads();
+        }
+        if (idx < nblk) off[idx * 4 + k] = carry + part[threadIdx.x] - v;
+        int blocksum = part[255];
+        __syncthreads();
+        carry += blocksum;
+      }
+      if (threadIdx.x == 0) totals[arr * 4 + k] = carry;
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    Meta m;
+    for (int a = 0; a < 2; ++a)
+      for (int k = 0; k < 4; ++k) { m.cnt[a][k] = 0; m.base[a][k] = 0; }
+    m.n = n;
+    m.nb = nb;
+    if (eval_mode) {
+      m.ncls[0] = totals[0]; m.ncls[1] = totals[1]; m.ncls[2] = 0;
+      m.nbside[0] = m.nbside[1] = 0;
+      m.nB = 0; m.overflow = 0;
+      m.cnt[0][KIND_A] = totals[0];
+      m.cnt[1][KIND_A] = totals[1];
+    } else {
+      m.ncls[0] = totals[0]; m.ncls[1] = totals[1]; m.ncls[2] = totals[2];
+      m.nbside[0] = totals[4]; m.nbside[1] = totals[5];
+      m.overflow = totals[2] > cut_cap ? 1 : 0;
+      m.nB = totals[2] < cut_cap ? totals[2] : cut_cap;
+      for (int a = 0; a < 2; ++a) {
+        m.cnt[a][KIND_A] = m.ncls[a];
+        m.cnt[a][KIND_B] = m.nB;
+        m.cnt[a][KIND_NBR] = (lo == a) ? 2 * dim * m.nB : 0;
+        m.cnt[a][KIND_BND] = m.nbside[a];
+      }
+    }
+    int tile = 0;
+    for (int a = 0; a < 2; ++a) {
+      int tot = 0;
+      for (int k = 0; k < 4; ++k) { m.base[a][k] = tile * kTile + tot; tot += m.cnt[a][k]; }
+      m.total[a] = tot;
+      m.tiles[a] = (tot + kTile - 1) / kTile;
+      m.tile0[a] = tile;
+      tile += m.tiles[a];
+    }
+    *meta = m;
+  }
+}
+
+// scatter: final ranks, centre lists (coordinates + source index).
+// bnd = 0: interior (or evaluation) points, class < 2 -> KIND_A of that net,
+// class 2 -> KIND_B of both nets (+ low-mu neighbour centres);
+// bnd = 1: boundary points -> KIND_BND of the net of their side.
+template <int D>
+__global__ __launch_bounds__(256) void k_scatter(Problem P, const Meta* meta, const float* pts,
+                                                 int64_t n, const int* cls, int* rank, const int* off,
+                                                 int bnd, int64_t tile_index, int grid_n,
+                                                 float4* centres, int* src, int* cutidx) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  int c = cls[i];
+  int r = rank[i] + off[blockIdx.x * 4 + c];
+  rank[i] = r;
+  float xf[3] = {0, 0, 0};
+  if (pts) {
+    for (int a = 0; a < D; ++a) xf[a] = pts[i * D + a];
+  } else {
+    int64_t q = tile_index * n + i, gn = grid_n;
+    for (int a = 0; a < D; ++a) { xf[a] = -1.0f + 2.0f * (float)(q % gn) / (float)gn; q /= gn; }
+  }
+  float4 xc = make_float4(xf[0], xf[1], xf[2], 0.0f);
+  if (bnd || c < 2) {
+    int slot = meta->base[c][bnd ? KIND_BND : KIND_A] + r;
+    centres[slot] = xc;
+    src[slot] = (int)i;
+    return;
+  }
+  if (r >= meta->nB) return;  // over capacity: dropped, the loss reports NaN
+  cutidx[r] = (int)i;
+  for (int a = 0; a < 2; ++a) {
+    int slot = meta->base[a][KIND_B] + r;
+    centres[slot] = xc;
+    src[slot] = (int)i;
+  }
+  if (P.lo >= 0) {
+    float h = (float)P.h;
+    for (int k = 0; k < 2 * D; ++k) {
+      float4 y = xc;
+      float dv = (k & 1) ? -h : h;
+      int ax = k >> 1;
+      if (ax == 0) y.x += dv; else if (ax == 1) y.y += dv; else y.z += dv;
+      int slot = meta->base[P.lo][KIND_NBR] + 2 * D * r + k;
+      centres[slot] = y;
+      src[slot] = (int)i;
+    }
+  }
+}
+
+// ===========================================================================
+// Utilities
+// ===========================================================================
+__global__ void k_fill(float* p, int64_t n, float v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <class T>
+__global__ void k_shadow(const float* params, int64_t off, int W, T* Wl, T* WlT) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= W * W) return;
+  int r = i / W, c = i % W;
+  float v = params[off + i];
+  Wl[i] = from_f<T>(v);
+  WlT[c * W + r] = from_f<T>(v);
+}
+
+__global__ void k_reduce_grad(const float* partial, int G, int64_t P, float* grad, double scale) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= P) return;
+  double s = 0.0;
+  for (int g = 0; g < G; ++g) s += (double)partial[(int64_t)g * P + j];
+  grad[j] = (float)(s * scale);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_loss(const double* lp, int nparts, const Meta* meta,
+                                                     double* loss) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  // fixed-order strided partial sums, then a fixed tree
+  for (int i = threadIdx.x; i < nparts; i += 256) acc += lp[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double L = s[0] / (double)(meta->n + meta->nb);
+    if (meta->overflow) L = __builtin_nan("");
+    *loss = L;
+  }
+}
+
+__global__ void k_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float gi = g[i];
+  float mi = b1 * m[i] + (1.0f - b1) * gi;
+  float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  float mh = mi / c1, vh = vi / c2;
+  p[i] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+__global__ void k_counts(const Meta* meta, int* counts) {
+  if (threadIdx.x == 0) {
+    counts[0] = meta->ncls[0]; counts[1] = meta->ncls[1]; counts[2] = meta->ncls[2];
+    counts[3] = meta->nbside[0]; counts[4] = meta->nbside[1]; counts[5] = meta->overflow;
+    counts[6] = 0; counts[7] = 0;
+  }
+}
+
+__global__ void k_eval_out(const Meta* meta, const float* outputs, const int* src, float* u_out) {
+  int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int a = 0; a < 2; ++a) {
+    int64_t s0 = (int64_t)meta->tile0[a] * kTile;
+    if (slot >= s0 && slot < s0 + meta->total[a]) u_out[src[slot]] = outputs[slot * 8];
+  }
+}
+
+// ===========================================================================
+// Block-level FP64 sum helper (fixed order)
+// ===========================================================================
+__device__ inline double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// ===========================================================================
+// Residual kernels (paper Sec. 3: r_p = |M^-1 A u - M^-1 b| per point)
+// ===========================================================================
+// uncut cells: r = -sum_i eu_i / h^2 - f^s(x) / mu^s
+template <int D>
+__global__ __launch_bounds__(256) void k_res_uncut(Problem P, const Meta* meta, const float* pts,
+                                                   int64_t n, const int* cls, const int* rank,
+                                                   const float* outputs, float* adj, float* resid,
+                                                   double* lossp, double scale) {
+  __shared__ double sh[256];
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double r2 = 0.0;
+  if (i < n) {
+    int c = cls[i];
+    if (c < 2) {
+      int64_t slot = meta->base[c][KIND_A] + rank[i];
+      float x[3] = {0, 0, 0};
+      for (int a = 0; a < D; ++a) x[a] = pts[i * D + a];
+      float hh = (float)(P.h * P.h);
+      float lap = 0.0f;
+      for (int a = 0; a < D; ++a) lap += outputs[slot * 8 + 1 + D + a];
+      float r = -lap / hh - f_side<float, D>(P, c, x) / (float)P.mu[c];
+      if (resid) resid[i] = r;
+      r2 = (double)r * (double)r;
+      float rb = (float)(scale * (double)r);
+      for (int a = 0; a < D; ++a) adj[slot * 8 + 1 + D + a] = -rb / hh;
+    }
+  }
+  double s = block_sum(r2, sh);
+  if (threadIdx.x == 0) lossp[blockIdx.x] = s;
+}
+
+// cut cells: full cut-cell residual in FP64 from the two networks' streams
+template <int D>
+__global__ __launch_bounds__(256) void k_res_cut(Problem P, const Meta* meta, const float* pts,
+                                                 const int* cutidx, const float* outputs,
+                                                 float* adj, float* resid, double* lossp,
+                                                 double scale) {
+  __shared__ double sh[256];
+  int b = blockIdx.x * 256 + threadIdx.x;
+  double r2 = 0.0;
+  int nB = meta->nB;
+  if (b < nB) {
+    const int S = 2 * D + 1;
+    int p = cutidx[b];
+    double h = P.h;
+    double x[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) x[a] = pts[(int64_t)p * D + a];
+    // network streams of both nets at the centre
+    double o[2][7];
+    int64_t slot[2];
+    for (int t = 0; t < 2; ++t) {
+      slot[t] = meta->base[t][KIND_B] + b;
+      for (int s = 0; s < S; ++s) o[t][s] = outputs[slot[t] * 8 + s];
+    }
+    // nodes: 0 centre, 1 + 2a = +e_a, 2 + 2a = -e_a
+    double y[7][3];
+    int sd[7];
+    for (int k = 0; k < S; ++k) {
+      for (int a = 0; a < 3; ++a) y[k][a] = a < D ? x[a] : 0.0;
+      if (k > 0) y[k][(k - 1) >> 1] += ((k - 1) & 1) ? -h : h;
+      sd[k] = is_minus<D>(P, y[k]) ? 0 : 1;
+    }
+    // node values of the node's own network (from the centre streams)
+    double U[7];
+    auto node_val = [&](int t, int k) -> double {
+      if (k == 0) return o[t][0];
+      int a = (k - 1) >> 1;
+      return ((k - 1) & 1) ? o[t][0] + o[t][1 + D + a] - o[t][1 + a] : o[t][0] + o[t][1 + a];
+    };
+    for (int k = 0; k < S; ++k) U[k] = node_val(sd[k], k);
+    // differences U_F - U_0, from the difference streams when both nodes
+    // belong to the same network
+    double dU[6];
+    for (int F = 0; F < 2 * D; ++F) {
+      int k = F + 1, a = F >> 1;
+      if (sd[k] == sd[0]) {
+        int t = sd[0];
+        dU[F] = (F & 1) ? o[t][1 + D + a] - o[t][1 + a] : o[t][1 + a];
+      } else {
+        dU[F] = U[k] - U[0];
+      }
+    }
+    // jump extension at the nodes
+    double J[7];
+    for (int k = 0; k < S; ++k) {
+      double glo[3] = {0, 0, 0};
+      if (P.lo >= 0) {
+        const float* ol;
+        if (k == 0) ol = outputs + slot[P.lo] * 8;
+        else ol = outputs + ((int64_t)meta->base[P.lo][KIND_NBR] + 2 * D * b + (k - 1)) * 8;
+        for (int a = 0; a < D; ++a) glo[a] = (2.0 * (double)ol[1 + a] - (double)ol[1 + D + a]) / (2.0 * h);
+      }
+      J[k] = jump_ext<D>(P, y[k], glo);
+    }
+    CutGeom G;
+    cut_geometry<D>(P, x, h, G);
+    double mm = P.mu[0], mp = P.mu[1];
+    double cF[6], csum = 0.0, flux_corr = 0.0;
+    auto corr = [&](int s, int k) -> double {
+      if (s == 0) return sd[k] == 0 ? 0.0 : -J[k];
+      return sd[k] == 0 ? J[k] : 0.0;
+    };
+    for (int F = 0; F < 2 * D; ++F) {
+      double an = G.aneg[F], ap = 1.0 - an;
+      cF[F] = mm * an + mp * ap;
+      csum += cF[F];
+      flux_corr += mm * an * (corr(0, F + 1) - corr(0, 0)) + mp * ap * (corr(1, F + 1) - corr(1, 0));
+    }
+    double mubar = csum / (2 * D);
+    double src = G.vneg * f_side<double, D>(P, 0, x) + (1.0 - G.vneg) * f_side<double, D>(P, 1, x);
+    double bterm = 0.0;
+    if (G.gamma > 0.0) {
+      double pc[3], dc, nc[3];
+      project<D>(P, G.cen, pc, dc, nc);
+      bterm = G.gamma * beta_at<D>(P, pc, nc) / h;
+    }
+    double R = -flux_corr / (h * h) - src + bterm;
+    for (int F = 0; F < 2 * D; ++F) R -= cF[F] * dU[F] / (h * h);
+    double r = R / mubar;
+    resid[p] = (float)r;
+    r2 = r * r;
+    // adjoints: dr/dU_F = -c_F/(h^2 mubar), dr/dU_0 = sum_F c_F/(h^2 mubar)
+    double rb = scale * r;
+    double Ub[7];
+    Ub[0] = rb * csum / (h * h * mubar);
+    for (int F = 0; F < 2 * D; ++F) Ub[F + 1] = -rb * cF[F] / (h * h * mubar);
+    double g[2][7];
+    for (int t = 0; t < 2; ++t)
+      for (int s = 0; s < 7; ++s) g[t][s] = 0.0;
+    for (int k = 0; k < S; ++k) {
+      int t = sd[k];
+      g[t][0] += Ub[k];
+      if (k > 0) {
+        int a = (k - 1) >> 1;
+        if ((k - 1) & 1) { g[t][1 + D + a] += Ub[k]; g[t][1 + a] -= Ub[k]; }
+        else g[t][1 + a] += Ub[k];
+      }
+    }
+    for (int t = 0; t < 2; ++t)
+      for (int s = 0; s < S; ++s) adj[slot[t] * 8 + s] = (float)g[t][s];
+  }
+  double s = block_sum(r2, sh);
+  if (threadIdx.x == 0) lossp[blockIdx.x] = s;
+}
+
+// Dirichlet rows at boundary points: r_b = (2d/h^2)(u - g)
+template <int D>
+__global__ __launch_bounds__(256) void k_res_bnd(Problem P, const Meta* meta, const float* bpts,
+                                                 int64_t nb, const int* bcls, const int* brank,
+                                                 const float* outputs, float* adj, float* resid,
+                                                 double* lossp, double scale) {
+  __shared__ double sh[256];
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double r2 = 0.0;
+  if (i < nb) {
+    int c = bcls[i];
+    int64_t slot = meta->base[c][KIND_BND] + brank[i];
+    float x[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) x[a] = bpts[i * D + a];
+    float w = (float)(2.0 * D / (P.h * P.h));
+    float r = w * (outputs[slot * 8] - g_dirichlet<D>(P, x));
+    resid[i] = r;
+    r2 = (double)r * (double)r;
+    adj[slot * 8] = (float)(scale * (double)r) * w;
+  }
+  double s = block_sum(r2, sh);
+  if (threadIdx.x == 0) lossp[blockIdx.x] = s;
+}
+
+// ===========================================================================
+// MLP forward over difference streams (one tile of 16 centres per block)
+// ===========================================================================
+template <int PREC> struct Pad { static constexpr int v = PREC == 0 ? 4 : 8; };
+
+__device__ inline int tile_net(const Meta* m, int t) {
+  if (t < m->tiles[0]) return 0;
+  if (t < m->tiles[0] + m->tiles[1]) return 1;
+  return -1;
+}
+
+template <int D, int W, int S, int ACT, int PREC, bool STORE>
+__global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4* centres, Nets nets,
+                                                 int L, float h, float* outputs, float* Zst,
+                                                 void* Ast_, float* ALst, int64_t lstride) {
+  typedef typename Op<PREC>::T T;
+  constexpr int LD = W + Pad<PREC>::v;
+  constexpr int NOB = W / 16;
+  constexpr int KC = W / 4;  // K chunk per lane group
+  __shared__ __attribute__((aligned(16))) T buf[2][S][kTile][LD];
+  __shared__ float part[4][kTile][8];
+  const int t = blockIdx.x;
+  const int net = tile_net(meta, t);
+  if (net < 0) return;
+  const NetPtrs& np = nets.net[net];
+  const int64_t slot0 = (int64_t)t * kTile;
+  const int64_t slot_end = (int64_t)meta->tile0[net] * kTile + meta->total[net];
+  T* Ast = (T*)Ast_;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r16 = lane & 15, g = lane >> 4;
+
+  // ---- layer 1 (K = d, VALU): z = W1 x + b1, p_i = h W1[:, i], e_i = 0
+  for (int it = tid; it < kTile * W; it += 256) {
+    int c = it & 15, n = it >> 4;
+    float x[3] = {0, 0, 0};
+    if (slot0 + c < slot_end) {
+      float4 cc = centres[slot0 + c];
+      x[0] = cc.x; x[1] = cc.y; x[2] = cc.z;
+    }
+    float z = np.b1[n];
+    float p[3], e[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+      float wv = np.W1[n * D + a];
+      z += wv * x[a];
+      p[a] = h * wv;
+    }
+    float av, Dv[3], Ev[3];
+    if constexpr (S == 1) av = act_base<ACT>(z);
+    else act_fwd<ACT, D>(z, p, e, av, Dv, Ev);
+    float vals[7], pre[7];
+    vals[0] = av; pre[0] = z;
+    if (S > 1)
+      for (int a = 0; a < D; ++a) {
+        vals[1 + a] = Dv[a]; vals[1 + D + a] = Ev[a];
+        pre[1 + a] = p[a]; pre[1 + D + a] = 0.0f;
+      }
+    for (int s = 0; s < S; ++s) {
+      buf[0][s][c][n] = from_f<T>(vals[s]);
+      if (STORE) {
+        int64_t o = (((int64_t)t * S + s) * W + n) * kTile + c;
+        Zst[o] = pre[s];
+        Ast[o] = from_f<T>(vals[s]);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- hidden layers 2..L on MFMA
+  float vout[S][4];
+  for (int s = 0; s < S; ++s)
+    for (int j = 0; j < 4; ++j) vout[s][j] = 0.0f;
+  int cur = 0;
+  for (int l = 2; l <= L; ++l) {
+    const T* Wm = (const T*)np.Wl[l - 2];
+    const float* bl = np.bl[l - 2];
+    const bool last = (l == L);
+    for (int ob = w; ob < NOB; ob += 4) {
+      const int nrow = ob * 16 + r16;
+      f4 acc[S];
+      for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (PREC == 0) {
+        float bk[KC];
+        const float4* wp = (const float4*)((const float*)Wm + (int64_t)nrow * W + g * KC);
+        for (int q = 0; q < KC / 4; ++q) {
+          float4 v4 = wp[q];
+          bk[4 * q] = v4.x; bk[4 * q + 1] = v4.y; bk[4 * q + 2] = v4.z; bk[4 * q + 3] = v4.w;
+        }
+        for (int s = 0; s < S; ++s) {
+          const float4* ap = (const float4*)(&buf[cur][s][r16][g * KC]);
+          for (int q = 0; q < KC / 4; ++q) {
+            float4 a4 = ap[q];
+            acc[s] = mfma4(a4.x, bk[4 * q], acc[s]);
+            acc[s] = mfma4(a4.y, bk[4 * q + 1], acc[s]);
+            acc[s] = mfma4(a4.z, bk[4 * q + 2], acc[s]);
+            acc[s] = mfma4(a4.w, bk[4 * q + 3], acc[s]);
+          }
+        }
+      } else {
+        bf8 bk[KC / 8];
+        const bf8* wp = (const bf8*)((const T*)Wm + (int64_t)nrow * W + g * KC);
+        for (int q = 0; q < KC / 8; ++q) bk[q] = wp[q];
+        for (int s = 0; s < S; ++s) {
+          const bf8* ap = (const bf8*)(&buf[cur][s][r16][g * KC]);
+          for (int q = 0; q < KC / 8; ++q) acc[s] = mfma32(ap[q], bk[q], acc[s]);
+        }
+      }
+      // epilogue: bias, activation streams; lane holds centres 4g+j of neuron nrow
+      float bias = bl[nrow];
+      float wo = last ? np.wout[nrow] : 0.0f;
+      for (int j = 0; j < 4; ++j) {
+        float z = acc[0][j] + bias;
+        float p[3], e[3], av, Dv[3], Ev[3];
+        float vals[7];
+        if constexpr (S == 1) {
+          av = act_base<ACT>(z);
+          vals[0] = av;
+        } else {
+          for (int a = 0; a < D; ++a) { p[a] = acc[1 + a][j]; e[a] = acc[1 + D + a][j]; }
+          act_fwd<ACT, D>(z, p, e, av, Dv, Ev);
+          vals[0] = av;
+          for (int a = 0; a < D; ++a) { vals[1 + a] = Dv[a]; vals[1 + D + a] = Ev[a]; }
+        }
+        acc[0][j] = z;
+        for (int s = 0; s < S; ++s) {
+          if (!last) buf[cur ^ 1][s][4 * g + j][nrow] = from_f<T>(vals[s]);
+          else vout[s][j] += wo * vals[s];
+        }
+        if (STORE) {
+          for (int s = 0; s < S; ++s) {
+            int64_t o = (((int64_t)t * S + s) * W + nrow) * kTile + 4 * g + j;
+            if (!last) Ast[(int64_t)(l - 1) * lstride + o] = from_f<T>(vals[s]);
+            else ALst[o] = vals[s];
+          }
+        }
+      }
+      if (STORE) {
+        for (int s = 0; s < S; ++s) {
+          int64_t o = (((int64_t)t * S + s) * W + nrow) * kTile + 4 * g;
+          float4 zv = make_float4(acc[s][0], acc[s][1], acc[s][2], acc[s][3]);
+          *(float4*)(Zst + (int64_t)(l - 1) * lstride + o) = zv;
+        }
+      }
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  // ---- output layer: u = w_out . a + b_out, du_i = w_out . D_i, eu_i = w_out . E_i
+  for (int s = 0; s < S; ++s)
+    for (int j = 0; j < 4; ++j) {
+      float v = vout[s][j];
+      v += __shfl_xor(v, 8);
+      v += __shfl_xor(v, 4);
+      v += __shfl_xor(v, 2);
+      v += __shfl_xor(v, 1);
+      vout[s][j] = v;
+    }
+  if (r16 == 0)
+    for (int s = 0; s < S; ++s)
+      for (int j = 0; j < 4; ++j) part[w][4 * g + j][s] = vout[s][j];
+  __syncthreads();
+  if (tid < kTile * S) {
+    int c = tid / S, s = tid % S;
+    float v = part[0][c][s] + part[1][c][s] + part[2][c][s] + part[3][c][s];
+    if (s == 0) v += np.bout[0];
+    if (slot0 + c < slot_end) outputs[(slot0 + c) * 8 + s] = v;
+  }
+}
+
+// ===========================================================================
+// MLP backward for hidden layer l (persistent work-groups; each accumulates
+// dW_l over its tiles in MFMA accumulators and writes one partial row)
+// ===========================================================================
+template <int D, int W, int ACT, int PREC>
+__global__ __launch_bounds__(256) void k_backward(const Meta* meta, const float4* centres, Nets nets,
+                                                  int L, int l, float h, const float* adj,
+                                                  const float* Zst, const void* Ast_,
+                                                  const float* ALst, float* dZ, float* partial,
+                                                  int64_t Ptot, NetLayout lay, int64_t net_off1,
+                                                  int64_t lstride) {
+  typedef typename Op<PREC>::T T;
+  constexpr int S = 2 * D + 1;
+  constexpr int LD = W + Pad<PREC>::v;
+  constexpr int NOB = W / 16;
+  constexpr int OBW = (NOB + 3) / 4;
+  constexpr int KC = W / 4;
+  __shared__ __attribute__((aligned(16))) T dzrow[S][kTile][LD];
+  __shared__ float adjs[kTile][8];
+  __shared__ float xs[kTile][4];
+  const T* Ast = (const T*)Ast_;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r16 = lane & 15, g = lane >> 4;
+  const int G = gridDim.x;
+  const int ntiles = meta->tiles[0] + meta->tiles[1];
+  const bool top = (l == L), bottom = (l == 2);
+
+  for (int net = 0; net < 2; ++net) {
+    const NetPtrs& np = nets.net[net];
+    const T* WmT = (const T*)np.WlT[l - 2];
+    f4 accW[OBW][NOB];
+    float accb[OBW], accwo[OBW], accW1[OBW][3], accb1[OBW];
+    float accbo = 0.0f;
+    for (int i = 0; i < OBW; ++i) {
+      for (int k = 0; k < NOB; ++k) accW[i][k] = f4{0.f, 0.f, 0.f, 0.f};
+      accb[i] = 0.f; accwo[i] = 0.f; accb1[i] = 0.f;
+      for (int a = 0; a < 3; ++a) accW1[i][a] = 0.f;
+    }
+    for (int t = blockIdx.x; t < ntiles; t += G) {
+      if (tile_net(meta, t) != net) continue;
+      const int64_t slot0 = (int64_t)t * kTile;
+      if (tid < kTile * 8) {
+        int c = tid >> 3, s = tid & 7;
+        adjs[c][s] = top ? adj[(slot0 + c) * 8 + s] : 0.0f;
+      }
+      if (tid < kTile) {
+        float4 cc = centres[slot0 + tid];
+        const int64_t slot_end = (int64_t)meta->tile0[net] * kTile + meta->total[net];
+        if (slot0 + tid >= slot_end) cc = make_float4(0.f, 0.f, 0.f, 0.f);
+        xs[tid][0] = cc.x; xs[tid][1] = cc.y; xs[tid][2] = cc.z; xs[tid][3] = 0.f;
+      }
+      __syncthreads();
+      // ---- dZ_l for the out-blocks owned by this wave (accumulator layout)
+      float dz[OBW][S][4];
+      for (int i = 0; i < OBW; ++i) {
+        int ob = w + 4 * i;
+        if (ob >= NOB) break;
+        int n = ob * 16 + r16;
+        if (top) {
+          float wo = np.wout[n];
+          for (int s = 0; s < S; ++s) {
+            int64_t o = (((int64_t)t * S + s) * W + n) * kTile + 4 * g;
+            float4 zv = *(const float4*)(Zst + (int64_t)(l - 1) * lstride + o);
+            float4 av = *(const float4*)(ALst + o);
+            float za[4] = {zv.x, zv.y, zv.z, zv.w}, aa[4] = {av.x, av.y, av.z, av.w};
+            for (int j = 0; j < 4; ++j) {
+              dz[i][s][j] = za[j];
+              accwo[i] += adjs[4 * g + j][s] * aa[j];
+            }
+          }
+          for (int j = 0; j < 4; ++j) {
+            float p[3], e[3], Db[3], Eb[3], zb, pb[3], eb[3];
+            for (int a = 0; a < D; ++a) {
+              p[a] = dz[i][1 + a][j]; e[a] = dz[i][1 + D + a][j];
+              Db[a] = wo * adjs[4 * g + j][1 + a]; Eb[a] = wo * adjs[4 * g + j][1 + D + a];
+            }
+            act_bwd<ACT, D>(dz[i][0][j], p, e, wo * adjs[4 * g + j][0], Db, Eb, zb, pb, eb);
+            dz[i][0][j] = zb;
+            for (int a = 0; a < D; ++a) { dz[i][1 + a][j] = pb[a]; dz[i][1 + D + a][j] = eb[a]; }
+          }
+        } else {
+          for (int s = 0; s < S; ++s) {
+            int64_t o = (((int64_t)t * S + s) * W + n) * kTile + 4 * g;
+            float4 v = *(const float4*)(dZ + o);
+            dz[i][s][0] = v.x; dz[i][s][1] = v.y; dz[i][s][2] = v.z; dz[i][s][3] = v.w;
+          }
+        }
+        for (int j = 0; j < 4; ++j) accb[i] += dz[i][0][j];
+      }
+      if (top && tid == 0)
+        for (int c = 0; c < kTile; ++c) accbo += adjs[c][0];
+      // ---- dW_l += dZ_l^T A_{l-1}: K runs over (stream, centre)
+      for (int ib = 0; ib < NOB; ++ib) {
+        const int nin = ib * 16 + r16;
+        if constexpr (PREC == 0) {
+          float ap[S][4];
+          for (int s = 0; s < S; ++s) {
+            int64_t o = (((int64_t)t * S + s) * W + nin) * kTile + 4 * g;
+            float4 v = *(const float4*)((const float*)Ast + (int64_t)(l - 2) * lstride + o);
+            ap[s][0] = v.x; ap[s][1] = v.y; ap[s][2] = v.z; ap[s][3] = v.w;
+          }
+          for (int i = 0; i < OBW; ++i) {
+            if (w + 4 * i >= NOB) break;
+            for (int s = 0; s < S; ++s)
+              for (int j = 0; j < 4; ++j) accW[i][ib] = mfma4(dz[i][s][j], ap[s][j], accW[i][ib]);
+          }
+        } else {
+          bf4 ap[S + 1];
+          for (int s = 0; s < S; ++s) {
+            int64_t o = (((int64_t)t * S + s) * W + nin) * kTile + 4 * g;
+            ap[s] = *(const bf4*)(Ast + (int64_t)(l - 2) * lstride + o);
+          }
+          ap[S] = bf4{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+          for (int i = 0; i < OBW; ++i) {
+            if (w + 4 * i >= NOB) break;
+            for (int s = 0; s < S; s += 2) {
+              bf8 av, bv;
+              for (int j = 0; j < 4; ++j) {
+                av[j] = (__bf16)dz[i][s][j];
+                av[4 + j] = (s + 1 < S) ? (__bf16)dz[i][s + 1][j] : (__bf16)0.f;
+                bv[j] = ap[s][j];
+                bv[4 + j] = ap[s + 1][j];
+              }
+              accW[i][ib] = mfma32(av, bv, accW[i][ib]);
+            }
+          }
+        }
+      }
+      // ---- dA: abar_{l-1} = dZ_l W_l, then dZ_{l-1} from the stored pre-activations
+      for (int i = 0; i < OBW; ++i) {
+        int ob = w + 4 * i;
+        if (ob >= NOB) break;
+        for (int s = 0; s < S; ++s)
+          for (int j = 0; j < 4; ++j) dzrow[s][4 * g + j][ob * 16 + r16] = from_f<T>(dz[i][s][j]);
+      }
+      __syncthreads();
+      for (int i = 0; i < OBW; ++i) {
+        int ib = w + 4 * i;
+        if (ib >= NOB) break;
+        const int nin = ib * 16 + r16;
+        f4 acc[S];
+        for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (PREC == 0) {
+          float bk[KC];
+          const float4* wp = (const float4*)((const float*)WmT + (int64_t)nin * W + g * KC);
+          for (int q = 0; q < KC / 4; ++q) {
+            float4 v4 = wp[q];
+            bk[4 * q] = v4.x; bk[4 * q + 1] = v4.y; bk[4 * q + 2] = v4.z; bk[4 * q + 3] = v4.w;
+          }
+          for (int s = 0; s < S; ++s) {
+            const float4* ap = (const float4*)(&dzrow[s][r16][g * KC]);
+            for (int q = 0; q < KC / 4; ++q) {
+              float4 a4 = ap[q];
+              acc[s] = mfma4(a4.x, bk[4 * q], acc[s]);
+              acc[s] = mfma4(a4.y, bk[4 * q + 1], acc[s]);
+              acc[s] = mfma4(a4.z, bk[4 * q + 2], acc[s]);
+              acc[s] = mfma4(a4.w, bk[4 * q + 3], acc[s]);
+            }
+          }
+        } else {
+          bf8 bk[KC / 8];
+          const bf8* wp = (const bf8*)((const T*)WmT + (int64_t)nin * W + g * KC);
+          for (int q = 0; q < KC / 8; ++q) bk[q] = wp[q];
+          for (int s = 0; s < S; ++s) {
+            const bf8* ap = (const bf8*)(&dzrow[s][r16][g * KC]);
+            for (int q = 0; q < KC / 8; ++q) acc[s] = mfma32(ap[q], bk[q], acc[s]);
+          }
+        }
+        // pre-activations of layer l-1
+        float zp[S][4];
+        for (int s = 0; s < S; ++s) {
+          int64_t o = (((int64_t)t * S + s) * W + nin) * kTile + 4 * g;
+          float4 v = *(const float4*)(Zst + (int64_t)(l - 2) * lstride + o);
+          zp[s][0] = v.x; zp[s][1] = v.y; zp[s][2] = v.z; zp[s][3] = v.w;
+        }
+        float out[S][4];
+        for (int j = 0; j < 4; ++j) {
+          float p[3], e[3], Db[3], Eb[3], zb, pb[3], eb[3];
+          for (int a = 0; a < D; ++a) {
+            p[a] = zp[1 + a][j]; e[a] = zp[1 + D + a][j];
+            Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j];
+          }
+          act_bwd<ACT, D>(zp[0][j], p, e, acc[0][j], Db, Eb, zb, pb, eb);
+          out[0][j] = zb;
+          for (int a = 0; a < D; ++a) { out[1 + a][j] = pb[a]; out[1 + D + a][j] = eb[a]; }
+        }
+        if (!bottom) {
+          for (int s = 0; s < S; ++s) {
+            int64_t o = (((int64_t)t * S + s) * W + nin) * kTile + 4 * g;
+            *(float4*)(dZ + o) = make_float4(out[s][0], out[s][1], out[s][2], out[s][3]);
+          }
+        } else {
+          // layer 1: z = W1 x + b1, p_a = h W1[:, a]
+          for (int j = 0; j < 4; ++j) {
+            int c = 4 * g + j;
+            accb1[i] += out[0][j];
+            for (int a = 0; a < D; ++a) accW1[i][a] += out[0][j] * xs[c][a] + h * out[1 + a][j];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // ---- flush this net's partial gradient
+    float* prow = partial + (int64_t)blockIdx.x * Ptot + (net == 0 ? 0 : net_off1);
+    for (int i = 0; i < OBW; ++i) {
+      int ob = w + 4 * i;
+      if (ob >= NOB) break;
+      for (int ib = 0; ib < NOB; ++ib)
+        for (int r = 0; r < 4; ++r) {
+          int row = ob * 16 + 4 * g + r, col = ib * 16 + r16;
+          prow[lay.Wl[l - 2] + (int64_t)row * W + col] = accW[i][ib][r];
+        }
+      float vb = accb[i];
+      vb += __shfl_xor(vb, 16);
+      vb += __shfl_xor(vb, 32);
+      float vwo = accwo[i];
+      vwo += __shfl_xor(vwo, 16);
+      vwo += __shfl_xor(vwo, 32);
+      float vb1 = accb1[i], vw1[3];
+      vb1 += __shfl_xor(vb1, 16);
+      vb1 += __shfl_xor(vb1, 32);
+      for (int a = 0; a < 3; ++a) {
+        vw1[a] = accW1[i][a];
+        vw1[a] += __shfl_xor(vw1[a], 16);
+        vw1[a] += __shfl_xor(vw1[a], 32);
+      }
+      int n = ob * 16 + r16;
+      if (g == 0) {
+        prow[lay.bl[l - 2] + n] = vb;
+        if (top) prow[lay.wout + n] = vwo;
+        if (bottom) {
+          prow[lay.b1 + n] = vb1;
+          for (int a = 0; a < D; ++a) prow[lay.W1 + (int64_t)n * D + a] = vw1[a];
+        }
+      }
+    }
+    if (top && tid == 0) prow[lay.bout] = accbo;
+  }
+}
+
+// ===========================================================================
+// Host-side launchers
+// ===========================================================================
+template <int D, int W, int ACT, int PREC>
+struct Launch {
+  static hipError_t forward(hipStream_t st, int grid, const Meta* meta, const float4* centres,
+                            const Nets& nets, int L, float h, float* outputs, float* Zst, void* Ast,
+                            float* ALst, int64_t lstride, bool store, bool streams) {
+    if (streams && store)
+      hipLaunchKernelGGL((k_forward<D, W, 2 * D + 1, ACT, PREC, true>), dim3(grid), dim3(256), 0, st,
+                         meta, centres, nets, L, h, outputs, Zst, Ast, ALst, lstride);
+    else if (streams)
+      hipLaunchKernelGGL((k_forward<D, W, 2 * D + 1, ACT, PREC, false>), dim3(grid), dim3(256), 0, st,
+                         meta, centres, nets, L, h, outputs, Zst, Ast, ALst, lstride);
+    else
+      hipLaunchKernelGGL((k_forward<D, W, 1, ACT, PREC, false>), dim3(grid), dim3(256), 0, st, meta,
+                         centres, nets, L, h, outputs, Zst, Ast, ALst, lstride);
+    return hipGetLastError();
+  }
+  static hipError_t backward(hipStream_t st, int G, const Meta* meta, const float4* centres,
+                             const Nets& nets, int L, int l, float h, const float* adj,
+                             const float* Zst, const void* Ast, const float* ALst, float* dZ,
+                             float* partial, int64_t Ptot, const NetLayout& lay, int64_t off1,
+                             int64_t lstride) {
+    hipLaunchKernelGGL((k_backward<D, W, ACT, PREC>), dim3(G), dim3(256), 0, st, meta, centres, nets,
+                       L, l, h, adj, Zst, Ast, ALst, dZ, partial, Ptot, lay, off1, lstride);
+    return hipGetLastError();
+  }
+};
+
+template <int D>
+hipError_t launch_sample(hipStream_t st, uint64_t seed, int64_t step, int64_t jh, float* pts,
+                         int64_t n, float* bpts, int64_t nb) {
+  int64_t tot = n + nb;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sample<D>, dim3((tot + 255) / 256), dim3(256), 0, st, seed, step, jh, pts, n,
+                     bpts, nb);
+  return hipGetLastError();
+}
+
+#define NBM_FWD_BWD(D, W, ACT, PREC)                                                                \
+  if (dim == D && width == W && act == ACT && prec == PREC) return &dispatch_impl<D, W, ACT, PREC>;
+
+template <int D, int W, int ACT, int PREC>
+hipError_t dispatch_impl(const MlpCall& c) {
+  if (c.op == MlpCall::FORWARD)
+    return Launch<D, W, ACT, PREC>::forward(c.stream, c.grid, c.meta, c.centres, *c.nets, c.L, c.h,
+                                            c.outputs, c.Zst, c.Ast, c.ALst, c.lstride, c.store,
+                                            c.streams);
+  return Launch<D, W, ACT, PREC>::backward(c.stream, c.grid, c.meta, c.centres, *c.nets, c.L, c.l,
+                                           c.h, c.adj, c.Zst, c.Ast, c.ALst, c.dZ, c.partial, c.Ptot,
+                                           *c.lay, c.off1, c.lstride);
+}
+
+MlpFn find_mlp(int dim, int width, int act, int prec) {
+  NBM_FWD_BWD(2, 16, 0, 0)
+  NBM_FWD_BWD(2, 16, 1, 0)
+  NBM_FWD_BWD(3, 16, 0, 0)
+  NBM_FWD_BWD(3, 16, 1, 0)
+  NBM_FWD_BWD(3, 64, 0, 0)
+  NBM_FWD_BWD(3, 64, 1, 0)
+  NBM_FWD_BWD(3, 64, 0, 1)
+  NBM_FWD_BWD(3, 64, 1, 1)
+  NBM_FWD_BWD(3, 128, 0, 0)
+  NBM_FWD_BWD(3, 128, 1, 0)
+  NBM_FWD_BWD(3, 128, 0, 1)
+  NBM_FWD_BWD(3, 128, 1, 1)
+  return nullptr;
+}
+
+// ---- non-MLP launchers ------------------------------------------------------
+template <int D>
+static void prep_impl(const PrepCall& c, int64_t nblk, int64_t nblkb) {
+  hipStream_t st = c.stream;
+  if (c.n)
+    hipLaunchKernelGGL(k_classify<D>, dim3(nblk), dim3(256), 0, st, c.P, c.pts, c.n, c.eval ? 1 : 0,
+                       c.tile_index, c.grid_n, c.cls, c.rank, c.blockcnt);
+  if (c.nb)
+    hipLaunchKernelGGL(k_classify<D>, dim3(nblkb), dim3(256), 0, st, c.P, c.bpts, c.nb, 1, (int64_t)0,
+                       0, c.bcls, c.brank, c.blockcnt_b);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, st, c.blockcnt, (int)nblk, c.blockcnt_b,
+                     (int)nblkb, c.off, c.off_b, c.meta, (int)c.n, (int)c.nb, c.cut_cap, D, c.P.lo,
+                     c.eval ? 1 : 0);
+  if (c.n)
+    hipLaunchKernelGGL(k_scatter<D>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls,
+                       c.rank, c.off, 0, c.tile_index, c.grid_n, c.centres, c.src, c.cutidx);
+  if (c.nb)
+    hipLaunchKernelGGL(k_scatter<D>, dim3(nblkb), dim3(256), 0, st, c.P, c.meta, c.bpts, c.nb,
+                       c.bcls, c.brank, c.off_b, 1, (int64_t)0, 0, c.centres, c.src, c.cutidx);
+}
+
+hipError_t launch_prep(const PrepCall& c) {
+  int64_t nblk = (c.n + 255) / 256, nblkb = (c.nb + 255) / 256;
+  if (c.P.dim == 2) prep_impl<2>(c, nblk, nblkb);
+  else prep_impl<3>(c, nblk, nblkb);
+  return hipGetLastError();
+}
+
+hipError_t launch_residuals(const ResCall& c) {
+  hipStream_t st = c.stream;
+  int64_t nblk = (c.n + 255) / 256, nblkb = (c.nb + 255) / 256, nblkc = (c.cut_cap + 255) / 256;
+  double* lp = c.lossp;
+  if (c.P.dim == 2) {
+    if (c.n) hipLaunchKernelGGL(k_res_uncut<2>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale);
+    if (c.n) hipLaunchKernelGGL(k_res_cut<2>, dim3(nblkc), dim3(256), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale);
+    if (c.nb) hipLaunchKernelGGL(k_res_bnd<2>, dim3(nblkb), dim3(256), 0, st, c.P, c.meta, c.bpts, c.nb, c.bcls, c.brank, c.outputs, c.adj, c.resid + c.n, lp + nblk + nblkc, c.scale);
+  } else {
+    if (c.n) hipLaunchKernelGGL(k_res_uncut<3>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale);
+    if (c.n) hipLaunchKernelGGL(k_res_cut<3>, dim3(nblkc), dim3(256), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale);
+    if (c.nb) hipLaunchKernelGGL(k_res_bnd<3>, dim3(nblkb), dim3(256), 0, st, c.P, c.meta, c.bpts, c.nb, c.bcls, c.brank, c.outputs, c.adj, c.resid + c.n, lp + nblk + nblkc, c.scale);
+  }
+  int nparts = (int)(nblk + nblkc + nblkb);
+  if (c.n == 0) nparts = (int)nblkb, lp = c.lossp + nblk + nblkc;
+  if (c.nb == 0 && c.n != 0) nparts = (int)(nblk + nblkc);
+  if (c.loss) hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(256), 0, st, lp, nparts, c.meta, c.loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(hipStream_t st, float* p, int64_t n, float v) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_shadow(hipStream_t st, int prec, const float* params, int64_t off, int W, void* Wl,
+                         void* WlT) {
+  int n = W * W;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_shadow<float>, dim3((n + 255) / 256), dim3(256), 0, st, params, off, W,
+                       (float*)Wl, (float*)WlT);
+  else
+    hipLaunchKernelGGL(k_shadow<__bf16>, dim3((n + 255) / 256), dim3(256), 0, st, params, off, W,
+                       (__bf16*)Wl, (__bf16*)WlT);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_grad(hipStream_t st, const float* partial, int G, int64_t P, float* grad,
+                              double scale) {
+  hipLaunchKernelGGL(k_reduce_grad, dim3((P + 255) / 256), dim3(256), 0, st, partial, G, P, grad,
+                     scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(hipStream_t st, float* p, float* m, float* v, const float* g, int64_t n,
+                       float lr, float b1, float b2, float eps, float c1, float c2) {
+  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, p, m, v, g, n, lr, b1, b2, eps,
+                     c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_points(hipStream_t st, int dim, uint64_t seed, int64_t step, int64_t jh,
+                                float* pts, int64_t n, float* bpts, int64_t nb) {
+  return dim == 2 ? launch_sample<2>(st, seed, step, jh, pts, n, bpts, nb)
+                  : launch_sample<3>(st, seed, step, jh, pts, n, bpts, nb);
+}
+
+hipError_t launch_counts(hipStream_t st, const Meta* meta, int* counts) {
+  hipLaunchKernelGGL(k_counts, dim3(1), dim3(64), 0, st, meta, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_out(hipStream_t st, int64_t slots, const Meta* meta, const float* outputs,
+                           const int* src, float* u_out) {
+  hipLaunchKernelGGL(k_eval_out, dim3((slots + 255) / 256), dim3(256), 0, st, meta, outputs, src,
+                     u_out);
+  return hipGetLastError();
+}
+
+}  // namespace nbm

@@ -1,0 +1,86 @@
+// Host-side launcher interface between the C ABI and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "nbm_internal.hpp"
+
+namespace nbm {
+
+struct MlpCall {
+  enum Op { FORWARD, BACKWARD } op;
+  hipStream_t stream;
+  int grid;
+  const Meta* meta;
+  const float4* centres;
+  const Nets* nets;
+  int L, l;
+  float h;
+  float* outputs;
+  const float* adj;
+  float* Zst;
+  void* Ast;
+  float* ALst;
+  float* dZ;
+  float* partial;
+  int64_t Ptot;
+  const NetLayout* lay;
+  int64_t off1;
+  int64_t lstride;
+  bool store, streams;
+};
+typedef hipError_t (*MlpFn)(const MlpCall&);
+MlpFn find_mlp(int dim, int width, int act, int prec);
+
+struct PrepCall {
+  hipStream_t stream;
+  Problem P;
+  const float* pts;
+  int64_t n;
+  const float* bpts;
+  int64_t nb;
+  bool eval;
+  int64_t tile_index;
+  int grid_n;
+  int cut_cap;
+  int *cls, *rank, *blockcnt, *off;
+  int *bcls, *brank, *blockcnt_b, *off_b;
+  Meta* meta;
+  float4* centres;
+  int* src;
+  int* cutidx;
+};
+hipError_t launch_prep(const PrepCall& c);
+
+struct ResCall {
+  hipStream_t stream;
+  Problem P;
+  const Meta* meta;
+  const float* pts;
+  int64_t n;
+  const float* bpts;
+  int64_t nb;
+  const int *cls, *rank, *bcls, *brank, *cutidx;
+  int cut_cap;
+  const float* outputs;
+  float* adj;
+  float* resid;
+  double* lossp;
+  double* loss;
+  double scale;
+};
+hipError_t launch_residuals(const ResCall& c);
+
+hipError_t launch_fill(hipStream_t st, float* p, int64_t n, float v);
+hipError_t launch_shadow(hipStream_t st, int prec, const float* params, int64_t off, int W, void* Wl,
+                         void* WlT);
+hipError_t launch_reduce_grad(hipStream_t st, const float* partial, int G, int64_t P, float* grad,
+                              double scale);
+hipError_t launch_adam(hipStream_t st, float* p, float* m, float* v, const float* g, int64_t n,
+                       float lr, float b1, float b2, float eps, float c1, float c2);
+hipError_t launch_sample_points(hipStream_t st, int dim, uint64_t seed, int64_t step, int64_t jh,
+                                float* pts, int64_t n, float* bpts, int64_t nb);
+hipError_t launch_counts(hipStream_t st, const Meta* meta, int* counts);
+hipError_t launch_eval_out(hipStream_t st, int64_t slots, const Meta* meta, const float* outputs,
+                           const int* src, float* u_out);
+
+}  // namespace nbm

@@ -1,0 +1,49 @@
+"""Helpers shared by the GPU parity tests: seeded inputs and oracle calls."""
+import math
+
+import numpy as np
+
+import nbm_inputs as I
+from oracle import geometry as G
+
+
+def near_star_points(wl, n, band, seed=9):
+    """Lattice points within `band` (radially) of the star interface: the star
+    radius in direction v is R + amp sin(5 theta) sin(4 psi), read off the
+    oracle level set along the ray."""
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=(n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    # phi(t v) = t - R(v) on a ray, so R(v) = t - phi(t v) for any t > 0
+    Rv = 0.5 - G.phi(wl, 0.5 * v)
+    r = Rv + 0.5 + rng.uniform(-band, band, size=n) - 0.5
+    x = v * r[:, None]
+    q = float(2 ** 22)
+    return np.round(x * q) / q
+
+
+def parity_batch(wl, n, nb, n_near, band, seed=1):
+    pts, bpts = I.collocation_batch(wl, n, nb, seed=seed)
+    if n_near:
+        if wl.interface == I.IFACE_STAR:
+            near = near_star_points(wl, n_near, band, seed=seed + 11)
+        else:
+            near = I.near_interface_points(wl, n_near, band, seed=seed + 11)
+        lo, hi = -1 + wl.h, 1 - wl.h
+        near = np.clip(near, lo, hi)
+        pts = np.concatenate([pts, near])
+    return pts, bpts
+
+
+def rel_err(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+
+
+def max_rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.abs(b).max()
+    return np.abs(a - b).max() / (den if den > 0 else 1.0)

@@ -1,0 +1,166 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Bars: FP32 operands rel <= 1e-5, BF16 operands
+rel <= 2e-2 (loss, residual vector, gradient)."""
+import math
+
+import numpy as np
+import pytest
+
+import nbm_inputs as I
+from oracle import nbm as N
+from oracle import philox as PH
+from oracle import scheme as S
+from tests.gpu_common import max_rel, parity_batch, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {I.PREC_FP32: 1e-5, I.PREC_BF16: 2e-2}
+
+
+def _nbm(wl, n, nb, **kw):
+    from paper_2210_14907_amd import NBM
+    return NBM(wl, max_points=max(n, 16), max_boundary=max(nb, 1), **kw)
+
+
+def _run(wl, pts, bpts, theta):
+    dev = torch.device("cuda:0")
+    m = _nbm(wl, pts.shape[0], bpts.shape[0])
+    p = torch.tensor(theta, dtype=torch.float32, device=dev)
+    tp = torch.tensor(pts, dtype=torch.float32, device=dev)
+    tb = torch.tensor(bpts, dtype=torch.float32, device=dev).reshape(-1, wl.dim)
+    loss, res, grad = m.forward_residual(p, tp, tb, want_residual=True, want_grad=True)
+    counts = m.batch_counts().cpu().numpy()
+    torch.cuda.synchronize()
+    return loss.item(), res.cpu().numpy(), grad.cpu().numpy(), counts, m
+
+
+CASES = [
+    # name, workload, n, nb, n_near, band
+    ("c1", I.C1, 4096, 256, 256, 0.05),
+    ("c2", I.C2, 4096, 96, 512, 0.02),
+    ("c3", I.C3, 2048, 48, 256, 0.01),
+    ("c4", I.C4, 2048, 48, 256, 0.004),
+    ("c3_fp32", I.C3.replace(prec=I.PREC_FP32), 2048, 48, 256, 0.01),
+    ("c2_bf16", I.C2.replace(prec=I.PREC_BF16), 4096, 96, 512, 0.02),
+]
+
+
+@pytest.mark.parametrize("name,wl,n,nb,n_near,band", CASES, ids=[c[0] for c in CASES])
+def test_step_parity(name, wl, n, nb, n_near, band):
+    print(f"[parity] {name} n={n}+{n_near} nb={nb}", flush=True)
+    theta = I.xavier_params(wl, 0)
+    pts, bpts = parity_batch(wl, n, nb, n_near, band)
+    # points are FP32 on the GPU: give the oracle the identical values
+    pts = pts.astype(np.float32).astype(np.float64)
+    bpts = bpts.astype(np.float32).astype(np.float64)
+    th32 = theta.astype(np.float32).astype(np.float64)
+    L_o, g_o, res_o = N.loss_and_grad(wl, th32, pts, bpts)
+    L_g, r_g, g_g, counts, _ = _run(wl, pts, bpts, th32)
+    cls = res_o["cls"]
+    ncut = int((cls == S.CLASS_CUT).sum())
+    assert counts[0] == (cls == 0).sum() and counts[1] == (cls == 1).sum() and counts[2] == ncut
+    assert ncut > 0 and counts[5] == 0
+    tol = TOL[wl.prec]
+    r_o = np.concatenate([res_o["r"], res_o["rb"]])
+    e_loss = abs(L_g - L_o) / abs(L_o)
+    e_res = max_rel(r_g, r_o)
+    e_grad = rel_err(g_g, g_o)
+    # uncut residuals on their own scale
+    un = np.nonzero(cls != S.CLASS_CUT)[0]
+    e_unc = max_rel(r_g[un], res_o["r"][un])
+    print(f"[parity] {name}: loss {e_loss:.2e} res {e_res:.2e} uncut {e_unc:.2e} grad {e_grad:.2e} "
+          f"(cut {ncut})", flush=True)
+    assert e_loss <= tol and e_res <= tol and e_grad <= tol
+    assert e_unc <= (5 * tol if wl.prec == I.PREC_FP32 else tol)
+
+
+def test_determinism_bitwise():
+    wl = I.C2
+    theta = I.xavier_params(wl, 3).astype(np.float32)
+    pts, bpts = parity_batch(wl, 4096, 96, 256, 0.02, seed=4)
+    a = _run(wl, pts, bpts, theta)
+    b = _run(wl, pts, bpts, theta)
+    assert a[0] == b[0]
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[1], b[1])
+
+
+def test_sampling_matches_oracle_philox():
+    from paper_2210_14907_amd import NBM
+    for wl in (I.C1, I.C2, I.C4):
+        m = NBM(wl, max_points=20000, max_boundary=700)
+        seed, step = 0x123456789A, 77
+        pts, bpts = m.sample_points(seed, step, 20000, 700)
+        po, bo = PH.sample_points(wl.dim, wl.h, 20000, 700, seed, step)
+        assert np.array_equal(pts.cpu().numpy().astype(np.float64), po)
+        assert np.array_equal(bpts.cpu().numpy().astype(np.float64), bo)
+
+
+def test_adam_matches_oracle():
+    from paper_2210_14907_amd import NBM
+    wl = I.C1
+    m = NBM(wl, max_points=64, max_boundary=8)
+    rng = np.random.default_rng(0)
+    P = wl.n_params
+    th = rng.normal(size=P).astype(np.float32)
+    g = rng.normal(size=P).astype(np.float32)
+    m0 = (0.1 * rng.normal(size=P)).astype(np.float32)
+    v0 = np.abs(0.1 * rng.normal(size=P)).astype(np.float32)
+    dev = torch.device("cuda:0")
+    tp, tm, tv, tg = (torch.tensor(a, device=dev) for a in (th, m0, v0, g))
+    m.adam_step(tp, tm, tv, tg, 5, lr=1e-3)
+    ref, mr, vr = N.adam_step(th.astype(np.float64), m0.astype(np.float64), v0.astype(np.float64),
+                              g.astype(np.float64), 5, lr=1e-3)
+    assert np.allclose(tp.cpu().numpy(), ref, rtol=0, atol=1e-6)
+    assert np.allclose(tm.cpu().numpy(), mr, rtol=1e-6, atol=1e-7)
+    assert np.allclose(tv.cpu().numpy(), vr, rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("wl", [I.C1, I.C2, I.C3, I.C4], ids=["c1", "c2", "c3", "c4"])
+def test_eval_matches_oracle(wl):
+    from paper_2210_14907_amd import NBM
+    from oracle import geometry as G
+    from oracle import mlp as M
+    theta = I.xavier_params(wl, 1).astype(np.float32).astype(np.float64)
+    m = NBM(wl, max_points=5000, max_boundary=1)
+    dev = torch.device("cuda:0")
+    p = torch.tensor(theta, dtype=torch.float32, device=dev)
+    q = I.lattice_points(3000, wl.dim, -1.0, 1.0, seed=5)
+    u = m.eval(p, torch.tensor(q, dtype=torch.float32, device=dev)).cpu().numpy()
+    ref = M.eval_two(wl, theta, q, G.side_minus(wl, q))
+    tol = 1e-5 if wl.prec == I.PREC_FP32 else 2e-2
+    assert max_rel(u, ref) <= tol
+    # grid tile: points -1 + 2 i / grid_n
+    gn = 16
+    mt = gn ** wl.dim // 4
+    ut = m.eval(p, None, m=mt, tile_index=2, grid_n=gn).cpu().numpy()
+    idx = np.arange(2 * mt, 3 * mt)
+    coords = np.stack([(idx // gn ** a) % gn for a in range(wl.dim)], axis=1)
+    xq = -1.0 + 2.0 * coords / gn
+    ref_t = M.eval_two(wl, theta, xq, G.side_minus(wl, xq))
+    assert max_rel(ut, ref_t) <= tol
+
+
+def test_edge_cases_small_and_ragged():
+    wl = I.C2
+    theta = I.xavier_params(wl, 2).astype(np.float32).astype(np.float64)
+    for n, nb in ((1, 0), (17, 3), (33, 0), (0, 5)):
+        pts, bpts = parity_batch(wl, max(n, 1), nb, 0, 0.0, seed=6 + n)
+        pts = pts[:n]
+        L_o, g_o, res_o = N.loss_and_grad(wl, theta, pts, bpts)
+        L_g, r_g, g_g, counts, _ = _run(wl, pts, bpts.reshape(-1, 3), theta)
+        assert abs(L_g - L_o) <= 1e-5 * abs(L_o)
+        assert rel_err(g_g, g_o) <= 1e-5
+
+
+def test_cut_capacity_overflow_gives_nan():
+    from paper_2210_14907_amd import NBM
+    wl = I.C2
+    dev = torch.device("cuda:0")
+    m = NBM(wl, max_points=512, max_boundary=8, cut_capacity=4)
+    pts, bpts = parity_batch(wl, 256, 8, 128, 0.01)
+    p = torch.tensor(I.xavier_params(wl, 0), dtype=torch.float32, device=dev)
+    loss, _, _ = m.forward_residual(p, torch.tensor(pts, dtype=torch.float32, device=dev),
+                                    torch.tensor(bpts, dtype=torch.float32, device=dev))
+    assert math.isnan(loss.item())
+    assert m.batch_counts().cpu().numpy()[5] == 1
