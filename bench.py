@@ -1,0 +1,228 @@
+"""Benchmark of the NBM training step on one MI355X.
+
+A step is one pass of the whole hot path over one batch of synthetic input:
+device sampling of the collocation points, classification, the difference-
+stream MLP forward on MFMA, the cut-cell residual and FP64 loss, the fused
+backward with FP64 gradient reduction, and Adam.  The batch is the 3-D sphere
+workload (65,536 interior + 1,536 boundary points, two 3->64x3->1 tanh nets,
+FP32 MFMA operands, h = 1/128, mu 1:10).  Inputs are resident in HBM before
+the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32": 157.3e12, "bf16": 2.5e15}
+
+
+def flops_per_centre(wl):
+    """Algorithmic FLOPs of evaluating one network on the 2d+1 stencil nodes
+    (forward) and of the backward, per the dense layer shapes."""
+    S, W, L, d = wl.n_streams, wl.width, wl.depth, wl.dim
+    fwd = 2 * S * ((L - 1) * W * W + d * W + W)
+    bwd = 2 * S * (2 * (L - 1) * W * W + d * W + 2 * W)
+    return fwd, bwd, 2 * S * 2 * W * W   # last: one backward hidden-layer launch
+
+
+def run_workload(wl, steps, warmup, seed=1, timing=True, train_to=0):
+    import torch
+    from paper_2210_14907_amd import NBM
+    from paper_2210_14907_amd.train import init_params
+
+    dev = torch.device("cuda:0")
+    nbm = NBM(wl)
+    params = init_params(wl, 0, dev)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    grad = torch.empty_like(params)
+    losses = torch.empty(max(steps + warmup, train_to) + 1, dtype=torch.float64, device=dev)
+    step = 0
+
+    def one(k):
+        pts, bpts = nbm.sample_points(seed, k)
+        nbm.forward_residual(params, pts, bpts, want_grad=True, loss=losses[k:k + 1], grad=grad)
+        nbm.adam_step(params, m, v, grad, k, lr=wl.lr)
+
+    for _ in range(warmup):
+        step += 1
+        one(step)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        step += 1
+        one(step)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    # fwd + residual + bwd only, on one resident batch
+    pts, bpts = nbm.sample_points(seed, 10 ** 6)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(steps):
+        nbm.forward_residual(params, pts, bpts, want_grad=True, loss=losses[0:1], grad=grad)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_fb = ev0.elapsed_time(ev1) / steps
+    out = {"ms_per_step": ms, "ms_fwd_res_bwd": ms_fb}
+    if timing:
+        counts = nbm.batch_counts().cpu().numpy()
+        nbm.set_timing(True)
+        for _ in range(max(3, min(steps, 20))):
+            step += 1
+            one(step)
+        tm = nbm.read_timing()
+        nbm.set_timing(False)
+        counts = nbm.batch_counts().cpu().numpy()
+        out["timing"] = tm
+        out["counts"] = counts
+    if train_to > step:
+        while step < train_to:
+            step += 1
+            one(step)
+        torch.cuda.synchronize()
+    out["steps_trained"] = step
+    out["final_loss"] = float(losses[step].item())
+    out["params"] = params
+    out["nbm"] = nbm
+    return out
+
+
+def accuracy(wl, res, judge_n):
+    """L-inf / L2 of the trained surrogate at the interior nodes of a judge
+    grid, against the closed-form solution and the FP64 grid CG oracle."""
+    import torch
+    from oracle import grid as OG
+
+    nbm, params = res["nbm"], res["params"]
+    gs = OG.GridSystem(wl, judge_n)
+    t0 = time.time()
+    U = gs.solve()
+    t_judge = time.time() - t0
+    xin = gs.x[gs.interior]
+    q = torch.tensor(xin, dtype=torch.float32, device=nbm.device)
+    u = np.concatenate([nbm.eval(params, q[i:i + 60000]).cpu().numpy() for i in range(0, len(q), 60000)])
+    out = {"judge_n": judge_n, "judge_seconds": round(t_judge, 2)}
+    e = u - U[gs.interior]
+    out["linf_vs_grid"] = float(np.abs(e).max())
+    out["l2_vs_grid"] = float(np.sqrt(np.mean(e * e)))
+    if gs.prob.has_exact():
+        ex = gs.prob.u_exact(xin)
+        out["linf_vs_exact"] = float(np.abs(u - ex).max())
+        out["l2_vs_exact"] = float(np.sqrt(np.mean((u - ex) ** 2)))
+        out["grid_linf_vs_exact"] = float(np.abs(U[gs.interior] - ex).max())
+    return out
+
+
+def cpu_baseline(wl, target_s=15.0):
+    """The FP64 oracle's step (point evaluation + reverse mode) on a bounded
+    sample of the same workload, timed on the host cores."""
+    from threadpoolctl import threadpool_info
+
+    import nbm_inputs as I
+    from oracle import nbm as ON
+
+    theta = I.xavier_params(wl, 0)
+    n0 = 2048
+    pts, bpts = I.collocation_batch(wl, n0, max(1, int(round(n0 * wl.dim * wl.h))), seed=11)
+    t = time.time()
+    ON.loss_and_grad(wl, theta, pts, bpts)
+    rate0 = n0 / (time.time() - t)
+    n = int(min(wl.n_points, max(n0, rate0 * target_s)))
+    nb = int(round(n * wl.dim * wl.h))
+    pts, bpts = I.collocation_batch(wl, n, nb, seed=12)
+    t = time.time()
+    ON.loss_and_grad(wl, theta, pts, bpts)
+    dt = time.time() - t
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": round(n / dt, 1), "unit": "colloc pts/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n} interior + {nb} boundary points of the same workload, one FP64 step "
+                      f"(loss + gradient), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the data-parallel path across GPUs is not part of "
+              "this build (see DESIGN.md, 'Sharding').", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import nbm_inputs as I
+
+    wl = I.C2
+    res = run_workload(wl, args.steps, args.warmup, train_to=0 if args.no_accuracy else wl.steps)
+    n_step = wl.n_points
+    value = n_step / (res["ms_per_step"] * 1e-3)
+    fwd_f, bwd_f, bl_f = flops_per_centre(wl)
+    tm = res["timing"]
+    c = res["counts"]
+    nbr = 2 * wl.dim if wl.mu_minus != wl.mu_plus else 0
+    centres = int(c[0] + c[1] + (2 + nbr) * c[2] + c[3] + c[4])
+    f_ms, f_n = tm["forward"]
+    b_ms, b_n = tm["backward"]
+    if b_ms >= f_ms:
+        name, per_launch, avg = "k_backward (hidden layer, dW+dA)", bl_f * centres, b_ms / b_n
+    else:
+        name, per_launch, avg = "k_forward (all layers)", fwd_f * centres, f_ms / f_n
+    dtype = "fp32" if wl.prec == I.PREC_FP32 else "bf16"
+    achieved = per_launch / (avg * 1e-3)
+    line = {
+        "metric": "colloc pts/s (fwd+FV residual+bwd), BF16 vs FP32, at stated Linf vs FP64 oracle",
+        "value": round(value, 1),
+        "unit": "colloc pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (Philox lattice points, manufactured sphere solution, Xavier init seed 0)",
+        "config": {"workload": wl.name, "n_points": wl.n_points, "n_boundary": wl.n_boundary,
+                   "h": wl.h, "net": f"2 x {wl.dim}->{wl.width}x{wl.depth}->1 tanh", "mu": [1, 10]},
+        "fwd_res_bwd_pts_per_s": round(n_step / (res["ms_fwd_res_bwd"] * 1e-3), 1),
+        "kernel_ms_per_step": {k: round(v[0] / max(1, tm["forward"][1]), 4) for k, v in tm.items() if v[1]},
+        "roofline": {"bound": "mfma", "kernel": name, "achieved": achieved / 1e12,
+                     "peak": PEAK[dtype] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[dtype],
+                     "traffic": None, "flop_per_launch": per_launch, "avg_launch_ms": avg},
+    }
+    if not args.no_accuracy:
+        acc = accuracy(wl, res, 64)
+        acc["steps_trained"] = res["steps_trained"]
+        acc["final_loss"] = res["final_loss"]
+        line["accuracy"] = acc
+    if not args.no_extra:
+        extra = {}
+        for tag, w in (("c2_bf16", wl.replace(prec=I.PREC_BF16)), ("c3_bf16", I.C3),
+                       ("c3_fp32", I.C3.replace(prec=I.PREC_FP32))):
+            r = run_workload(w, max(10, args.steps // 2), 3, timing=False)
+            extra[tag] = {"pts_per_s": round(w.n_points / (r["ms_per_step"] * 1e-3), 1),
+                          "fwd_res_bwd_pts_per_s": round(w.n_points / (r["ms_fwd_res_bwd"] * 1e-3), 1),
+                          "ms_per_step": round(r["ms_per_step"], 4)}
+            del r
+            torch.cuda.empty_cache()
+        line["same_step_other_precisions"] = extra
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -152,6 +152,18 @@ int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const float* query
  * cut, boundary^-, boundary^+, overflow flag, 0, 0. */
 int nbm_batch_counts(nbm_ctx* ctx, void* stream, int32_t* counts, void* ws, size_t ws_bytes);
 
+/* Measurement support.  With timing enabled, every later call records a
+ * pair of HIP events on its stream around each kernel group:
+ * 0 shadow+classify+compact, 1 forward streams, 2 residual+loss,
+ * 3 backward (one pair per hidden-layer launch), 4 gradient reduction,
+ * 5 Adam, 6 sampling, 7 evaluation.  Costs a little host time per call. */
+int nbm_set_timing(nbm_ctx* ctx, int enable);
+
+/* Wait for the recorded events, write per group the summed milliseconds
+ * ms[8] and the number of timed launches launches[8] (host arrays), then
+ * forget the records.  Blocks the host. */
+int nbm_read_timing(nbm_ctx* ctx, double* ms, int64_t* launches);
+
 /* Thread-local description of the last error. */
 const char* nbm_last_error(void);
 

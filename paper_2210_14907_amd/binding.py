@@ -19,7 +19,7 @@ _lib = None
 
 EXPORTS = ["nbm_create", "nbm_destroy", "nbm_param_count", "nbm_workspace_bytes", "nbm_prepare",
            "nbm_sample_points", "nbm_forward_residual", "nbm_backward", "nbm_adam_step", "nbm_eval",
-           "nbm_batch_counts", "nbm_last_error"]
+           "nbm_batch_counts", "nbm_set_timing", "nbm_read_timing", "nbm_last_error"]
 
 
 class NbmConfig(ctypes.Structure):
@@ -64,6 +64,8 @@ def lib():
         L.nbm_adam_step.argtypes = [vp, vp, vp, vp, vp, vp, i64, f32, f32, f32, f32]
         L.nbm_eval.argtypes = [vp, vp, vp, vp, i64, i64, ctypes.c_int32, vp, vp, ctypes.c_size_t]
         L.nbm_batch_counts.argtypes = [vp, vp, vp, vp, ctypes.c_size_t]
+        L.nbm_set_timing.argtypes = [vp, ctypes.c_int]
+        L.nbm_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.nbm_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -177,6 +179,18 @@ class NBM:
         _check(lib().nbm_eval(self.ctx, _stream(), _ptr(params), _ptr(query), m, tile_index, grid_n,
                               _ptr(out), _ptr(self.ws_view), self.ws_bytes))
         return out
+
+    TIMING_GROUPS = ["prep", "forward", "residual", "backward", "reduce", "adam", "sample", "eval"]
+
+    def set_timing(self, enable: bool):
+        _check(lib().nbm_set_timing(self.ctx, 1 if enable else 0))
+
+    def read_timing(self):
+        """{group: (total ms, launches)} since the last read (blocks the host)."""
+        ms = (ctypes.c_double * 8)()
+        n = (ctypes.c_int64 * 8)()
+        _check(lib().nbm_read_timing(self.ctx, ms, n))
+        return {g: (ms[i], n[i]) for i, g in enumerate(self.TIMING_GROUPS)}
 
     def batch_counts(self):
         c = torch.zeros(8, dtype=torch.int32, device=self.device)

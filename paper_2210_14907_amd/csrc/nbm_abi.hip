@@ -33,7 +33,15 @@ struct Layout {
 };
 }  // namespace
 
+struct TimedPair {
+  int group;
+  hipEvent_t a, b;
+};
+
 struct nbm_ctx {
+  bool timing = false;
+  std::vector<TimedPair> timed;
+  std::vector<hipEvent_t> pool;
   nbm_config cfg;
   std::vector<float> modes32;
   std::vector<double> modes64;
@@ -46,6 +54,28 @@ struct nbm_ctx {
   int G;
   Layout lo;
   void* prepared_ws;
+};
+
+// event pair around one kernel group (no-op unless timing is enabled)
+struct Timer {
+  nbm_ctx* c;
+  hipStream_t st;
+  int group;
+  hipEvent_t b_;
+  bool on;
+  Timer(nbm_ctx* c_, hipStream_t s, int g) : c(c_), st(s), group(g), b_(nullptr), on(c_->timing) {
+    if (!on) return;
+    hipEvent_t a;
+    if (!c->pool.empty()) { a = c->pool.back(); c->pool.pop_back(); }
+    else if (hipEventCreate(&a) != hipSuccess) { on = false; return; }
+    if (!c->pool.empty()) { b_ = c->pool.back(); c->pool.pop_back(); }
+    else if (hipEventCreate(&b_) != hipSuccess) { on = false; return; }
+    (void)hipEventRecord(a, st);
+    c->timed.push_back({group, a, b_});
+  }
+  ~Timer() {
+    if (on) (void)hipEventRecord(b_, st);
+  }
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -183,7 +213,34 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
   return NBM_OK;
 }
 
-extern "C" void nbm_destroy(nbm_ctx* ctx) { delete ctx; }
+extern "C" void nbm_destroy(nbm_ctx* ctx) {
+  if (!ctx) return;
+  for (auto& t : ctx->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
+  for (auto& e : ctx->pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+extern "C" int nbm_set_timing(nbm_ctx* ctx, int enable) {
+  if (!ctx) return fail(NBM_EINVAL, "null context");
+  ctx->timing = enable != 0;
+  return NBM_OK;
+}
+
+extern "C" int nbm_read_timing(nbm_ctx* ctx, double* ms, int64_t* launches) {
+  if (!ctx || !ms || !launches) return fail(NBM_EINVAL, "null argument");
+  for (int g = 0; g < 8; ++g) { ms[g] = 0.0; launches[g] = 0; }
+  for (auto& t : ctx->timed) {
+    HIPCHK(hipEventSynchronize(t.b));
+    float v = 0.f;
+    HIPCHK(hipEventElapsedTime(&v, t.a, t.b));
+    ms[t.group] += v;
+    launches[t.group] += 1;
+    ctx->pool.push_back(t.a);
+    ctx->pool.push_back(t.b);
+  }
+  ctx->timed.clear();
+  return NBM_OK;
+}
 
 extern "C" int64_t nbm_param_count(const nbm_ctx* ctx) { return ctx ? ctx->Ptot : -1; }
 
@@ -261,6 +318,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   Problem P = problem_for(ctx, ws);
   // operand shadows of the hidden matrices
   Nets N = nets_for(ctx, params, ws);
+  Timer* tprep = new Timer(ctx, st, 0);
   for (int net = 0; net < 2; ++net)
     for (int l = 0; l < ctx->L - 1; ++l) {
       hipError_t e = launch_shadow(st, ctx->cfg.prec, params, net * ctx->per_net + ctx->lay.Wl[l], ctx->W,
@@ -281,6 +339,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   pc.src = at<int>(ws, Lo.src);
   pc.cutidx = at<int>(ws, Lo.cutidx);
   hipError_t e = launch_prep(pc);
+  delete tprep;
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("prep: ") + hipGetErrorString(e));
   // network streams at every centre
   int nbr = P.lo >= 0 ? 2 * ctx->D : 0;
@@ -295,10 +354,14 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   mc.Zst = at<float>(ws, Lo.Zst); mc.Ast = at<void>(ws, Lo.Ast); mc.ALst = at<float>(ws, Lo.ALst);
   mc.dZ = at<float>(ws, Lo.dZ); mc.lstride = ctx->lstride;
   mc.store = grad != nullptr; mc.streams = true;
-  e = ctx->mlp(mc);
+  {
+    Timer tf(ctx, st, 1);
+    e = ctx->mlp(mc);
+  }
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("forward: ") + hipGetErrorString(e));
   // residuals, loss and output adjoints
   float* adj = at<float>(ws, Lo.adj);
+  Timer* tres = new Timer(ctx, st, 2);
   if (grad) {
     e = launch_fill(st, adj, (int64_t)grid * kTile * 8, 0.0f);
     if (e != hipSuccess) return fail(NBM_EHIP, std::string("fill: ") + hipGetErrorString(e));
@@ -314,6 +377,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   rc.loss = loss ? loss : at<double>(ws, Lo.lossbuf);
   rc.scale = 2.0 * dL / (double)(n + nb);
   e = launch_residuals(rc);
+  delete tres;
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("residual: ") + hipGetErrorString(e));
   if (!grad) return NBM_OK;
   // backward through the hidden layers, gradient partials, FP64 reduction
@@ -326,10 +390,16 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   mc.off1 = ctx->per_net;
   for (int l = ctx->L; l >= 2; --l) {
     mc.l = l;
-    e = ctx->mlp(mc);
+    {
+      Timer tb(ctx, st, 3);
+      e = ctx->mlp(mc);
+    }
     if (e != hipSuccess) return fail(NBM_EHIP, std::string("backward: ") + hipGetErrorString(e));
   }
-  e = launch_reduce_grad(st, mc.partial, ctx->G, ctx->Ptot, grad, 1.0);
+  {
+    Timer tr(ctx, st, 4);
+    e = launch_reduce_grad(st, mc.partial, ctx->G, ctx->Ptot, grad, 1.0);
+  }
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("reduce: ") + hipGetErrorString(e));
   return NBM_OK;
 }
@@ -364,6 +434,7 @@ extern "C" int nbm_adam_step(nbm_ctx* ctx, void* stream, float* params, float* m
   if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
     return fail(NBM_EINVAL, "bad Adam hyper-parameters");
   double c1 = 1.0 - std::pow((double)beta1, (double)step), c2 = 1.0 - std::pow((double)beta2, (double)step);
+  Timer ta(ctx, (hipStream_t)stream, 5);
   hipError_t e = launch_adam((hipStream_t)stream, params, m, v, grad, ctx->Ptot, lr, beta1, beta2, eps,
                              (float)c1, (float)c2);
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("adam: ") + hipGetErrorString(e));
@@ -376,6 +447,7 @@ extern "C" int nbm_sample_points(nbm_ctx* ctx, void* stream, uint64_t seed, int6
   if (n < 0 || nb < 0 || (n && !pts) || (nb && !bpts)) return fail(NBM_EINVAL, "bad point buffers");
   if (step < 0) return fail(NBM_EINVAL, "negative step");
   int64_t jh = (int64_t)std::llround(ctx->cfg.h * (double)(1 << 22));
+  Timer ts(ctx, (hipStream_t)stream, 6);
   hipError_t e = launch_sample_points((hipStream_t)stream, ctx->D, seed, step, jh, pts, n, bpts, nb);
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("sample: ") + hipGetErrorString(e));
   return NBM_OK;
@@ -398,6 +470,7 @@ extern "C" int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const f
   const Layout& Lo = ctx->lo;
   Problem P = problem_for(ctx, ws);
   Nets N = nets_for(ctx, params, ws);
+  Timer tev(ctx, st, 7);
   for (int net = 0; net < 2; ++net)
     for (int l = 0; l < ctx->L - 1; ++l) {
       hipError_t e = launch_shadow(st, ctx->cfg.prec, params, net * ctx->per_net + ctx->lay.Wl[l], ctx->W,

@@ -138,7 +138,12 @@ def test_eval_matches_oracle(wl):
     coords = np.stack([(idx // gn ** a) % gn for a in range(wl.dim)], axis=1)
     xq = -1.0 + 2.0 * coords / gn
     ref_t = M.eval_two(wl, theta, xq, G.side_minus(wl, xq))
-    assert max_rel(ut, ref_t) <= tol
+    # grid points on Gamma (|phi| at rounding level) may take either network:
+    # compare the unique ones, accept either side for the rest
+    tie = np.abs(G.phi(wl, xq)) < 1e-12
+    alt = M.eval_two(wl, theta, xq, ~G.side_minus(wl, xq))
+    ok_tie = np.minimum(np.abs(ut - ref_t), np.abs(ut - alt)) <= tol * np.abs(ref_t).max()
+    assert max_rel(ut[~tie], ref_t[~tie]) <= tol and ok_tie[tie].all()
 
 
 def test_edge_cases_small_and_ragged():
