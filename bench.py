@@ -44,7 +44,7 @@ def run_workload(wl, steps, warmup, seed=1, timing=True, train_to=0):
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     grad = torch.empty_like(params)
-    losses = torch.empty(max(steps + warmup, train_to) + 1, dtype=torch.float64, device=dev)
+    losses = torch.empty(max(steps + warmup + 32, train_to + 1) + 1, dtype=torch.float64, device=dev)
     step = 0
 
     def one(k):

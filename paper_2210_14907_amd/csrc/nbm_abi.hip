@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -47,11 +48,13 @@ struct nbm_ctx {
   std::vector<double> modes64;
   Problem P;
   MlpFn mlp;
+  FusedFn fused;
   int D, W, L, S, opbytes;
   int64_t per_net, Ptot;
   NetLayout lay;
   int64_t cap_n, cap_nb, cut_cap, cap_slots, cap_tiles, lstride;
-  int G;
+  int G, Gf;
+  bool no_fused;
   Layout lo;
   void* prepared_ws;
 };
@@ -108,7 +111,7 @@ static void make_layout(nbm_ctx* c) {
   L.dZ = take(sizeof(float) * c->lstride);
   L.shadow = take((size_t)c->opbytes * 2 * (c->L - 1) * 2 * c->W * c->W);
   L.partial = take(sizeof(float) * (size_t)c->G * c->Ptot);
-  L.lossp = take(sizeof(double) * (nblk + nblkb + nblkc + 4));
+  L.lossp = take(sizeof(double) * (nblk + nblkb + nblkc + 4 + 512));
   L.resid = take(sizeof(float) * (c->cap_n + c->cap_nb));
   L.lossbuf = take(sizeof(double) * 4);
   L.total = o;
@@ -154,6 +157,7 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
   x->cfg.mode_k = nullptr;
   x->cfg.mode_a = x->cfg.mode_b = nullptr;
   x->mlp = fn;
+  x->fused = find_fused(c.dim, c.width, c.depth, c.act, c.prec);
   x->D = c.dim; x->W = c.width; x->L = c.depth; x->S = 2 * c.dim + 1;
   x->opbytes = c.prec == NBM_PREC_BF16 ? 2 : 4;
   // parameter layout of one net
@@ -207,6 +211,8 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
   x->cap_slots = x->cap_tiles * kTile;
   x->lstride = x->cap_tiles * (int64_t)x->S * x->W * kTile;
   x->G = 512;
+  x->Gf = 256;
+  x->no_fused = std::getenv("NBM_NO_FUSED") != nullptr;
   x->prepared_ws = nullptr;
   make_layout(x);
   *out = x;
@@ -346,6 +352,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   int64_t cut_here = std::min<int64_t>(ctx->cut_cap, n);
   int64_t slots = n + (2 + nbr) * cut_here + nb + 2 * kTile;
   int grid = (int)((slots + kTile - 1) / kTile + 2);
+  const bool fused = grad != nullptr && ctx->fused != nullptr && !ctx->no_fused;
   MlpCall mc;
   std::memset(&mc, 0, sizeof(mc));
   mc.op = MlpCall::FORWARD; mc.stream = st; mc.grid = grid; mc.meta = pc.meta;
@@ -353,7 +360,12 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   mc.outputs = at<float>(ws, Lo.outputs);
   mc.Zst = at<float>(ws, Lo.Zst); mc.Ast = at<void>(ws, Lo.Ast); mc.ALst = at<float>(ws, Lo.ALst);
   mc.dZ = at<float>(ws, Lo.dZ); mc.lstride = ctx->lstride;
-  mc.store = grad != nullptr; mc.streams = true;
+  mc.store = grad != nullptr && !fused; mc.streams = true;
+  if (fused) {
+    // forward only over the tiles that are not 16 uncut centres
+    mc.noninline = 1;
+    mc.grid = (int)(((2 + nbr) * cut_here + nb + kTile - 1) / kTile + 6);
+  }
   {
     Timer tf(ctx, st, 1);
     e = ctx->mlp(mc);
@@ -364,7 +376,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   Timer* tres = new Timer(ctx, st, 2);
   if (grad) {
     e = launch_fill(st, adj, (int64_t)grid * kTile * 8, 0.0f);
-    if (e != hipSuccess) return fail(NBM_EHIP, std::string("fill: ") + hipGetErrorString(e));
+    if (e != hipSuccess) { delete tres; return fail(NBM_EHIP, std::string("fill: ") + hipGetErrorString(e)); }
   }
   ResCall rc;
   std::memset(&rc, 0, sizeof(rc));
@@ -374,31 +386,53 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   rc.outputs = mc.outputs; rc.adj = adj;
   rc.resid = residual ? residual : at<float>(ws, Lo.resid);
   rc.lossp = at<double>(ws, Lo.lossp);
-  rc.loss = loss ? loss : at<double>(ws, Lo.lossbuf);
+  double* loss_out = loss ? loss : at<double>(ws, Lo.lossbuf);
+  rc.loss = fused ? nullptr : loss_out;
   rc.scale = 2.0 * dL / (double)(n + nb);
+  rc.skip_inline = fused ? 1 : 0;
   e = launch_residuals(rc);
   delete tres;
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("residual: ") + hipGetErrorString(e));
   if (!grad) return NBM_OK;
-  // backward through the hidden layers, gradient partials, FP64 reduction
-  mc.op = MlpCall::BACKWARD;
-  mc.grid = ctx->G;
-  mc.adj = adj;
-  mc.partial = at<float>(ws, Lo.partial);
-  mc.Ptot = ctx->Ptot;
-  mc.lay = &ctx->lay;
-  mc.off1 = ctx->per_net;
-  for (int l = ctx->L; l >= 2; --l) {
-    mc.l = l;
+  float* partial = at<float>(ws, Lo.partial);
+  int Grows = ctx->G;
+  if (fused) {
+    int nres = (int)((n + 255) / 256 + (cut_here + 255) / 256 + (nb + 255) / 256);
+    FusedCall fc;
+    std::memset(&fc, 0, sizeof(fc));
+    fc.stream = st; fc.grid = ctx->Gf; fc.meta = pc.meta; fc.centres = pc.centres; fc.src = pc.src;
+    fc.nets = &N; fc.P = P; fc.h = (float)ctx->cfg.h; fc.adj = adj; fc.resid = rc.resid;
+    fc.partial = partial; fc.Ptot = ctx->Ptot; fc.lay = &ctx->lay; fc.off1 = ctx->per_net;
+    fc.lossp = rc.lossp + nres; fc.scale = rc.scale;
     {
       Timer tb(ctx, st, 3);
-      e = ctx->mlp(mc);
+      e = ctx->fused(fc);
     }
-    if (e != hipSuccess) return fail(NBM_EHIP, std::string("backward: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return fail(NBM_EHIP, std::string("fused: ") + hipGetErrorString(e));
+    e = launch_reduce_loss(st, rc.lossp, nres + ctx->Gf, pc.meta, loss_out);
+    if (e != hipSuccess) return fail(NBM_EHIP, std::string("loss: ") + hipGetErrorString(e));
+    Grows = ctx->Gf;
+  } else {
+    // backward through the hidden layers, gradient partials
+    mc.op = MlpCall::BACKWARD;
+    mc.grid = ctx->G;
+    mc.adj = adj;
+    mc.partial = partial;
+    mc.Ptot = ctx->Ptot;
+    mc.lay = &ctx->lay;
+    mc.off1 = ctx->per_net;
+    for (int l = ctx->L; l >= 2; --l) {
+      mc.l = l;
+      {
+        Timer tb(ctx, st, 3);
+        e = ctx->mlp(mc);
+      }
+      if (e != hipSuccess) return fail(NBM_EHIP, std::string("backward: ") + hipGetErrorString(e));
+    }
   }
   {
     Timer tr(ctx, st, 4);
-    e = launch_reduce_grad(st, mc.partial, ctx->G, ctx->Ptot, grad, 1.0);
+    e = launch_reduce_grad(st, partial, Grows, ctx->Ptot, grad, 1.0);
   }
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("reduce: ") + hipGetErrorString(e));
   return NBM_OK;

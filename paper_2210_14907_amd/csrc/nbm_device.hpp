@@ -41,16 +41,82 @@ template <> __device__ __forceinline__ __bf16 from_f<__bf16>(float x) { return (
 // exact rewriting of evaluating the network at x and x +- h e_i; the forms
 // below avoid the cancellation of forming those differences from point values
 // (sum-to-product identities for sin, addition theorems for tanh).
+//
+// The difference arguments are O(h), so their sin / cos / tanh are evaluated
+// by truncated Taylor series where the argument is small (truncation error
+// below FP32 rounding) and by the general library function otherwise.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// sin x = x (1 - x^2/3! + x^4/5! - x^6/7! + x^8/9!), |x| <= pi/4: next term
+// x^11/11! < 2e-9
+__device__ __forceinline__ float sin_taylor(float x) {
+  float y = x * x;
+  float p = 1.0f / 362880.0f;
+  p = fmaf(p, y, -1.0f / 5040.0f);
+  p = fmaf(p, y, 1.0f / 120.0f);
+  p = fmaf(p, y, -1.0f / 6.0f);
+  p = fmaf(p, y, 1.0f);
+  return x * p;
+}
+// cos x = 1 - x^2/2! + ... - x^10/10!, |x| <= pi/4: next term < 2e-10
+__device__ __forceinline__ float cos_taylor(float x) {
+  float y = x * x;
+  float p = -1.0f / 3628800.0f;
+  p = fmaf(p, y, 1.0f / 40320.0f);
+  p = fmaf(p, y, -1.0f / 720.0f);
+  p = fmaf(p, y, 1.0f / 24.0f);
+  p = fmaf(p, y, -0.5f);
+  return fmaf(p, y, 1.0f);
+}
+// tanh x = x - x^3/3 + 2x^5/15 - 17x^7/315 + 62x^9/2835 - 1382x^11/155925
+//          + 21844x^13/6081075, |x| <= 0.4: next term < 2e-9 relative
+__device__ __forceinline__ float tanh_taylor(float x) {
+  float y = x * x;
+  float p = 21844.0f / 6081075.0f;
+  p = fmaf(p, y, -1382.0f / 155925.0f);
+  p = fmaf(p, y, 62.0f / 2835.0f);
+  p = fmaf(p, y, -17.0f / 315.0f);
+  p = fmaf(p, y, 2.0f / 15.0f);
+  p = fmaf(p, y, -1.0f / 3.0f);
+  p = fmaf(p, y, 1.0f);
+  return x * p;
+}
+
+constexpr float kSmallTrig = 0.78539816f;   // pi / 4
+constexpr float kSmallTanh = 0.4f;
+
+__device__ __forceinline__ void sincos_small(float x, float* s, float* c) {
+  if (fabsf(x) <= kSmallTrig) {
+    *s = sin_taylor(x);
+    *c = cos_taylor(x);
+  } else {
+    sincosf(x, s, c);
+  }
+}
+__device__ __forceinline__ float sin_small(float x) {
+  return fabsf(x) <= kSmallTrig ? sin_taylor(x) : sinf(x);
+}
+__device__ __forceinline__ float tanh_small(float x) {
+  return fabsf(x) <= kSmallTanh ? tanh_taylor(x) : tanhf(x);
+}
+
 struct TanhBase { float t, q; };   // t = tanh z, q = 1 - t^2
 
 __device__ __forceinline__ TanhBase tanh_base(float z) {
   float az = fabsf(z);
-  float ez = expf(-2.0f * az);
-  float em1 = expm1f(-2.0f * az);
-  float t = -em1 / (1.0f + ez);
-  t = z < 0.0f ? -t : t;
-  float q = 4.0f * ez / ((1.0f + ez) * (1.0f + ez));
+  float t, q;
+  if (az <= kSmallTanh) {
+    t = tanh_taylor(z);
+    q = (1.0f - t) * (1.0f + t);
+  } else {
+    // t = (1 - e) / (1 + e), q = 4 e / (1 + e)^2 with e = exp(-2|z|)
+    float ez = expf(-2.0f * az);
+    float r = rcp(1.0f + ez);
+    t = (1.0f - ez) * r;
+    t = z < 0.0f ? -t : t;
+    q = 4.0f * ez * r * r;
+  }
   return {t, q};
 }
 
@@ -72,9 +138,9 @@ __device__ __forceinline__ void act_fwd(float z, const float* p, const float* e,
     for (int i = 0; i < D; ++i) {
       float hp = 0.5f * p[i], m = p[i] - e[i], hm = 0.5f * m, he = 0.5f * e[i];
       float sp, cp, sm, cm;
-      sincosf(hp, &sp, &cp);
-      sincosf(hm, &sm, &cm);
-      float se = sinf(he);
+      sincos_small(hp, &sp, &cp);
+      sincos_small(hm, &sm, &cm);
+      float se = sin_small(he);
       float cs2 = cp * cm - sp * sm;  // cos((p+m)/2)
       Dv[i] = 2.0f * sp * (C * cp - S * sp);
       Ev[i] = -2.0f * S * (sp * sp + sm * sm) + 2.0f * C * cs2 * se;
@@ -86,10 +152,11 @@ __device__ __forceinline__ void act_fwd(float z, const float* p, const float* e,
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       float m = p[i] - e[i];
-      float Tp = tanhf(p[i]), Tm = tanhf(m), Te = tanhf(e[i]), Ts = tanhf(p[i] + m);
-      float P = 1.0f + t * Tp, M = 1.0f - t * Tm;
-      Dv[i] = Tp * q / P;
-      Ev[i] = (q / P) * (Te * (1.0f - Tp * Tm) - t * Tm * Ts * (1.0f + Tp * Tm) / M);
+      float Tp = tanh_small(p[i]), Tm = tanh_small(m), Te = tanh_small(e[i]), Ts = tanh_small(p[i] + m);
+      float rP = rcp(1.0f + t * Tp), rM = rcp(1.0f - t * Tm);
+      float qP = q * rP;
+      Dv[i] = Tp * qP;
+      Ev[i] = qP * (Te * (1.0f - Tp * Tm) - t * Tm * Ts * (1.0f + Tp * Tm) * rM);
     }
   }
 }
@@ -107,9 +174,9 @@ __device__ __forceinline__ void act_bwd(float z, const float* p, const float* e,
     for (int i = 0; i < D; ++i) {
       float hp = 0.5f * p[i], m = p[i] - e[i], hm = 0.5f * m, he = 0.5f * e[i];
       float sp, cp, sm, cm, se, ce;
-      sincosf(hp, &sp, &cp);
-      sincosf(hm, &sm, &cm);
-      sincosf(he, &se, &ce);
+      sincos_small(hp, &sp, &cp);
+      sincos_small(hm, &sm, &cm);
+      sincos_small(he, &se, &ce);
       float cs2 = cp * cm - sp * sm;        // cos(s/2), s = p + m
       float ss2 = sp * cm + cp * sm;        // sin(s/2)
       float sq = sp * sp + sm * sm;
@@ -129,16 +196,17 @@ __device__ __forceinline__ void act_bwd(float z, const float* p, const float* e,
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       float m = p[i] - e[i];
-      float Tp = tanhf(p[i]), Tm = tanhf(m), Te = tanhf(e[i]), Ts = tanhf(p[i] + m);
-      float P = 1.0f + t * Tp, M = 1.0f - t * Tm;
-      float Dd = Tp * q / P;
-      float Bd = Tm * q / M;
-      float Ed = (q / P) * (Te * (1.0f - Tp * Tm) - t * Tm * Ts * (1.0f + Tp * Tm) / M);
+      float Tp = tanh_small(p[i]), Tm = tanh_small(m), Te = tanh_small(e[i]), Ts = tanh_small(p[i] + m);
+      float rP = rcp(1.0f + t * Tp), rM = rcp(1.0f - t * Tm);
+      float qP = q * rP, qM = q * rM;
+      float Dd = Tp * qP;
+      float Bd = Tm * qM;
+      float Ed = qP * (Te * (1.0f - Tp * Tm) - t * Tm * Ts * (1.0f + Tp * Tm) * rM);
       float dDdz = -Dd * (2.0f * t + Dd);
-      float dDdp = q * (1.0f - Tp * Tp) / (P * P);
+      float dDdp = qP * (1.0f - Tp * Tp) * rP;
       float dEdz = -2.0f * t * Ed - Dd * Dd - Bd * Bd;
       float dEdp = -(Dd + Bd) * (2.0f * t + Ed);
-      float dEde = q * (1.0f - Tm * Tm) / (M * M);
+      float dEde = qM * (1.0f - Tm * Tm) * rM;
       zb += Db[i] * dDdz + Eb[i] * dEdz;
       pb[i] = Db[i] * dDdp + Eb[i] * dEdp;
       eb[i] = Eb[i] * dEde;

@@ -345,14 +345,18 @@ template <int D>
 __global__ __launch_bounds__(256) void k_res_uncut(Problem P, const Meta* meta, const float* pts,
                                                    int64_t n, const int* cls, const int* rank,
                                                    const float* outputs, float* adj, float* resid,
-                                                   double* lossp, double scale) {
+                                                   double* lossp, double scale, int skip_inline) {
   __shared__ double sh[256];
   int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double r2 = 0.0;
   if (i < n) {
     int c = cls[i];
+    int64_t slot = c < 2 ? meta->base[c][KIND_A] + rank[i] : 0;
+    if (c < 2 && skip_inline) {
+      int64_t a_end = (int64_t)meta->base[c][KIND_A] + meta->cnt[c][KIND_A];
+      if ((slot / kTile) * kTile + kTile <= a_end) c = 3;   // handled by the fused kernel
+    }
     if (c < 2) {
-      int64_t slot = meta->base[c][KIND_A] + rank[i];
       float x[3] = {0, 0, 0};
       for (int a = 0; a < D; ++a) x[a] = pts[i * D + a];
       float hh = (float)(P.h * P.h);
@@ -521,14 +525,24 @@ __device__ inline int tile_net(const Meta* m, int t) {
 template <int D, int W, int S, int ACT, int PREC, bool STORE>
 __global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4* centres, Nets nets,
                                                  int L, float h, float* outputs, float* Zst,
-                                                 void* Ast_, float* ALst, int64_t lstride) {
+                                                 void* Ast_, float* ALst, int64_t lstride,
+                                                 int noninline) {
   typedef typename Op<PREC>::T T;
   constexpr int LD = W + Pad<PREC>::v;
   constexpr int NOB = W / 16;
   constexpr int KC = W / 4;  // K chunk per lane group
   __shared__ __attribute__((aligned(16))) T buf[2][S][kTile][LD];
   __shared__ float part[4][kTile][8];
-  const int t = blockIdx.x;
+  int t = blockIdx.x;
+  if (noninline) {
+    // only tiles that are not 16 uncut centres (the fused kernel forms the
+    // residual of those itself)
+    int inl0 = meta->cnt[0][KIND_A] / kTile, inl1 = meta->cnt[1][KIND_A] / kTile;
+    int n0 = meta->tiles[0] - inl0, n1 = meta->tiles[1] - inl1;
+    if (t < n0) t = meta->tile0[0] + inl0 + t;
+    else if (t < n0 + n1) t = meta->tile0[1] + inl1 + (t - n0);
+    else return;
+  }
   const int net = tile_net(meta, t);
   if (net < 0) return;
   const NetPtrs& np = nets.net[net];
@@ -920,16 +934,16 @@ template <int D, int W, int ACT, int PREC>
 struct Launch {
   static hipError_t forward(hipStream_t st, int grid, const Meta* meta, const float4* centres,
                             const Nets& nets, int L, float h, float* outputs, float* Zst, void* Ast,
-                            float* ALst, int64_t lstride, bool store, bool streams) {
+                            float* ALst, int64_t lstride, bool store, bool streams, int noninline) {
     if (streams && store)
       hipLaunchKernelGGL((k_forward<D, W, 2 * D + 1, ACT, PREC, true>), dim3(grid), dim3(256), 0, st,
-                         meta, centres, nets, L, h, outputs, Zst, Ast, ALst, lstride);
+                         meta, centres, nets, L, h, outputs, Zst, Ast, ALst, lstride, noninline);
     else if (streams)
       hipLaunchKernelGGL((k_forward<D, W, 2 * D + 1, ACT, PREC, false>), dim3(grid), dim3(256), 0, st,
-                         meta, centres, nets, L, h, outputs, Zst, Ast, ALst, lstride);
+                         meta, centres, nets, L, h, outputs, Zst, Ast, ALst, lstride, noninline);
     else
       hipLaunchKernelGGL((k_forward<D, W, 1, ACT, PREC, false>), dim3(grid), dim3(256), 0, st, meta,
-                         centres, nets, L, h, outputs, Zst, Ast, ALst, lstride);
+                         centres, nets, L, h, outputs, Zst, Ast, ALst, lstride, noninline);
     return hipGetLastError();
   }
   static hipError_t backward(hipStream_t st, int G, const Meta* meta, const float4* centres,
@@ -961,7 +975,7 @@ hipError_t dispatch_impl(const MlpCall& c) {
   if (c.op == MlpCall::FORWARD)
     return Launch<D, W, ACT, PREC>::forward(c.stream, c.grid, c.meta, c.centres, *c.nets, c.L, c.h,
                                             c.outputs, c.Zst, c.Ast, c.ALst, c.lstride, c.store,
-                                            c.streams);
+                                            c.streams, c.noninline);
   return Launch<D, W, ACT, PREC>::backward(c.stream, c.grid, c.meta, c.centres, *c.nets, c.L, c.l,
                                            c.h, c.adj, c.Zst, c.Ast, c.ALst, c.dZ, c.partial, c.Ptot,
                                            *c.lay, c.off1, c.lstride);
@@ -1016,18 +1030,24 @@ hipError_t launch_residuals(const ResCall& c) {
   int64_t nblk = (c.n + 255) / 256, nblkb = (c.nb + 255) / 256, nblkc = (c.cut_cap + 255) / 256;
   double* lp = c.lossp;
   if (c.P.dim == 2) {
-    if (c.n) hipLaunchKernelGGL(k_res_uncut<2>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale);
+    if (c.n) hipLaunchKernelGGL(k_res_uncut<2>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale, c.skip_inline);
     if (c.n) hipLaunchKernelGGL(k_res_cut<2>, dim3(nblkc), dim3(256), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale);
     if (c.nb) hipLaunchKernelGGL(k_res_bnd<2>, dim3(nblkb), dim3(256), 0, st, c.P, c.meta, c.bpts, c.nb, c.bcls, c.brank, c.outputs, c.adj, c.resid + c.n, lp + nblk + nblkc, c.scale);
   } else {
-    if (c.n) hipLaunchKernelGGL(k_res_uncut<3>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale);
+    if (c.n) hipLaunchKernelGGL(k_res_uncut<3>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale, c.skip_inline);
     if (c.n) hipLaunchKernelGGL(k_res_cut<3>, dim3(nblkc), dim3(256), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale);
     if (c.nb) hipLaunchKernelGGL(k_res_bnd<3>, dim3(nblkb), dim3(256), 0, st, c.P, c.meta, c.bpts, c.nb, c.bcls, c.brank, c.outputs, c.adj, c.resid + c.n, lp + nblk + nblkc, c.scale);
   }
-  int nparts = (int)(nblk + nblkc + nblkb);
-  if (c.n == 0) nparts = (int)nblkb, lp = c.lossp + nblk + nblkc;
-  if (c.nb == 0 && c.n != 0) nparts = (int)(nblk + nblkc);
-  if (c.loss) hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(256), 0, st, lp, nparts, c.meta, c.loss);
+  if (c.loss) {
+    int nparts = (int)(nblk + nblkc + nblkb) + c.extra_parts;
+    hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(256), 0, st, c.lossp, nparts, c.meta, c.loss);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_loss(hipStream_t st, const double* lossp, int nparts, const Meta* meta,
+                              double* loss) {
+  hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(256), 0, st, lossp, nparts, meta, loss);
   return hipGetLastError();
 }
 

@@ -27,9 +27,31 @@ struct MlpCall {
   int64_t off1;
   int64_t lstride;
   bool store, streams;
+  int noninline;
 };
 typedef hipError_t (*MlpFn)(const MlpCall&);
 MlpFn find_mlp(int dim, int width, int act, int prec);
+
+struct FusedCall {
+  hipStream_t stream;
+  int grid;
+  const Meta* meta;
+  const float4* centres;
+  const int* src;
+  const Nets* nets;
+  Problem P;
+  float h;
+  const float* adj;
+  float* resid;
+  float* partial;
+  int64_t Ptot;
+  const NetLayout* lay;
+  int64_t off1;
+  double* lossp;
+  double scale;
+};
+typedef hipError_t (*FusedFn)(const FusedCall&);
+FusedFn find_fused(int dim, int width, int depth, int act, int prec);
 
 struct PrepCall {
   hipStream_t stream;
@@ -67,8 +89,12 @@ struct ResCall {
   double* lossp;
   double* loss;
   double scale;
+  int skip_inline;
+  int extra_parts;   // loss partials appended after the residual kernels' ones
 };
 hipError_t launch_residuals(const ResCall& c);
+hipError_t launch_reduce_loss(hipStream_t st, const double* lossp, int nparts, const Meta* meta,
+                              double* loss);
 
 hipError_t launch_fill(hipStream_t st, float* p, int64_t n, float v);
 hipError_t launch_shadow(hipStream_t st, int prec, const float* params, int64_t off, int W, void* Wl,
