@@ -157,6 +157,9 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--workload", default="c2", help="c2 (default, the headline line) or c1/c3/c4 for profiling")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the data-parallel path across GPUs is not part of "
@@ -165,7 +168,15 @@ def main():
     import torch
     import nbm_inputs as I
 
-    wl = I.C2
+    wl = I.WORKLOADS[args.workload]
+    if args.calib_copy_mb:
+        nbytes = args.calib_copy_mb << 20
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     res = run_workload(wl, args.steps, args.warmup, train_to=0 if args.no_accuracy else wl.steps)
     n_step = wl.n_points
     value = n_step / (res["ms_per_step"] * 1e-3)
@@ -193,17 +204,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if wl.prec == I.PREC_FP32 else "bf16",
         "data": "synthetic (Philox lattice points, manufactured sphere solution, Xavier init seed 0)",
         "config": {"workload": wl.name, "n_points": wl.n_points, "n_boundary": wl.n_boundary,
-                   "h": wl.h, "net": f"2 x {wl.dim}->{wl.width}x{wl.depth}->1 tanh", "mu": [1, 10]},
+                   "h": wl.h, "net": f"2 x {wl.dim}->{wl.width}x{wl.depth}->1 {'tanh' if wl.act == I.ACT_TANH else 'sin'}",
+                   "mu": [wl.mu_minus, wl.mu_plus]},
         "fwd_res_bwd_pts_per_s": round(n_step / (res["ms_fwd_res_bwd"] * 1e-3), 1),
         "kernel_ms_per_step": {k: round(v[0] / max(1, tm["forward"][1]), 4) for k, v in tm.items() if v[1]},
         "roofline": {"bound": "mfma", "kernel": name, "achieved": achieved / 1e12,
                      "peak": PEAK[dtype] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[dtype],
                      "traffic": None, "flop_per_launch": per_launch, "avg_launch_ms": avg},
     }
-    if not args.no_accuracy:
+    if not args.no_accuracy and wl.problem != I.PROB_FOURIER:
         acc = accuracy(wl, res, 64)
         acc["steps_trained"] = res["steps_trained"]
         acc["final_loss"] = res["final_loss"]

@@ -30,7 +30,7 @@ static int fail(int code, const std::string& msg) {
 namespace {
 struct Layout {
   size_t modes32, modes64, meta, blockcnt, off, blockcnt_b, off_b, cls, rank, bcls, brank, cutidx,
-      centres, src, outputs, adj, Zst, Ast, ALst, dZ, shadow, partial, lossp, resid, lossbuf, total;
+      centres, src, outputs, adj, Zst, Ast, ALst, dZ, dZw, shadow, partial, lossp, resid, lossbuf, total;
 };
 }  // namespace
 
@@ -49,6 +49,7 @@ struct nbm_ctx {
   Problem P;
   MlpFn mlp;
   FusedFn fused;
+  WideFn wide;
   int D, W, L, S, opbytes;
   int64_t per_net, Ptot;
   NetLayout lay;
@@ -105,13 +106,17 @@ static void make_layout(nbm_ctx* c) {
   L.src = take(sizeof(int) * c->cap_slots);
   L.outputs = take(sizeof(float) * 8 * c->cap_slots);
   L.adj = take(sizeof(float) * 8 * c->cap_slots);
-  L.Zst = take(sizeof(float) * c->L * c->lstride);
+  // stored pre-activations are needed only by the layered backward, used when
+  // no fused path is compiled for the shape (or NBM_NO_FUSED is set)
+  const bool layered = c->no_fused || (!c->fused && !c->wide);
+  L.Zst = take(layered ? sizeof(float) * c->L * c->lstride : 0);
   L.Ast = take((size_t)c->opbytes * (c->L - 1) * c->lstride);
-  L.ALst = take(sizeof(float) * c->lstride);
-  L.dZ = take(sizeof(float) * c->lstride);
+  L.ALst = take(layered ? sizeof(float) * c->lstride : 0);
+  L.dZ = take(layered ? sizeof(float) * c->lstride : 0);
+  L.dZw = take(c->wide && !c->no_fused ? (size_t)c->opbytes * (c->L - 1) * c->lstride : 0);
   L.shadow = take((size_t)c->opbytes * 2 * (c->L - 1) * 2 * c->W * c->W);
   L.partial = take(sizeof(float) * (size_t)c->G * c->Ptot);
-  L.lossp = take(sizeof(double) * (nblk + nblkb + nblkc + 4 + 512));
+  L.lossp = take(sizeof(double) * (nblk + nblkb + c->cut_cap + 4 + 512));
   L.resid = take(sizeof(float) * (c->cap_n + c->cap_nb));
   L.lossbuf = take(sizeof(double) * 4);
   L.total = o;
@@ -158,6 +163,8 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
   x->cfg.mode_a = x->cfg.mode_b = nullptr;
   x->mlp = fn;
   x->fused = find_fused(c.dim, c.width, c.depth, c.act, c.prec);
+  x->wide = find_wide(c.dim, c.width, c.depth, c.act, c.prec);
+  x->no_fused = std::getenv("NBM_NO_FUSED") != nullptr;
   x->D = c.dim; x->W = c.width; x->L = c.depth; x->S = 2 * c.dim + 1;
   x->opbytes = c.prec == NBM_PREC_BF16 ? 2 : 4;
   // parameter layout of one net
@@ -212,7 +219,6 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
   x->lstride = x->cap_tiles * (int64_t)x->S * x->W * kTile;
   x->G = 512;
   x->Gf = 256;
-  x->no_fused = std::getenv("NBM_NO_FUSED") != nullptr;
   x->prepared_ws = nullptr;
   make_layout(x);
   *out = x;
@@ -352,7 +358,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   int64_t cut_here = std::min<int64_t>(ctx->cut_cap, n);
   int64_t slots = n + (2 + nbr) * cut_here + nb + 2 * kTile;
   int grid = (int)((slots + kTile - 1) / kTile + 2);
-  const bool fused = grad != nullptr && ctx->fused != nullptr && !ctx->no_fused;
+  const bool fused = grad != nullptr && (ctx->fused != nullptr || ctx->wide != nullptr) && !ctx->no_fused;
   MlpCall mc;
   std::memset(&mc, 0, sizeof(mc));
   mc.op = MlpCall::FORWARD; mc.stream = st; mc.grid = grid; mc.meta = pc.meta;
@@ -396,8 +402,25 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   if (!grad) return NBM_OK;
   float* partial = at<float>(ws, Lo.partial);
   int Grows = ctx->G;
-  if (fused) {
-    int nres = (int)((n + 255) / 256 + (cut_here + 255) / 256 + (nb + 255) / 256);
+  if (fused && ctx->wide) {
+    int nres = (int)((n + 255) / 256 + (n ? cut_here : 0) + (nb + 255) / 256);
+    WideCall wc;
+    std::memset(&wc, 0, sizeof(wc));
+    wc.stream = st; wc.grid = ctx->Gf; wc.meta = pc.meta; wc.centres = pc.centres; wc.src = pc.src;
+    wc.nets = &N; wc.P = P; wc.h = (float)ctx->cfg.h; wc.adj = adj; wc.resid = rc.resid;
+    wc.A = at<void>(ws, Lo.Ast); wc.dZ = at<void>(ws, Lo.dZw); wc.lstride = ctx->lstride;
+    wc.partial = partial; wc.Ptot = ctx->Ptot; wc.lay = &ctx->lay; wc.off1 = ctx->per_net;
+    wc.lossp = rc.lossp + nres; wc.scale = rc.scale;
+    {
+      Timer tb(ctx, st, 3);
+      e = ctx->wide(wc);
+    }
+    if (e != hipSuccess) return fail(NBM_EHIP, std::string("wide: ") + hipGetErrorString(e));
+    e = launch_reduce_loss(st, rc.lossp, nres + ctx->Gf, pc.meta, loss_out);
+    if (e != hipSuccess) return fail(NBM_EHIP, std::string("loss: ") + hipGetErrorString(e));
+    Grows = ctx->Gf;
+  } else if (fused) {
+    int nres = (int)((n + 255) / 256 + (n ? cut_here : 0) + (nb + 255) / 256);
     FusedCall fc;
     std::memset(&fc, 0, sizeof(fc));
     fc.stream = st; fc.grid = ctx->Gf; fc.meta = pc.meta; fc.centres = pc.centres; fc.src = pc.src;

@@ -103,20 +103,15 @@ __device__ __forceinline__ float tanh_small(float x) {
 
 struct TanhBase { float t, q; };   // t = tanh z, q = 1 - t^2
 
+// t = (1 - e) / (1 + e), q = 4 e / (1 + e)^2 with e = exp(-2|z|): branch free;
+// t carries an absolute (not relative) error of a few ulp of 1 near z = 0,
+// which is the accuracy every stream formula below needs
 __device__ __forceinline__ TanhBase tanh_base(float z) {
-  float az = fabsf(z);
-  float t, q;
-  if (az <= kSmallTanh) {
-    t = tanh_taylor(z);
-    q = (1.0f - t) * (1.0f + t);
-  } else {
-    // t = (1 - e) / (1 + e), q = 4 e / (1 + e)^2 with e = exp(-2|z|)
-    float ez = expf(-2.0f * az);
-    float r = rcp(1.0f + ez);
-    t = (1.0f - ez) * r;
-    t = z < 0.0f ? -t : t;
-    q = 4.0f * ez * r * r;
-  }
+  float ez = __expf(-2.0f * fabsf(z));
+  float r = rcp(1.0f + ez);
+  float t = (1.0f - ez) * r;
+  t = z < 0.0f ? -t : t;
+  float q = 4.0f * ez * r * r;
   return {t, q};
 }
 
@@ -126,24 +121,93 @@ __device__ __forceinline__ float act_base(float z) {
   return sinf(z);
 }
 
-// forward: base a, and per-axis D, E from (z, p, e)
+// Short series for the second-difference argument e = O(h^2):
+// sin e = e (1 - e^2/6 + e^4/120), cos e = 1 - e^2/2 + e^4/24,
+// tanh e = e (1 - e^2/3 + 2 e^4/15); |e| <= 1/32: next terms < 1e-11 relative.
+constexpr float kTinyArg = 0.03125f;
+__device__ __forceinline__ float sin_short(float e) {
+  float y = e * e;
+  return e * fmaf(fmaf(y, 1.0f / 120.0f, -1.0f / 6.0f), y, 1.0f);
+}
+__device__ __forceinline__ float cos_short(float e) {
+  float y = e * e;
+  return fmaf(fmaf(y, 1.0f / 24.0f, -0.5f), y, 1.0f);
+}
+__device__ __forceinline__ float tanh_short(float e) {
+  float y = e * e;
+  return e * fmaf(fmaf(y, 2.0f / 15.0f, -1.0f / 3.0f), y, 1.0f);
+}
+
+// Per-axis trigonometric factors of the sin streams.  Fast path (whole
+// wavefront has |p|/2 <= pi/4 and |e| <= 1/32): Taylor series for p/2, short
+// series for e/2, and the half-angle m/2 = p/2 - e/2 by the addition theorem.
+struct SinAxis { float sp, cp, sm, cm, se, ce; };
+
+template <bool FAST>
+__device__ __forceinline__ SinAxis sin_axis(float p, float e) {
+  SinAxis r;
+  float hp = 0.5f * p, he = 0.5f * e;
+  if (FAST) {
+    r.sp = sin_taylor(hp);
+    r.cp = cos_taylor(hp);
+    r.se = sin_short(he);
+    r.ce = cos_short(he);
+    r.sm = r.sp * r.ce - r.cp * r.se;   // sin(p/2 - e/2)
+    r.cm = r.cp * r.ce + r.sp * r.se;   // cos(p/2 - e/2)
+  } else {
+    float hm = 0.5f * (p - e);
+    sincos_small(hp, &r.sp, &r.cp);
+    sincos_small(hm, &r.sm, &r.cm);
+    sincos_small(he, &r.se, &r.ce);
+  }
+  return r;
+}
+
+// Per-axis tanh factors: T_p, T_m, T_e, T_s with m = p - e, s = p + m.
+struct TanhAxis { float Tp, Tm, Te, Ts; };
+
+template <bool FAST>
+__device__ __forceinline__ TanhAxis tanh_axis(float p, float e) {
+  TanhAxis r;
+  float m = p - e;
+  if (FAST) {
+    r.Tp = tanh_taylor(p);
+    r.Tm = tanh_taylor(m);
+    r.Ts = tanh_taylor(p + m);
+    r.Te = tanh_short(e);
+  } else {
+    r.Tp = tanh_small(p);
+    r.Tm = tanh_small(m);
+    r.Te = tanh_small(e);
+    r.Ts = tanh_small(p + m);
+  }
+  return r;
+}
+
 template <int ACT, int D>
-__device__ __forceinline__ void act_fwd(float z, const float* p, const float* e, float& a,
-                                        float* Dv, float* Ev) {
+__device__ __forceinline__ bool fast_args(const float* p, const float* e) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    if (ACT == 1) ok = ok && fabsf(p[i]) <= 2.0f * kSmallTrig && fabsf(e[i]) <= kTinyArg;
+    else ok = ok && fabsf(p[i]) <= 0.5f * kSmallTanh && fabsf(e[i]) <= kTinyArg;
+  }
+  return ok;
+}
+
+template <int ACT, int D, bool FAST>
+__device__ __forceinline__ void act_fwd_impl(float z, const float* p, const float* e, float& a,
+                                             float* Dv, float* Ev) {
   if (ACT == 1) {
     float S, C;
     sincosf(z, &S, &C);
     a = S;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      float hp = 0.5f * p[i], m = p[i] - e[i], hm = 0.5f * m, he = 0.5f * e[i];
-      float sp, cp, sm, cm;
-      sincos_small(hp, &sp, &cp);
-      sincos_small(hm, &sm, &cm);
-      float se = sin_small(he);
-      float cs2 = cp * cm - sp * sm;  // cos((p+m)/2)
-      Dv[i] = 2.0f * sp * (C * cp - S * sp);
-      Ev[i] = -2.0f * S * (sp * sp + sm * sm) + 2.0f * C * cs2 * se;
+      SinAxis f = sin_axis<FAST>(p[i], e[i]);
+      float cs2 = f.cp * f.cm - f.sp * f.sm;  // cos((p+m)/2)
+      Dv[i] = 2.0f * f.sp * (C * f.cp - S * f.sp);
+      Ev[i] = -2.0f * S * (f.sp * f.sp + f.sm * f.sm) + 2.0f * C * cs2 * f.se;
     }
   } else {
     TanhBase tb = tanh_base(z);
@@ -151,32 +215,27 @@ __device__ __forceinline__ void act_fwd(float z, const float* p, const float* e,
     a = t;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      float m = p[i] - e[i];
-      float Tp = tanh_small(p[i]), Tm = tanh_small(m), Te = tanh_small(e[i]), Ts = tanh_small(p[i] + m);
-      float rP = rcp(1.0f + t * Tp), rM = rcp(1.0f - t * Tm);
+      TanhAxis f = tanh_axis<FAST>(p[i], e[i]);
+      float rP = rcp(1.0f + t * f.Tp), rM = rcp(1.0f - t * f.Tm);
       float qP = q * rP;
-      Dv[i] = Tp * qP;
-      Ev[i] = qP * (Te * (1.0f - Tp * Tm) - t * Tm * Ts * (1.0f + Tp * Tm) * rM);
+      Dv[i] = f.Tp * qP;
+      Ev[i] = qP * (f.Te * (1.0f - f.Tp * f.Tm) - t * f.Tm * f.Ts * (1.0f + f.Tp * f.Tm) * rM);
     }
   }
 }
 
-// backward: given stream adjoints (ab, Db, Eb) return (zb, pb, eb)
-template <int ACT, int D>
-__device__ __forceinline__ void act_bwd(float z, const float* p, const float* e, float ab,
-                                        const float* Db, const float* Eb, float& zb, float* pb,
-                                        float* eb) {
+template <int ACT, int D, bool FAST>
+__device__ __forceinline__ void act_bwd_impl(float z, const float* p, const float* e, float ab,
+                                             const float* Db, const float* Eb, float& zb, float* pb,
+                                             float* eb) {
   if (ACT == 1) {
     float S, C;
     sincosf(z, &S, &C);
     zb = ab * C;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      float hp = 0.5f * p[i], m = p[i] - e[i], hm = 0.5f * m, he = 0.5f * e[i];
-      float sp, cp, sm, cm, se, ce;
-      sincos_small(hp, &sp, &cp);
-      sincos_small(hm, &sm, &cm);
-      sincos_small(he, &se, &ce);
+      SinAxis f = sin_axis<FAST>(p[i], e[i]);
+      float sp = f.sp, cp = f.cp, sm = f.sm, cm = f.cm, se = f.se, ce = f.ce;
       float cs2 = cp * cm - sp * sm;        // cos(s/2), s = p + m
       float ss2 = sp * cm + cp * sm;        // sin(s/2)
       float sq = sp * sp + sm * sm;
@@ -195,13 +254,13 @@ __device__ __forceinline__ void act_bwd(float z, const float* p, const float* e,
     zb = ab * q;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      float m = p[i] - e[i];
-      float Tp = tanh_small(p[i]), Tm = tanh_small(m), Te = tanh_small(e[i]), Ts = tanh_small(p[i] + m);
+      TanhAxis f = tanh_axis<FAST>(p[i], e[i]);
+      float Tp = f.Tp, Tm = f.Tm;
       float rP = rcp(1.0f + t * Tp), rM = rcp(1.0f - t * Tm);
       float qP = q * rP, qM = q * rM;
       float Dd = Tp * qP;
       float Bd = Tm * qM;
-      float Ed = qP * (Te * (1.0f - Tp * Tm) - t * Tm * Ts * (1.0f + Tp * Tm) * rM);
+      float Ed = qP * (f.Te * (1.0f - Tp * Tm) - t * Tm * f.Ts * (1.0f + Tp * Tm) * rM);
       float dDdz = -Dd * (2.0f * t + Dd);
       float dDdp = qP * (1.0f - Tp * Tp) * rP;
       float dEdz = -2.0f * t * Ed - Dd * Dd - Bd * Bd;
@@ -212,6 +271,38 @@ __device__ __forceinline__ void act_bwd(float z, const float* p, const float* e,
       eb[i] = Eb[i] * dEde;
     }
   }
+}
+
+// general paths kept out of line: taken only when some lane has a large
+// difference argument (coarse h), so the common path stays register-lean
+template <int ACT, int D>
+__device__ __attribute__((noinline)) void act_fwd_general(float z, const float* p, const float* e,
+                                                          float& a, float* Dv, float* Ev) {
+  act_fwd_impl<ACT, D, false>(z, p, e, a, Dv, Ev);
+}
+template <int ACT, int D>
+__device__ __attribute__((noinline)) void act_bwd_general(float z, const float* p, const float* e,
+                                                          float ab, const float* Db, const float* Eb,
+                                                          float& zb, float* pb, float* eb) {
+  act_bwd_impl<ACT, D, false>(z, p, e, ab, Db, Eb, zb, pb, eb);
+}
+
+// forward: base a, and per-axis D, E from (z, p, e).  One wave-uniform
+// branch picks the series path when every lane's arguments are small.
+template <int ACT, int D>
+__device__ __forceinline__ void act_fwd(float z, const float* p, const float* e, float& a,
+                                        float* Dv, float* Ev) {
+  if (__all(fast_args<ACT, D>(p, e))) act_fwd_impl<ACT, D, true>(z, p, e, a, Dv, Ev);
+  else act_fwd_general<ACT, D>(z, p, e, a, Dv, Ev);
+}
+
+// backward: given stream adjoints (ab, Db, Eb) return (zb, pb, eb)
+template <int ACT, int D>
+__device__ __forceinline__ void act_bwd(float z, const float* p, const float* e, float ab,
+                                        const float* Db, const float* Eb, float& zb, float* pb,
+                                        float* eb) {
+  if (__all(fast_args<ACT, D>(p, e))) act_bwd_impl<ACT, D, true>(z, p, e, ab, Db, Eb, zb, pb, eb);
+  else act_bwd_general<ACT, D>(z, p, e, ab, Db, Eb, zb, pb, eb);
 }
 
 // ---------------------------------------------------------------------------

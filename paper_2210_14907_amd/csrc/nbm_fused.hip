@@ -206,38 +206,13 @@ __global__ __launch_bounds__(256) void k_fused(const Meta* meta, const float4* c
       if (tid == 0)
         for (int c = 0; c < kTile; ++c) accbo += adjs[c][0];
 
-      // ---------------- backward through the hidden layers
+      // ---------------- backward through the hidden layers.  Per layer: dZ_l
+      // goes to LDS in row layout, dA = dZ_l W_l runs on MFMA, then the dW_l
+      // MFMAs (independent of dA) are issued next to the VALU derivative
+      // epilogue of layer l-1 so that the two can overlap.
 #pragma unroll
       for (int l = L; l >= 2; --l) {
         for (int j = 0; j < 4; ++j) accb[l - 1] += dz[0][j];
-        // dW_l[n][:] += sum over (stream, centre) of dZ_l[.][n] A_{l-1}[.][:]
-        for (int ib = 0; ib < NOB; ++ib) {
-          const int nin = ib * 16 + r16;
-          if constexpr (PREC == 0) {
-            for (int s = 0; s < S; ++s) {
-              float4 v = *(const float4*)(&colA[l - 2][s][nin][4 * g]);
-              accW[l - 2][ib] = mfma4(dz[s][0], v.x, accW[l - 2][ib]);
-              accW[l - 2][ib] = mfma4(dz[s][1], v.y, accW[l - 2][ib]);
-              accW[l - 2][ib] = mfma4(dz[s][2], v.z, accW[l - 2][ib]);
-              accW[l - 2][ib] = mfma4(dz[s][3], v.w, accW[l - 2][ib]);
-            }
-          } else {
-            for (int s = 0; s < S; s += 2) {
-              bf4 v0 = *(const bf4*)(&colA[l - 2][s][nin][4 * g]);
-              bf4 v1 = (s + 1 < S) ? *(const bf4*)(&colA[l - 2][s + 1][nin][4 * g])
-                                   : bf4{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
-              bf8 av, bv;
-              for (int j = 0; j < 4; ++j) {
-                av[j] = (__bf16)dz[s][j];
-                av[4 + j] = (s + 1 < S) ? (__bf16)dz[s + 1][j] : (__bf16)0.f;
-                bv[j] = v0[j];
-                bv[4 + j] = v1[j];
-              }
-              accW[l - 2][ib] = mfma32(av, bv, accW[l - 2][ib]);
-            }
-          }
-        }
-        // dA: abar_{l-1}[c][n'] = sum_k dZ_l[c][k] W_l[k][n'], via LDS row layout
         for (int s = 0; s < S; ++s)
           for (int j = 0; j < 4; ++j) bufR[0][s][4 * g + j][n] = from_f<T>(dz[s][j]);
         __syncthreads();
@@ -269,7 +244,34 @@ __global__ __launch_bounds__(256) void k_fused(const Meta* meta, const float4* c
             for (int q = 0; q < KC / 8; ++q) acc[s] = mfma32(ap[q], bk[q], acc[s]);
           }
         }
-        __syncthreads();   // bufR[0] is rewritten by the next layer's dA
+        // dW_l[n][:] += sum over (stream, centre) of dZ_l[.][n] A_{l-1}[.][:]
+        for (int ib = 0; ib < NOB; ++ib) {
+          const int nin = ib * 16 + r16;
+          if constexpr (PREC == 0) {
+            for (int s = 0; s < S; ++s) {
+              float4 v = *(const float4*)(&colA[l - 2][s][nin][4 * g]);
+              accW[l - 2][ib] = mfma4(dz[s][0], v.x, accW[l - 2][ib]);
+              accW[l - 2][ib] = mfma4(dz[s][1], v.y, accW[l - 2][ib]);
+              accW[l - 2][ib] = mfma4(dz[s][2], v.z, accW[l - 2][ib]);
+              accW[l - 2][ib] = mfma4(dz[s][3], v.w, accW[l - 2][ib]);
+            }
+          } else {
+            for (int s = 0; s < S; s += 2) {
+              bf4 v0 = *(const bf4*)(&colA[l - 2][s][nin][4 * g]);
+              bf4 v1 = (s + 1 < S) ? *(const bf4*)(&colA[l - 2][s + 1][nin][4 * g])
+                                   : bf4{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+              bf8 av, bv;
+              for (int j = 0; j < 4; ++j) {
+                av[j] = (__bf16)dz[s][j];
+                av[4 + j] = (s + 1 < S) ? (__bf16)dz[s + 1][j] : (__bf16)0.f;
+                bv[j] = v0[j];
+                bv[4 + j] = v1[j];
+              }
+              accW[l - 2][ib] = mfma32(av, bv, accW[l - 2][ib]);
+            }
+          }
+        }
+        // derivative epilogue of layer l-1 (pre-activations kept in registers)
         for (int j = 0; j < 4; ++j) {
           float pp[3], ee[3], Db[3], Eb[3], zb, pb[3], eb[3];
           if (l > 2) {
@@ -288,8 +290,8 @@ __global__ __launch_bounds__(256) void k_fused(const Meta* meta, const float4* c
             for (int a = 0; a < D; ++a) accW1[a] += zb * xs[c][a] + h * pb[a];
           }
         }
+        __syncthreads();   // bufR[0] is rewritten by the next layer
       }
-      __syncthreads();
     }
 
     // ---------------- flush this net's partial gradient

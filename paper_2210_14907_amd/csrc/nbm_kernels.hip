@@ -266,12 +266,25 @@ __global__ void k_shadow(const float* params, int64_t off, int W, T* Wl, T* WlT)
   WlT[c * W + r] = from_f<T>(v);
 }
 
-__global__ void k_reduce_grad(const float* partial, int G, int64_t P, float* grad, double scale) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= P) return;
-  double s = 0.0;
-  for (int g = 0; g < G; ++g) s += (double)partial[(int64_t)g * P + j];
-  grad[j] = (float)(s * scale);
+// grad[j] = sum_g partial[g][j] in FP64: 64 columns per block, the rows split
+// over 4 groups (g = k, k+4, ...), group sums added in a fixed order
+__global__ __launch_bounds__(256) void k_reduce_grad(const float* partial, int G, int64_t P,
+                                                     float* grad, double scale) {
+  __shared__ double sh[4][64];
+  const int c = threadIdx.x & 63, k = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + c;
+  double s0 = 0.0, s1 = 0.0;
+  if (j < P) {
+    int g = k;
+    for (; g + 4 < G; g += 8) {
+      s0 += (double)partial[(int64_t)g * P + j];
+      s1 += (double)partial[(int64_t)(g + 4) * P + j];
+    }
+    for (; g < G; g += 4) s0 += (double)partial[(int64_t)g * P + j];
+  }
+  sh[k][c] = s0 + s1;
+  __syncthreads();
+  if (k == 0 && j < P) grad[j] = (float)((((sh[0][c] + sh[1][c]) + sh[2][c]) + sh[3][c]) * scale);
 }
 
 __global__ __launch_bounds__(256) void k_reduce_loss(const double* lp, int nparts, const Meta* meta,
@@ -373,118 +386,160 @@ __global__ __launch_bounds__(256) void k_res_uncut(Problem P, const Meta* meta, 
   if (threadIdx.x == 0) lossp[blockIdx.x] = s;
 }
 
-// cut cells: full cut-cell residual in FP64 from the two networks' streams
+// cut cells: full cut-cell residual in FP64 from the two networks' streams.
+// One wavefront per cut cell: corners, node jump extensions, face pieces and
+// Kuhn simplices are evaluated by separate lanes, lane 0 assembles.
 template <int D>
-__global__ __launch_bounds__(256) void k_res_cut(Problem P, const Meta* meta, const float* pts,
-                                                 const int* cutidx, const float* outputs,
-                                                 float* adj, float* resid, double* lossp,
-                                                 double scale) {
-  __shared__ double sh[256];
-  int b = blockIdx.x * 256 + threadIdx.x;
-  double r2 = 0.0;
-  int nB = meta->nB;
-  if (b < nB) {
-    const int S = 2 * D + 1;
-    int p = cutidx[b];
-    double h = P.h;
-    double x[3] = {0, 0, 0};
-    for (int a = 0; a < D; ++a) x[a] = pts[(int64_t)p * D + a];
-    // network streams of both nets at the centre
-    double o[2][7];
-    int64_t slot[2];
-    for (int t = 0; t < 2; ++t) {
-      slot[t] = meta->base[t][KIND_B] + b;
-      for (int s = 0; s < S; ++s) o[t][s] = outputs[slot[t] * 8 + s];
-    }
-    // nodes: 0 centre, 1 + 2a = +e_a, 2 + 2a = -e_a
-    double y[7][3];
-    int sd[7];
-    for (int k = 0; k < S; ++k) {
-      for (int a = 0; a < 3; ++a) y[k][a] = a < D ? x[a] : 0.0;
-      if (k > 0) y[k][(k - 1) >> 1] += ((k - 1) & 1) ? -h : h;
-      sd[k] = is_minus<D>(P, y[k]) ? 0 : 1;
-    }
-    // node values of the node's own network (from the centre streams)
-    double U[7];
-    auto node_val = [&](int t, int k) -> double {
-      if (k == 0) return o[t][0];
-      int a = (k - 1) >> 1;
-      return ((k - 1) & 1) ? o[t][0] + o[t][1 + D + a] - o[t][1 + a] : o[t][0] + o[t][1 + a];
-    };
-    for (int k = 0; k < S; ++k) U[k] = node_val(sd[k], k);
-    // differences U_F - U_0, from the difference streams when both nodes
-    // belong to the same network
-    double dU[6];
-    for (int F = 0; F < 2 * D; ++F) {
-      int k = F + 1, a = F >> 1;
-      if (sd[k] == sd[0]) {
-        int t = sd[0];
-        dU[F] = (F & 1) ? o[t][1 + D + a] - o[t][1 + a] : o[t][1 + a];
-      } else {
-        dU[F] = U[k] - U[0];
-      }
-    }
-    // jump extension at the nodes
-    double J[7];
-    for (int k = 0; k < S; ++k) {
-      double glo[3] = {0, 0, 0};
-      if (P.lo >= 0) {
-        const float* ol;
-        if (k == 0) ol = outputs + slot[P.lo] * 8;
-        else ol = outputs + ((int64_t)meta->base[P.lo][KIND_NBR] + 2 * D * b + (k - 1)) * 8;
-        for (int a = 0; a < D; ++a) glo[a] = (2.0 * (double)ol[1 + a] - (double)ol[1 + D + a]) / (2.0 * h);
-      }
-      J[k] = jump_ext<D>(P, y[k], glo);
-    }
-    CutGeom G;
-    cut_geometry<D>(P, x, h, G);
-    double mm = P.mu[0], mp = P.mu[1];
-    double cF[6], csum = 0.0, flux_corr = 0.0;
-    auto corr = [&](int s, int k) -> double {
-      if (s == 0) return sd[k] == 0 ? 0.0 : -J[k];
-      return sd[k] == 0 ? J[k] : 0.0;
-    };
-    for (int F = 0; F < 2 * D; ++F) {
-      double an = G.aneg[F], ap = 1.0 - an;
-      cF[F] = mm * an + mp * ap;
-      csum += cF[F];
-      flux_corr += mm * an * (corr(0, F + 1) - corr(0, 0)) + mp * ap * (corr(1, F + 1) - corr(1, 0));
-    }
-    double mubar = csum / (2 * D);
-    double src = G.vneg * f_side<double, D>(P, 0, x) + (1.0 - G.vneg) * f_side<double, D>(P, 1, x);
-    double bterm = 0.0;
-    if (G.gamma > 0.0) {
-      double pc[3], dc, nc[3];
-      project<D>(P, G.cen, pc, dc, nc);
-      bterm = G.gamma * beta_at<D>(P, pc, nc) / h;
-    }
-    double R = -flux_corr / (h * h) - src + bterm;
-    for (int F = 0; F < 2 * D; ++F) R -= cF[F] * dU[F] / (h * h);
-    double r = R / mubar;
-    resid[p] = (float)r;
-    r2 = r * r;
-    // adjoints: dr/dU_F = -c_F/(h^2 mubar), dr/dU_0 = sum_F c_F/(h^2 mubar)
-    double rb = scale * r;
-    double Ub[7];
-    Ub[0] = rb * csum / (h * h * mubar);
-    for (int F = 0; F < 2 * D; ++F) Ub[F + 1] = -rb * cF[F] / (h * h * mubar);
-    double g[2][7];
-    for (int t = 0; t < 2; ++t)
-      for (int s = 0; s < 7; ++s) g[t][s] = 0.0;
-    for (int k = 0; k < S; ++k) {
-      int t = sd[k];
-      g[t][0] += Ub[k];
-      if (k > 0) {
-        int a = (k - 1) >> 1;
-        if ((k - 1) & 1) { g[t][1 + D + a] += Ub[k]; g[t][1 + a] -= Ub[k]; }
-        else g[t][1 + a] += Ub[k];
-      }
-    }
-    for (int t = 0; t < 2; ++t)
-      for (int s = 0; s < S; ++s) adj[slot[t] * 8 + s] = (float)g[t][s];
+__global__ __launch_bounds__(64) void k_res_cut(Problem P, const Meta* meta, const float* pts,
+                                                const int* cutidx, const float* outputs,
+                                                float* adj, float* resid, double* lossp,
+                                                double scale) {
+  constexpr int S = 2 * D + 1;
+  constexpr int NC = 1 << D;
+  __shared__ double cf[8], Jn[7], fpart[12], tvol[6], tmeas[6], tmom[6][3];
+  __shared__ int sd[7];
+  const int b = blockIdx.x, lane = threadIdx.x;
+  if (b >= meta->nB) {
+    if (lane == 0) lossp[b] = 0.0;
+    return;
   }
-  double s = block_sum(r2, sh);
-  if (threadIdx.x == 0) lossp[blockIdx.x] = s;
+  const int p = cutidx[b];
+  const double h = P.h;
+  double x[3] = {0, 0, 0};
+  for (int a = 0; a < D; ++a) x[a] = pts[(int64_t)p * D + a];
+  int64_t slot[2];
+  for (int t = 0; t < 2; ++t) slot[t] = meta->base[t][KIND_B] + b;
+  auto corner = [&](int c, double* q) {
+    for (int a = 0; a < 3; ++a) q[a] = a < D ? x[a] + h * ((((c >> a) & 1) ? 0.5 : -0.5)) : 0.0;
+  };
+  if (lane < NC) {
+    double q[3];
+    corner(lane, q);
+    cf[lane] = phi_at<D>(P, q);
+  } else if (lane >= 8 && lane < 8 + S) {
+    const int k = lane - 8;
+    double y[3] = {x[0], x[1], x[2]};
+    if (k > 0) y[(k - 1) >> 1] += ((k - 1) & 1) ? -h : h;
+    sd[k] = is_minus<D>(P, y) ? 0 : 1;
+    double glo[3] = {0, 0, 0};
+    if (P.lo >= 0) {
+      const float* ol = k == 0 ? outputs + slot[P.lo] * 8
+                               : outputs + ((int64_t)meta->base[P.lo][KIND_NBR] + 2 * D * b + (k - 1)) * 8;
+      for (int a = 0; a < D; ++a) glo[a] = (2.0 * (double)ol[1 + a] - (double)ol[1 + D + a]) / (2.0 * h);
+    }
+    Jn[k] = jump_ext<D>(P, y, glo);
+  }
+  __syncthreads();
+  if (lane >= 16 && lane < 16 + 2 * D * (D - 1)) {
+    // face F, piece k: 2-D segment (k = 0), 3-D triangle k of the split square
+    const int F = (lane - 16) / (D - 1), k = (lane - 16) % (D - 1);
+    const int a = F >> 1, sgn = F & 1;
+    int ids[4];
+    for (int m = 0; m < (1 << (D - 1)); ++m) {
+      int c = sgn == 0 ? (1 << a) : 0, t = 0;
+      for (int bb = 0; bb < D; ++bb) {
+        if (bb == a) continue;
+        if ((m >> t) & 1) c |= 1 << bb;
+        ++t;
+      }
+      ids[m] = c;
+    }
+    fpart[lane - 16] = D == 2 ? seg_neg(cf[ids[0]], cf[ids[1]])
+                              : tri_neg(cf[ids[0]], cf[ids[k == 0 ? 1 : 2]], cf[ids[3]]);
+  } else if (lane >= 32 && lane < 32 + (D == 2 ? 2 : 6)) {
+    const int t = lane - 32;
+    double meas = 0.0, mom[3] = {0.0, 0.0, 0.0};
+    if (D == 2) {
+      const int tris[2][3] = {{0, 1, 3}, {0, 2, 3}};
+      double Pt[3][3], ft[3];
+      for (int i = 0; i < 3; ++i) { corner(tris[t][i], Pt[i]); ft[i] = cf[tris[t][i]]; }
+      tvol[t] = tri_neg(ft[0], ft[1], ft[2]);
+      iface_tri(Pt, ft, meas, mom);
+    } else {
+      const int tets[6][4] = {{0, 1, 3, 7}, {0, 1, 5, 7}, {0, 2, 3, 7}, {0, 2, 6, 7}, {0, 4, 5, 7}, {0, 4, 6, 7}};
+      double Pt[4][3], ft[4];
+      for (int i = 0; i < 4; ++i) { corner(tets[t][i], Pt[i]); ft[i] = cf[tets[t][i]]; }
+      tvol[t] = tet_neg(ft);
+      iface_tet(Pt, ft, meas, mom);
+    }
+    tmeas[t] = meas;
+    for (int a = 0; a < 3; ++a) tmom[t][a] = mom[a];
+  }
+  __syncthreads();
+  if (lane != 0) return;
+  const int NT = D == 2 ? 2 : 6;
+  double vneg = 0.0, meas = 0.0, mom[3] = {0.0, 0.0, 0.0};
+  for (int t = 0; t < NT; ++t) {
+    vneg += tvol[t];
+    meas += tmeas[t];
+    for (int a = 0; a < 3; ++a) mom[a] += tmom[t][a];
+  }
+  vneg /= NT;
+  double gamma = D == 2 ? meas / h : meas / (h * h);
+  double cen[3];
+  for (int a = 0; a < 3; ++a) cen[a] = meas > 0.0 ? mom[a] / meas : 0.0;
+  double o[2][7];
+  for (int t = 0; t < 2; ++t)
+    for (int s = 0; s < S; ++s) o[t][s] = outputs[slot[t] * 8 + s];
+  // node values of the node's own network from the centre streams, and
+  // U_F - U_0 from the difference streams when both nodes share a network
+  double dU[6];
+  for (int F = 0; F < 2 * D; ++F) {
+    const int k = F + 1, a = F >> 1;
+    if (sd[k] == sd[0]) {
+      const int t = sd[0];
+      dU[F] = (F & 1) ? o[t][1 + D + a] - o[t][1 + a] : o[t][1 + a];
+    } else {
+      const int t = sd[k];
+      double Uk = (F & 1) ? o[t][0] + o[t][1 + D + a] - o[t][1 + a] : o[t][0] + o[t][1 + a];
+      dU[F] = Uk - o[sd[0]][0];
+    }
+  }
+  auto corr = [&](int s, int k) -> double {
+    if (s == 0) return sd[k] == 0 ? 0.0 : -Jn[k];
+    return sd[k] == 0 ? Jn[k] : 0.0;
+  };
+  const double mm = P.mu[0], mp = P.mu[1];
+  double cF[6], csum = 0.0, flux_corr = 0.0;
+  for (int F = 0; F < 2 * D; ++F) {
+    double an = D == 2 ? fpart[F] : 0.5 * (fpart[2 * F] + fpart[2 * F + 1]);
+    double ap = 1.0 - an;
+    cF[F] = mm * an + mp * ap;
+    csum += cF[F];
+    flux_corr += mm * an * (corr(0, F + 1) - corr(0, 0)) + mp * ap * (corr(1, F + 1) - corr(1, 0));
+  }
+  double mubar = csum / (2 * D);
+  double src = vneg * f_side<double, D>(P, 0, x) + (1.0 - vneg) * f_side<double, D>(P, 1, x);
+  double bterm = 0.0;
+  if (gamma > 0.0) {
+    double pc[3], dc, nc[3];
+    project<D>(P, cen, pc, dc, nc);
+    bterm = gamma * beta_at<D>(P, pc, nc) / h;
+  }
+  double R = -flux_corr / (h * h) - src + bterm;
+  for (int F = 0; F < 2 * D; ++F) R -= cF[F] * dU[F] / (h * h);
+  double r = R / mubar;
+  resid[p] = (float)r;
+  lossp[b] = r * r;
+  // adjoints: dr/dU_F = -c_F/(h^2 mubar), dr/dU_0 = sum_F c_F/(h^2 mubar)
+  double rb = scale * r;
+  double Ub[7];
+  Ub[0] = rb * csum / (h * h * mubar);
+  for (int F = 0; F < 2 * D; ++F) Ub[F + 1] = -rb * cF[F] / (h * h * mubar);
+  double g[2][7];
+  for (int t = 0; t < 2; ++t)
+    for (int s = 0; s < 7; ++s) g[t][s] = 0.0;
+  for (int k = 0; k < S; ++k) {
+    const int t = sd[k];
+    g[t][0] += Ub[k];
+    if (k > 0) {
+      const int a = (k - 1) >> 1;
+      if ((k - 1) & 1) { g[t][1 + D + a] += Ub[k]; g[t][1 + a] -= Ub[k]; }
+      else g[t][1 + a] += Ub[k];
+    }
+  }
+  for (int t = 0; t < 2; ++t)
+    for (int s = 0; s < S; ++s) adj[slot[t] * 8 + s] = (float)g[t][s];
 }
 
 // Dirichlet rows at boundary points: r_b = (2d/h^2)(u - g)
@@ -1027,15 +1082,15 @@ hipError_t launch_prep(const PrepCall& c) {
 
 hipError_t launch_residuals(const ResCall& c) {
   hipStream_t st = c.stream;
-  int64_t nblk = (c.n + 255) / 256, nblkb = (c.nb + 255) / 256, nblkc = (c.cut_cap + 255) / 256;
+  int64_t nblk = (c.n + 255) / 256, nblkb = (c.nb + 255) / 256, nblkc = c.cut_cap;
   double* lp = c.lossp;
   if (c.P.dim == 2) {
     if (c.n) hipLaunchKernelGGL(k_res_uncut<2>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale, c.skip_inline);
-    if (c.n) hipLaunchKernelGGL(k_res_cut<2>, dim3(nblkc), dim3(256), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale);
+    if (c.n && nblkc) hipLaunchKernelGGL(k_res_cut<2>, dim3(nblkc), dim3(64), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale);
     if (c.nb) hipLaunchKernelGGL(k_res_bnd<2>, dim3(nblkb), dim3(256), 0, st, c.P, c.meta, c.bpts, c.nb, c.bcls, c.brank, c.outputs, c.adj, c.resid + c.n, lp + nblk + nblkc, c.scale);
   } else {
     if (c.n) hipLaunchKernelGGL(k_res_uncut<3>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale, c.skip_inline);
-    if (c.n) hipLaunchKernelGGL(k_res_cut<3>, dim3(nblkc), dim3(256), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale);
+    if (c.n && nblkc) hipLaunchKernelGGL(k_res_cut<3>, dim3(nblkc), dim3(64), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale);
     if (c.nb) hipLaunchKernelGGL(k_res_bnd<3>, dim3(nblkb), dim3(256), 0, st, c.P, c.meta, c.bpts, c.nb, c.bcls, c.brank, c.outputs, c.adj, c.resid + c.n, lp + nblk + nblkc, c.scale);
   }
   if (c.loss) {
@@ -1071,7 +1126,7 @@ hipError_t launch_shadow(hipStream_t st, int prec, const float* params, int64_t 
 
 hipError_t launch_reduce_grad(hipStream_t st, const float* partial, int G, int64_t P, float* grad,
                               double scale) {
-  hipLaunchKernelGGL(k_reduce_grad, dim3((P + 255) / 256), dim3(256), 0, st, partial, G, P, grad,
+  hipLaunchKernelGGL(k_reduce_grad, dim3((P + 63) / 64), dim3(256), 0, st, partial, G, P, grad,
                      scale);
   return hipGetLastError();
 }

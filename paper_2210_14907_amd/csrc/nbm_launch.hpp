@@ -53,6 +53,33 @@ struct FusedCall {
 typedef hipError_t (*FusedFn)(const FusedCall&);
 FusedFn find_fused(int dim, int width, int depth, int act, int prec);
 
+struct WideCall {
+  hipStream_t stream;
+  int grid;
+  const Meta* meta;
+  const float4* centres;
+  const int* src;
+  const Nets* nets;
+  Problem P;
+  float h;
+  const float* adj;
+  float* resid;
+  void* A;       // (L-1) layers of activations, tile layout, operand dtype
+  void* dZ;      // (L-1) layers of pre-activation adjoints, tile layout, operand dtype
+  int64_t lstride;
+  float* partial;
+  int64_t Ptot;
+  const NetLayout* lay;
+  int64_t off1;
+  double* lossp;
+  double scale;
+  void (*timer_begin)(void*);
+  void (*timer_end)(void*);
+  void* timer_ctx;
+};
+typedef hipError_t (*WideFn)(const WideCall&);
+WideFn find_wide(int dim, int width, int depth, int act, int prec);
+
 struct PrepCall {
   hipStream_t stream;
   Problem P;

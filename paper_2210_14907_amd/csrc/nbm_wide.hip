@@ -1,0 +1,403 @@
+// Training step for W = 128 networks in two passes.
+//
+// Pass 1 (k_wide_fb): one persistent work-group of W/16 wavefronts per
+// 16-centre tile walks forward through every layer (pre-activations stay in
+// registers: each lane owns one neuron and four centres), forms the uncut
+// residual inline (or reads the adjoints written by the residual kernels for
+// other tiles), and walks backward computing dZ_l for every hidden layer.
+// The operands of the weight-gradient contraction, A_{l-1} and dZ_l, leave
+// the chip in the accumulator ("tile") layout [tile][stream][neuron][16];
+// the small gradients (biases, W_1, w_out) are accumulated per work-group.
+//
+// Pass 2 (k_wide_dw): dW_l = sum over (tile, stream, centre) of dZ_l^T A_{l-1}
+// read straight from the tile layout as MFMA operands (the K index runs over
+// stream pairs x 4 centres per lane group), split over persistent work-groups
+// that each write one partial row; the FP64 reduction follows.
+#include <hip/hip_runtime.h>
+
+#include "nbm_device.hpp"
+#include "nbm_internal.hpp"
+#include "nbm_launch.hpp"
+
+namespace nbm {
+
+__device__ inline int wide_tile_net(const Meta* m, int t) {
+  if (t < m->tiles[0]) return 0;
+  if (t < m->tiles[0] + m->tiles[1]) return 1;
+  return -1;
+}
+
+template <int D, int W, int L, int ACT, int PREC>
+__global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float4* centres,
+                                                   const int* src, Nets nets, Problem P, float h,
+                                                   const float* adj, float* resid, void* Aout_,
+                                                   void* dZout_, int64_t lstride, float* partial,
+                                                   int64_t Ptot, NetLayout lay, int64_t net_off1,
+                                                   double* lossp, double scale) {
+  typedef typename Op<PREC>::T T;
+  constexpr int S = 2 * D + 1;
+  constexpr int LD = W + (PREC == 0 ? 4 : 8);
+  constexpr int NW = W / 16;     // wavefronts; wave w owns neurons 16w .. 16w+15
+  constexpr int KC = W / 4;
+  constexpr int NT = NW * 64;
+  __shared__ __attribute__((aligned(16))) T bufR[2][S][kTile][LD];
+  // last-layer activations: LDS for BF16 operands (room left), registers for FP32
+  constexpr bool kALinLDS = PREC == 1;
+  __shared__ float colL[kALinLDS ? S : 1][kALinLDS ? W : 1][kTile];
+  __shared__ float adjs[kTile][8];
+  __shared__ float part[NW][kTile][8];
+  __shared__ float xs[kTile][4];
+  __shared__ double lsum[kTile];
+  __shared__ int tflag;
+  T* Aout = (T*)Aout_;
+  T* dZout = (T*)dZout_;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r16 = lane & 15, g = lane >> 4;
+  const int n = w * 16 + r16;
+  const int G = gridDim.x;
+  const int ntiles = meta->tiles[0] + meta->tiles[1];
+  const float hh = h * h;
+  if (tid < kTile) lsum[tid] = 0.0;
+
+  for (int net = 0; net < 2; ++net) {
+    const NetPtrs& np = nets.net[net];
+    float accb[L], accW1[3] = {0.f, 0.f, 0.f}, accwo = 0.f, accbo = 0.f;
+    for (int l = 0; l < L; ++l) accb[l] = 0.f;
+    float W1n[3], p1[3], e0[3] = {0.f, 0.f, 0.f};
+    for (int a = 0; a < D; ++a) { W1n[a] = np.W1[n * D + a]; p1[a] = h * W1n[a]; }
+    const float b1n = np.b1[n], won = np.wout[n];
+    const int64_t a_end = (int64_t)meta->base[net][KIND_A] + meta->cnt[net][KIND_A];
+
+    for (int t = blockIdx.x; t < ntiles; t += G) {
+      if (wide_tile_net(meta, t) != net) continue;
+      const int64_t slot0 = (int64_t)t * kTile;
+      const int64_t slot_end = (int64_t)meta->tile0[net] * kTile + meta->total[net];
+      if (tid < kTile) {
+        float4 cc = centres[slot0 + tid];
+        if (slot0 + tid >= slot_end) cc = make_float4(0.f, 0.f, 0.f, 0.f);
+        xs[tid][0] = cc.x; xs[tid][1] = cc.y; xs[tid][2] = cc.z; xs[tid][3] = 0.f;
+      }
+      if (tid == 0) tflag = (slot0 + kTile <= a_end) ? 1 : 0;
+      __syncthreads();
+      const bool inl = tflag != 0;
+      auto tofs = [&](int s, int nn) -> int64_t { return (((int64_t)t * S + s) * W + nn) * kTile + 4 * g; };
+
+      // ---- layer 1
+      float z1[4];
+      for (int j = 0; j < 4; ++j) {
+        const int c = 4 * g + j;
+        float z = b1n;
+        for (int a = 0; a < D; ++a) z += W1n[a] * xs[c][a];
+        z1[j] = z;
+      }
+      {
+        float vals[S][4];
+        for (int j = 0; j < 4; ++j) {
+          float av, Dv[3], Ev[3];
+          act_fwd<ACT, D>(z1[j], p1, e0, av, Dv, Ev);
+          vals[0][j] = av;
+          for (int a = 0; a < D; ++a) { vals[1 + a][j] = Dv[a]; vals[1 + D + a][j] = Ev[a]; }
+        }
+        for (int s = 0; s < S; ++s) {
+          for (int j = 0; j < 4; ++j) bufR[0][s][4 * g + j][n] = from_f<T>(vals[s][j]);
+          if constexpr (PREC == 0)
+            *(float4*)(Aout + tofs(s, n)) = make_float4(vals[s][0], vals[s][1], vals[s][2], vals[s][3]);
+          else
+            *(bf4*)(Aout + tofs(s, n)) = bf4{(__bf16)vals[s][0], (__bf16)vals[s][1], (__bf16)vals[s][2], (__bf16)vals[s][3]};
+        }
+      }
+      __syncthreads();
+
+      // ---- hidden layers
+      float Z[L - 1][S][4];
+      float AL[kALinLDS ? 1 : S][4];
+      auto al = [&](int s, int j) -> float& {
+        if constexpr (kALinLDS) return colL[s][n][4 * g + j];
+        else return AL[s][j];
+      };
+      int cur = 0;
+#pragma unroll
+      for (int l = 2; l <= L; ++l) {
+        f4 acc[S];
+        for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (PREC == 0) {
+          const float4* wp = (const float4*)((const float*)np.Wl[l - 2] + (int64_t)n * W + g * KC);
+          for (int q = 0; q < KC / 4; ++q) {
+            float4 b4 = wp[q];
+            for (int s = 0; s < S; ++s) {
+              float4 a4 = *(const float4*)(&bufR[cur][s][r16][g * KC + 4 * q]);
+              acc[s] = mfma4(a4.x, b4.x, acc[s]);
+              acc[s] = mfma4(a4.y, b4.y, acc[s]);
+              acc[s] = mfma4(a4.z, b4.z, acc[s]);
+              acc[s] = mfma4(a4.w, b4.w, acc[s]);
+            }
+          }
+        } else {
+          const bf8* wp = (const bf8*)((const T*)np.Wl[l - 2] + (int64_t)n * W + g * KC);
+          for (int q = 0; q < KC / 8; ++q) {
+            bf8 bk = wp[q];
+            for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[cur][s][r16][g * KC + 8 * q]), bk, acc[s]);
+          }
+        }
+        const float bias = np.bl[l - 2][n];
+        const bool last = (l == L);
+        float vals[S][4];
+        for (int j = 0; j < 4; ++j) {
+          float z = acc[0][j] + bias;
+          float pp[3], ee[3], av, Dv[3], Ev[3];
+          for (int a = 0; a < D; ++a) { pp[a] = acc[1 + a][j]; ee[a] = acc[1 + D + a][j]; }
+          act_fwd<ACT, D>(z, pp, ee, av, Dv, Ev);
+          Z[l - 2][0][j] = z;
+          for (int s = 1; s < S; ++s) Z[l - 2][s][j] = acc[s][j];
+          vals[0][j] = av;
+          for (int a = 0; a < D; ++a) { vals[1 + a][j] = Dv[a]; vals[1 + D + a][j] = Ev[a]; }
+        }
+        if (!last) {
+          for (int s = 0; s < S; ++s) {
+            for (int j = 0; j < 4; ++j) bufR[cur ^ 1][s][4 * g + j][n] = from_f<T>(vals[s][j]);
+            T* dst = Aout + (int64_t)(l - 1) * lstride + tofs(s, n);
+            if constexpr (PREC == 0)
+              *(float4*)dst = make_float4(vals[s][0], vals[s][1], vals[s][2], vals[s][3]);
+            else
+              *(bf4*)dst = bf4{(__bf16)vals[s][0], (__bf16)vals[s][1], (__bf16)vals[s][2], (__bf16)vals[s][3]};
+          }
+        } else {
+          for (int s = 0; s < S; ++s)
+            for (int j = 0; j < 4; ++j) al(s, j) = vals[s][j];
+        }
+        __syncthreads();
+        cur ^= 1;
+      }
+
+      // ---- output layer, residual / adjoints
+      for (int s = 0; s < S; ++s)
+        for (int j = 0; j < 4; ++j) {
+          float v = won * al(s, j);
+          v += __shfl_xor(v, 8);
+          v += __shfl_xor(v, 4);
+          v += __shfl_xor(v, 2);
+          v += __shfl_xor(v, 1);
+          if (r16 == 0) part[w][4 * g + j][s] = v;
+        }
+      __syncthreads();
+      if (tid < kTile) {
+        const int c = tid;
+        const int64_t slot = slot0 + c;
+        if (inl) {
+          float eu = 0.f;
+          for (int a = 0; a < D; ++a)
+            for (int v = 0; v < NW; ++v) eu += part[v][c][1 + D + a];
+          float x[3] = {xs[c][0], xs[c][1], xs[c][2]};
+          float r = -eu / hh - f_side<float, D>(P, net, x) / (float)P.mu[net];
+          resid[src[slot]] = r;
+          lsum[c] += (double)r * (double)r;
+          float rb = (float)(scale * (double)r);
+          for (int s = 0; s < 8; ++s) adjs[c][s] = 0.f;
+          for (int a = 0; a < D; ++a) adjs[c][1 + D + a] = -rb / hh;
+        } else {
+          const bool valid = slot < slot_end;
+          for (int s = 0; s < 8; ++s) adjs[c][s] = valid ? adj[slot * 8 + s] : 0.f;
+        }
+      }
+      __syncthreads();
+
+      // ---- backward, top layer
+      float dz[S][4];
+      for (int j = 0; j < 4; ++j) {
+        const int c = 4 * g + j;
+        float pp[3], ee[3], Db[3], Eb[3], zb, pb[3], eb[3];
+        for (int a = 0; a < D; ++a) {
+          pp[a] = Z[L - 2][1 + a][j]; ee[a] = Z[L - 2][1 + D + a][j];
+          Db[a] = won * adjs[c][1 + a]; Eb[a] = won * adjs[c][1 + D + a];
+        }
+        act_bwd<ACT, D>(Z[L - 2][0][j], pp, ee, won * adjs[c][0], Db, Eb, zb, pb, eb);
+        dz[0][j] = zb;
+        for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
+        for (int s = 0; s < S; ++s) accwo += adjs[c][s] * al(s, j);
+      }
+      if (tid == 0)
+        for (int c = 0; c < kTile; ++c) accbo += adjs[c][0];
+
+      // ---- backward through the hidden layers
+#pragma unroll
+      for (int l = L; l >= 2; --l) {
+        for (int j = 0; j < 4; ++j) accb[l - 1] += dz[0][j];
+        for (int s = 0; s < S; ++s) {
+          for (int j = 0; j < 4; ++j) bufR[0][s][4 * g + j][n] = from_f<T>(dz[s][j]);
+          T* dst = dZout + (int64_t)(l - 2) * lstride + tofs(s, n);
+          if constexpr (PREC == 0)
+            *(float4*)dst = make_float4(dz[s][0], dz[s][1], dz[s][2], dz[s][3]);
+          else
+            *(bf4*)dst = bf4{(__bf16)dz[s][0], (__bf16)dz[s][1], (__bf16)dz[s][2], (__bf16)dz[s][3]};
+        }
+        __syncthreads();
+        f4 acc[S];
+        for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (PREC == 0) {
+          const float4* wp = (const float4*)((const float*)np.WlT[l - 2] + (int64_t)n * W + g * KC);
+          for (int q = 0; q < KC / 4; ++q) {
+            float4 b4 = wp[q];
+            for (int s = 0; s < S; ++s) {
+              float4 a4 = *(const float4*)(&bufR[0][s][r16][g * KC + 4 * q]);
+              acc[s] = mfma4(a4.x, b4.x, acc[s]);
+              acc[s] = mfma4(a4.y, b4.y, acc[s]);
+              acc[s] = mfma4(a4.z, b4.z, acc[s]);
+              acc[s] = mfma4(a4.w, b4.w, acc[s]);
+            }
+          }
+        } else {
+          const bf8* wp = (const bf8*)((const T*)np.WlT[l - 2] + (int64_t)n * W + g * KC);
+          for (int q = 0; q < KC / 8; ++q) {
+            bf8 bk = wp[q];
+            for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[0][s][r16][g * KC + 8 * q]), bk, acc[s]);
+          }
+        }
+        for (int j = 0; j < 4; ++j) {
+          float pp[3], ee[3], Db[3], Eb[3], zb, pb[3], eb[3];
+          if (l > 2) {
+            for (int a = 0; a < D; ++a) {
+              pp[a] = Z[l - 3][1 + a][j]; ee[a] = Z[l - 3][1 + D + a][j];
+              Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j];
+            }
+            act_bwd<ACT, D>(Z[l - 3][0][j], pp, ee, acc[0][j], Db, Eb, zb, pb, eb);
+            dz[0][j] = zb;
+            for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
+          } else {
+            for (int a = 0; a < D; ++a) { Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j]; }
+            act_bwd<ACT, D>(z1[j], p1, e0, acc[0][j], Db, Eb, zb, pb, eb);
+            const int c = 4 * g + j;
+            accb[0] += zb;
+            for (int a = 0; a < D; ++a) accW1[a] += zb * xs[c][a] + h * pb[a];
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // ---- flush the small gradients of this net
+    float* prow = partial + (int64_t)blockIdx.x * Ptot + (net == 0 ? 0 : net_off1);
+    for (int l = 0; l < L; ++l) {
+      float v = accb[l];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      accb[l] = v;
+    }
+    accwo += __shfl_xor(accwo, 16);
+    accwo += __shfl_xor(accwo, 32);
+    for (int a = 0; a < 3; ++a) {
+      accW1[a] += __shfl_xor(accW1[a], 16);
+      accW1[a] += __shfl_xor(accW1[a], 32);
+    }
+    if (g == 0) {
+      prow[lay.b1 + n] = accb[0];
+      for (int a = 0; a < D; ++a) prow[lay.W1 + (int64_t)n * D + a] = accW1[a];
+      for (int l = 2; l <= L; ++l) prow[lay.bl[l - 2] + n] = accb[l - 1];
+      prow[lay.wout + n] = accwo;
+    }
+    if (tid == 0) prow[lay.bout] = accbo;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double s = 0.0;
+    for (int c = 0; c < kTile; ++c) s += lsum[c];
+    lossp[blockIdx.x] = s;
+  }
+}
+
+// dW_l partials: wave w owns out-blocks {w, w+4, ...}, all in-blocks
+template <int D, int W, int PREC>
+__global__ __launch_bounds__(256) void k_wide_dw(const Meta* meta, const void* A_, const void* dZ_,
+                                                 float* partial, int64_t Ptot, int64_t woff,
+                                                 int64_t net_off1) {
+  typedef typename Op<PREC>::T T;
+  constexpr int S = 2 * D + 1;
+  constexpr int NOB = W / 16;
+  constexpr int OBW = NOB / 4;
+  const T* A = (const T*)A_;
+  const T* dZ = (const T*)dZ_;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r16 = lane & 15, g = lane >> 4;
+  const int G = gridDim.x;
+  const int ntiles = meta->tiles[0] + meta->tiles[1];
+  for (int net = 0; net < 2; ++net) {
+    f4 acc[OBW][NOB];
+    for (int i = 0; i < OBW; ++i)
+      for (int k = 0; k < NOB; ++k) acc[i][k] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int t = blockIdx.x; t < ntiles; t += G) {
+      if (wide_tile_net(meta, t) != net) continue;
+      auto tofs = [&](int s, int nn) -> int64_t { return (((int64_t)t * S + s) * W + nn) * kTile + 4 * g; };
+      if constexpr (PREC == 0) {
+        float dzv[OBW][S][4];
+        for (int i = 0; i < OBW; ++i)
+          for (int s = 0; s < S; ++s) {
+            float4 v = *(const float4*)(dZ + tofs(s, (w + 4 * i) * 16 + r16));
+            dzv[i][s][0] = v.x; dzv[i][s][1] = v.y; dzv[i][s][2] = v.z; dzv[i][s][3] = v.w;
+          }
+        for (int ib = 0; ib < NOB; ++ib)
+          for (int s = 0; s < S; ++s) {
+            float4 a = *(const float4*)(A + tofs(s, ib * 16 + r16));
+            for (int i = 0; i < OBW; ++i) {
+              acc[i][ib] = mfma4(dzv[i][s][0], a.x, acc[i][ib]);
+              acc[i][ib] = mfma4(dzv[i][s][1], a.y, acc[i][ib]);
+              acc[i][ib] = mfma4(dzv[i][s][2], a.z, acc[i][ib]);
+              acc[i][ib] = mfma4(dzv[i][s][3], a.w, acc[i][ib]);
+            }
+          }
+      } else {
+        bf8 dzv[OBW][(S + 1) / 2];
+        const bf4 zero4 = bf4{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+        for (int i = 0; i < OBW; ++i)
+          for (int s = 0; s < S; s += 2) {
+            bf4 v0 = *(const bf4*)(dZ + tofs(s, (w + 4 * i) * 16 + r16));
+            bf4 v1 = s + 1 < S ? *(const bf4*)(dZ + tofs(s + 1, (w + 4 * i) * 16 + r16)) : zero4;
+            for (int j = 0; j < 4; ++j) { dzv[i][s / 2][j] = v0[j]; dzv[i][s / 2][4 + j] = v1[j]; }
+          }
+        for (int ib = 0; ib < NOB; ++ib)
+          for (int s = 0; s < S; s += 2) {
+            bf4 v0 = *(const bf4*)(A + tofs(s, ib * 16 + r16));
+            bf4 v1 = s + 1 < S ? *(const bf4*)(A + tofs(s + 1, ib * 16 + r16)) : zero4;
+            bf8 a;
+            for (int j = 0; j < 4; ++j) { a[j] = v0[j]; a[4 + j] = v1[j]; }
+            for (int i = 0; i < OBW; ++i) acc[i][ib] = mfma32(dzv[i][s / 2], a, acc[i][ib]);
+          }
+      }
+    }
+    float* prow = partial + (int64_t)blockIdx.x * Ptot + (net == 0 ? 0 : net_off1) + woff;
+    for (int i = 0; i < OBW; ++i)
+      for (int ib = 0; ib < NOB; ++ib)
+        for (int r = 0; r < 4; ++r) {
+          int row = (w + 4 * i) * 16 + 4 * g + r, col = ib * 16 + r16;
+          prow[(int64_t)row * W + col] = acc[i][ib][r];
+        }
+  }
+}
+
+template <int D, int W, int L, int ACT, int PREC>
+hipError_t wide_impl(const WideCall& c) {
+  hipLaunchKernelGGL((k_wide_fb<D, W, L, ACT, PREC>), dim3(c.grid), dim3(W * 4), 0, c.stream, c.meta,
+                     c.centres, c.src, *c.nets, c.P, c.h, c.adj, c.resid, c.A, c.dZ, c.lstride,
+                     c.partial, c.Ptot, *c.lay, c.off1, c.lossp, c.scale);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int l = 2; l <= L; ++l) {
+    if (c.timer_begin) c.timer_begin(c.timer_ctx);
+    hipLaunchKernelGGL((k_wide_dw<D, W, PREC>), dim3(c.grid), dim3(256), 0, c.stream, c.meta,
+                       (const char*)c.A + (int64_t)(l - 2) * c.lstride * Op<PREC>::bytes,
+                       (const char*)c.dZ + (int64_t)(l - 2) * c.lstride * Op<PREC>::bytes, c.partial,
+                       c.Ptot, c.lay->Wl[l - 2], c.off1);
+    if (c.timer_end) c.timer_end(c.timer_ctx);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+#define NBM_WIDE(D, W, L, ACT, PREC) \
+  if (dim == D && width == W && depth == L && act == ACT && prec == PREC) return &wide_impl<D, W, L, ACT, PREC>;
+
+WideFn find_wide(int dim, int width, int depth, int act, int prec) {
+  NBM_WIDE(3, 128, 4, 1, 1)
+  NBM_WIDE(3, 128, 4, 1, 0)
+  NBM_WIDE(3, 128, 4, 0, 1)
+  NBM_WIDE(3, 128, 4, 0, 0)
+  return nullptr;
+}
+
+}  // namespace nbm

@@ -75,18 +75,19 @@ def test_step_parity(name, wl, n, nb, n_near, band):
     assert e_unc <= (5 * tol if wl.prec == I.PREC_FP32 else tol)
 
 
-def test_fused_and_layered_paths_agree(monkeypatch):
-    """The fused W=64 kernel and the layered forward/backward give the same
-    step (both are also checked against the oracle above)."""
-    wl = I.C2
+@pytest.mark.parametrize("wl", [I.C2, I.C3.replace(prec=I.PREC_FP32)], ids=["c2_fused", "c3_two_pass"])
+def test_fused_and_layered_paths_agree(monkeypatch, wl):
+    """The fused kernels (W=64 one-pass, W=128 two-pass) and the layered
+    forward/backward give the same step (all are also checked against the
+    oracle above)."""
     theta = I.xavier_params(wl, 5).astype(np.float32)
-    pts, bpts = parity_batch(wl, 4096, 96, 512, 0.02, seed=8)
+    pts, bpts = parity_batch(wl, 2048, 96, 256, 0.02, seed=8)
     a = _run(wl, pts, bpts, theta)
     monkeypatch.setenv("NBM_NO_FUSED", "1")
     b = _run(wl, pts, bpts, theta)
     assert abs(a[0] - b[0]) <= 1e-6 * abs(b[0])
     assert max_rel(a[1], b[1]) <= 1e-6
-    assert rel_err(a[2], b[2]) <= 1e-6
+    assert rel_err(a[2], b[2]) <= 2e-6
 
 
 def test_determinism_bitwise():
