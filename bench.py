@@ -187,8 +187,13 @@ def main():
     centres = int(c[0] + c[1] + (2 + nbr) * c[2] + c[3] + c[4])
     f_ms, f_n = tm["forward"]
     b_ms, b_n = tm["backward"]
-    if b_ms >= f_ms:
-        name, per_launch, avg = "k_backward (hidden layer, dW+dA)", bl_f * centres, b_ms / b_n
+    if wl.width == 64:
+        # one launch per step runs the forward, residual and backward of every
+        # tile on chip; it is the dominant kernel
+        name, per_launch, avg = ("k_fused (forward + residual + backward, all layers)",
+                                 (fwd_f + bwd_f) * centres, b_ms / b_n)
+    elif b_ms >= f_ms:
+        name, per_launch, avg = "backward group", bwd_f * centres, b_ms / b_n
     else:
         name, per_launch, avg = "k_forward (all layers)", fwd_f * centres, f_ms / f_n
     dtype = "fp32" if wl.prec == I.PREC_FP32 else "bf16"

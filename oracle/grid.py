@@ -174,11 +174,15 @@ class GridSystem:
         the nodes of the cut cells (contrast only)."""
         d, h, wl, prob = self.d, self.h, self.wl, self.prob
         b = np.zeros(self.N)
-        xu = self.x[self.uncut]
-        su = self.side[self.uncut]
-        fm = prob.f_side(0, xu)
-        fp = prob.f_side(1, xu)
-        b[self.uncut] = h * h * np.where(su, fm, fp)
+        if not hasattr(self, "_f_uncut"):
+            # the forcing does not change across Picard iterations
+            xu = self.x[self.uncut]
+            su = self.side[self.uncut]
+            if wl.problem == I.PROB_FOURIER:
+                self._f_uncut = prob.f_side(0, xu)   # f^- = f^+
+            else:
+                self._f_uncut = np.where(su, prob.f_side(0, xu), prob.f_side(1, xu))
+        b[self.uncut] = h * h * self._f_uncut
         if self.cut.size:
             nodes = self.cut[:, None] + self.node_offsets()[None, :]
             y = self.x[nodes]

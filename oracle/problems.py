@@ -88,9 +88,13 @@ class Problem:
             return mu * 2.0 * np.cos(x[..., 0]) * np.sin(x[..., 1])
         if p == I.PROB_LINEAR:
             return np.zeros(x.shape[:-1])
-        # f(x) = sum_k a_k cos(pi k.x) + b_k sin(pi k.x)
-        ph = np.pi * (x @ self.k.T)
-        return np.cos(ph) @ self.a + np.sin(ph) @ self.b
+        # f(x) = sum_k a_k cos(pi k.x) + b_k sin(pi k.x), in chunks of points
+        flat = x.reshape(-1, x.shape[-1])
+        out = np.empty(flat.shape[0])
+        for i in range(0, flat.shape[0], 8192):
+            ph = np.pi * (flat[i:i + 8192] @ self.k.T)
+            out[i:i + 8192] = np.cos(ph) @ self.a + np.sin(ph) @ self.b
+        return out.reshape(x.shape[:-1])
 
     # jump data on Gamma (arguments are points on or projected to Gamma) -------
     def alpha(self, y, n):

@@ -172,12 +172,22 @@ class NBM:
                                    int(step), lr, beta1, beta2, eps))
 
     def eval(self, params, query=None, m=None, tile_index=0, grid_n=0, out=None):
+        """u at query points [m][d] (split into calls of at most max_points),
+        or at grid tile `tile_index` of m points of the grid_n^d lattice."""
         if query is not None:
             m = query.shape[0]
         if out is None:
             out = torch.empty(m, dtype=torch.float32, device=self.device)
-        _check(lib().nbm_eval(self.ctx, _stream(), _ptr(params), _ptr(query), m, tile_index, grid_n,
-                              _ptr(out), _ptr(self.ws_view), self.ws_bytes))
+        cap = int(self.cfg.max_points)
+        if query is None:
+            _check(lib().nbm_eval(self.ctx, _stream(), _ptr(params), None, m, tile_index, grid_n,
+                                  _ptr(out), _ptr(self.ws_view), self.ws_bytes))
+            return out
+        for i in range(0, m, cap):
+            q = query[i:i + cap]
+            o = out[i:i + cap]
+            _check(lib().nbm_eval(self.ctx, _stream(), _ptr(params), _ptr(q), q.shape[0], 0, 0,
+                                  _ptr(o), _ptr(self.ws_view), self.ws_bytes))
         return out
 
     TIMING_GROUPS = ["prep", "forward", "residual", "backward", "reduce", "adam", "sample", "eval"]

@@ -37,10 +37,14 @@ __global__ __launch_bounds__(256) void k_fused(const Meta* meta, const float4* c
   constexpr int KC = W / 4;         // K chunk per lane group
   static_assert(NOB == 4, "one 16-neuron block per wave");
   __shared__ __attribute__((aligned(16))) T bufR[2][S][kTile][LD];      // row layout [c][n]
-  __shared__ __attribute__((aligned(16))) T colA[L - 1][S][W][kTile];   // column layout [n][c]
+  constexpr int CP = kTile + (PREC == 0 ? 4 : 8);   // padded column stride
+  __shared__ __attribute__((aligned(16))) T colA[L - 1][S][W][CP];      // column layout [n][c]
   __shared__ __attribute__((aligned(16))) float colL[S][W][kTile];   // last-layer activations (FP32)
   __shared__ float adjs[kTile][8];
-  __shared__ float part[4][kTile][8];
+  // output-layer partial sums live in the row buffers, free between the last
+  // forward layer and the first backward write
+  float (*part)[kTile][8] = reinterpret_cast<float (*)[kTile][8]>(&bufR[0][0][0][0]);
+  static_assert(sizeof(bufR) >= 4 * kTile * 8 * sizeof(float), "partials fit the row buffers");
   __shared__ float xs[kTile][4];
   __shared__ double lsum[kTile];
   __shared__ int tflag;
