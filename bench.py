@@ -228,7 +228,7 @@ def main():
     if not args.no_extra:
         extra = {}
         for tag, w in (("c2_bf16", wl.replace(prec=I.PREC_BF16)), ("c3_bf16", I.C3),
-                       ("c3_fp32", I.C3.replace(prec=I.PREC_FP32))):
+                       ("c3_fp32", I.C3.replace(prec=I.PREC_FP32)), ("c4_bf16", I.C4)):
             r = run_workload(w, max(10, args.steps // 2), 3, timing=False)
             extra[tag] = {"pts_per_s": round(w.n_points / (r["ms_per_step"] * 1e-3), 1),
                           "fwd_res_bwd_pts_per_s": round(w.n_points / (r["ms_fwd_res_bwd"] * 1e-3), 1),

@@ -87,6 +87,8 @@ typedef struct nbm_config {
   int64_t max_points;    /* largest interior batch n the workspace must hold */
   int64_t max_boundary;  /* largest boundary batch nb */
   int64_t cut_capacity;  /* max cut cells per batch; 0 -> max_points/8 + 64 */
+  int32_t eval_only;     /* 1: workspace for nbm_eval only (max_points = largest
+                            query tile); training calls return NBM_EWORKSPACE */
 } nbm_config;
 
 typedef struct nbm_ctx nbm_ctx;

@@ -35,7 +35,7 @@ class NbmConfig(ctypes.Structure):
                 ("n_modes", ctypes.c_int32), ("mode_k", ctypes.POINTER(ctypes.c_int32)),
                 ("mode_a", ctypes.POINTER(ctypes.c_double)), ("mode_b", ctypes.POINTER(ctypes.c_double)),
                 ("max_points", ctypes.c_int64), ("max_boundary", ctypes.c_int64),
-                ("cut_capacity", ctypes.c_int64)]
+                ("cut_capacity", ctypes.c_int64), ("eval_only", ctypes.c_int32)]
 
 
 class NbmError(RuntimeError):
@@ -88,7 +88,7 @@ class NBM:
     """One NBM problem/network configuration with its device workspace."""
 
     def __init__(self, wl: I.Workload, max_points: int = None, max_boundary: int = None,
-                 cut_capacity: int = 0, device: str = "cuda:0"):
+                 cut_capacity: int = 0, device: str = "cuda:0", eval_only: bool = False):
         self.wl = wl
         self.device = torch.device(device)
         cfg = NbmConfig()
@@ -116,6 +116,7 @@ class NBM:
         cfg.max_points = wl.n_points if max_points is None else max_points
         cfg.max_boundary = wl.n_boundary if max_boundary is None else max_boundary
         cfg.cut_capacity = cut_capacity
+        cfg.eval_only = 1 if eval_only else 0
         self.cfg = cfg
         h = ctypes.c_void_p()
         _check(lib().nbm_create(ctypes.byref(cfg), ctypes.byref(h)))

@@ -30,7 +30,7 @@ static int fail(int code, const std::string& msg) {
 namespace {
 struct Layout {
   size_t modes32, modes64, meta, blockcnt, off, blockcnt_b, off_b, cls, rank, bcls, brank, cutidx,
-      centres, src, outputs, adj, Zst, Ast, ALst, dZ, dZw, shadow, partial, lossp, resid, lossbuf, total;
+      centres, src, outputs, adj, Zst, Ast, ALst, dZ, dZw, shadow, partial, lossp, resid, lossbuf, fpre, total;
 };
 }  // namespace
 
@@ -58,6 +58,7 @@ struct nbm_ctx {
   bool no_fused;
   Layout lo;
   void* prepared_ws;
+  bool eval_only;
 };
 
 // event pair around one kernel group (no-op unless timing is enabled)
@@ -87,7 +88,11 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 static void make_layout(nbm_ctx* c) {
   Layout& L = c->lo;
   size_t o = 0;
+  const bool ev = c->eval_only;
+  // evaluation-only workspaces keep just the classification, centre lists,
+  // outputs and operand shadows
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  auto take_tr = [&](size_t bytes) { return take(ev ? 0 : bytes); };
   int64_t nblk = (c->cap_n + 255) / 256 + 1, nblkb = (c->cap_nb + 255) / 256 + 1;
   int64_t nblkc = (c->cut_cap + 255) / 256 + 1;
   L.modes32 = take(sizeof(float) * 8 * (c->cfg.n_modes + 1));
@@ -105,20 +110,21 @@ static void make_layout(nbm_ctx* c) {
   L.centres = take(sizeof(float) * 4 * c->cap_slots);
   L.src = take(sizeof(int) * c->cap_slots);
   L.outputs = take(sizeof(float) * 8 * c->cap_slots);
-  L.adj = take(sizeof(float) * 8 * c->cap_slots);
+  L.adj = take_tr(sizeof(float) * 8 * c->cap_slots);
   // stored pre-activations are needed only by the layered backward, used when
   // no fused path is compiled for the shape (or NBM_NO_FUSED is set)
   const bool layered = c->no_fused || (!c->fused && !c->wide);
-  L.Zst = take(layered ? sizeof(float) * c->L * c->lstride : 0);
-  L.Ast = take((size_t)c->opbytes * (c->L - 1) * c->lstride);
-  L.ALst = take(layered ? sizeof(float) * c->lstride : 0);
-  L.dZ = take(layered ? sizeof(float) * c->lstride : 0);
-  L.dZw = take(c->wide && !c->no_fused ? (size_t)c->opbytes * (c->L - 1) * c->lstride : 0);
+  L.Zst = take_tr(layered ? sizeof(float) * c->L * c->lstride : 0);
+  L.Ast = take_tr((size_t)c->opbytes * (c->L - 1) * c->lstride);
+  L.ALst = take_tr(layered ? sizeof(float) * c->lstride : 0);
+  L.dZ = take_tr(layered ? sizeof(float) * c->lstride : 0);
+  L.dZw = take_tr(c->wide && !c->no_fused ? (size_t)c->opbytes * (c->L - 1) * c->lstride : 0);
   L.shadow = take((size_t)c->opbytes * 2 * (c->L - 1) * 2 * c->W * c->W);
-  L.partial = take(sizeof(float) * (size_t)c->G * c->Ptot);
+  L.partial = take_tr(sizeof(float) * (size_t)c->G * c->Ptot);
   L.lossp = take(sizeof(double) * (nblk + nblkb + c->cut_cap + 4 + 512));
-  L.resid = take(sizeof(float) * (c->cap_n + c->cap_nb));
+  L.resid = take_tr(sizeof(float) * (c->cap_n + c->cap_nb));
   L.lossbuf = take(sizeof(double) * 4);
+  L.fpre = take_tr(c->cfg.problem == NBM_PROB_FOURIER ? sizeof(float) * c->cap_n : 0);
   L.total = o;
 }
 
@@ -151,6 +157,8 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
   }
   if (c.max_points < 1 || c.max_points > (1LL << 26) || c.max_boundary < 0 || c.max_boundary > (1LL << 24))
     return fail(NBM_EINVAL, "max_points must be in [1, 2^26], max_boundary in [0, 2^24]");
+  if (!c.eval_only && c.max_points > (1LL << 24))
+    return fail(NBM_EINVAL, "training batches are limited to 2^24 points (use eval_only for larger tiles)");
   MlpFn fn = find_mlp(c.dim, c.width, c.act, c.prec);
   if (!fn)
     return fail(NBM_EUNSUPPORTED, "no kernel compiled for (dim, width, act, prec) = (" +
@@ -208,10 +216,12 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
   }
   x->cfg.n_modes = P.n_modes;
   // capacities
+  x->eval_only = c.eval_only != 0;
   x->cap_n = c.max_points;
   x->cap_nb = c.max_boundary;
   x->cut_cap = c.cut_capacity > 0 ? c.cut_capacity : c.max_points / 8 + 64;
   if (x->cut_cap > x->cap_n) x->cut_cap = x->cap_n;
+  if (x->eval_only) { x->cut_cap = 0; x->cap_nb = 0; }
   int nbr = P.lo >= 0 ? 2 * c.dim : 0;
   x->cap_slots = x->cap_n + (2 + nbr) * x->cut_cap + x->cap_nb + 2 * kTile;
   x->cap_tiles = (x->cap_slots + kTile - 1) / kTile + 2;
@@ -314,6 +324,7 @@ static Nets nets_for(nbm_ctx* ctx, const float* params, void* ws) {
 }
 
 static int check_points(nbm_ctx* ctx, const float* pts, int64_t n, const float* bpts, int64_t nb) {
+  if (ctx->eval_only) return fail(NBM_EWORKSPACE, "context was created with eval_only");
   if (n < 0 || nb < 0) return fail(NBM_EINVAL, "negative batch size");
   if (n + nb == 0) return fail(NBM_EINVAL, "empty batch");
   if (n > ctx->cap_n || nb > ctx->cap_nb) return fail(NBM_EINVAL, "batch exceeds max_points / max_boundary");
@@ -351,6 +362,11 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   pc.src = at<int>(ws, Lo.src);
   pc.cutidx = at<int>(ws, Lo.cutidx);
   hipError_t e = launch_prep(pc);
+  const float* fpre = nullptr;
+  if (ctx->cfg.problem == NBM_PROB_FOURIER && n > 0) {
+    fpre = at<float>(ws, Lo.fpre);
+    if (e == hipSuccess) e = launch_forcing(st, P, pts, n, (float*)fpre);
+  }
   delete tprep;
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("prep: ") + hipGetErrorString(e));
   // network streams at every centre
@@ -396,6 +412,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   rc.loss = fused ? nullptr : loss_out;
   rc.scale = 2.0 * dL / (double)(n + nb);
   rc.skip_inline = fused ? 1 : 0;
+  rc.fpre = fpre;
   e = launch_residuals(rc);
   delete tres;
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("residual: ") + hipGetErrorString(e));
@@ -410,7 +427,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
     wc.nets = &N; wc.P = P; wc.h = (float)ctx->cfg.h; wc.adj = adj; wc.resid = rc.resid;
     wc.A = at<void>(ws, Lo.Ast); wc.dZ = at<void>(ws, Lo.dZw); wc.lstride = ctx->lstride;
     wc.partial = partial; wc.Ptot = ctx->Ptot; wc.lay = &ctx->lay; wc.off1 = ctx->per_net;
-    wc.lossp = rc.lossp + nres; wc.scale = rc.scale;
+    wc.lossp = rc.lossp + nres; wc.scale = rc.scale; wc.fpre = fpre;
     {
       Timer tb(ctx, st, 3);
       e = ctx->wide(wc);
@@ -426,7 +443,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
     fc.stream = st; fc.grid = ctx->Gf; fc.meta = pc.meta; fc.centres = pc.centres; fc.src = pc.src;
     fc.nets = &N; fc.P = P; fc.h = (float)ctx->cfg.h; fc.adj = adj; fc.resid = rc.resid;
     fc.partial = partial; fc.Ptot = ctx->Ptot; fc.lay = &ctx->lay; fc.off1 = ctx->per_net;
-    fc.lossp = rc.lossp + nres; fc.scale = rc.scale;
+    fc.lossp = rc.lossp + nres; fc.scale = rc.scale; fc.fpre = fpre;
     {
       Timer tb(ctx, st, 3);
       e = ctx->fused(fc);

@@ -249,6 +249,45 @@ __global__ __launch_bounds__(256) void k_scatter(Problem P, const Meta* meta, co
 }
 
 // ===========================================================================
+// Fourier forcing of every interior point (one thread per point): per-axis
+// phase factors exp(i pi k x_a), k = 0..8, in LDS, then the mode sum.
+// ===========================================================================
+template <int D>
+__global__ __launch_bounds__(256) void k_forcing(Problem P, const float* pts, int64_t n,
+                                                 float* fout) {
+  __shared__ float ph[256][D][9][2];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int t = threadIdx.x;
+  float x[3] = {0.f, 0.f, 0.f};
+  if (i < n)
+    for (int a = 0; a < D; ++a) x[a] = pts[i * D + a];
+  for (int a = 0; a < D; ++a)
+    for (int k = 0; k <= 8; ++k) {
+      float sv, cv;
+      sincospif((float)k * x[a], &sv, &cv);
+      ph[t][a][k][0] = cv;
+      ph[t][a][k][1] = sv;
+    }
+  float acc = 0.0f;
+  for (int m = 0; m < P.n_modes; ++m) {
+    const float* md = P.modes32 + 8 * m;
+    float re = 1.0f, im = 0.0f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int k = (int)md[a];
+      const int kk = k < 0 ? -k : k;
+      const float fr = ph[t][a][kk][0];
+      const float fi = (k < 0 ? -1.0f : 1.0f) * ph[t][a][kk][1];
+      const float nr = re * fr - im * fi;
+      im = re * fi + im * fr;
+      re = nr;
+    }
+    acc += md[3] * re + md[4] * im;
+  }
+  if (i < n) fout[i] = acc;
+}
+
+// ===========================================================================
 // Utilities
 // ===========================================================================
 __global__ void k_fill(float* p, int64_t n, float v) {
@@ -358,7 +397,8 @@ template <int D>
 __global__ __launch_bounds__(256) void k_res_uncut(Problem P, const Meta* meta, const float* pts,
                                                    int64_t n, const int* cls, const int* rank,
                                                    const float* outputs, float* adj, float* resid,
-                                                   double* lossp, double scale, int skip_inline) {
+                                                   double* lossp, double scale, int skip_inline,
+                                                   const float* fpre) {
   __shared__ double sh[256];
   int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double r2 = 0.0;
@@ -375,7 +415,8 @@ __global__ __launch_bounds__(256) void k_res_uncut(Problem P, const Meta* meta, 
       float hh = (float)(P.h * P.h);
       float lap = 0.0f;
       for (int a = 0; a < D; ++a) lap += outputs[slot * 8 + 1 + D + a];
-      float r = -lap / hh - f_side<float, D>(P, c, x) / (float)P.mu[c];
+      float fv = fpre ? fpre[i] : f_side<float, D>(P, c, x);
+      float r = -lap / hh - fv / (float)P.mu[c];
       if (resid) resid[i] = r;
       r2 = (double)r * (double)r;
       float rb = (float)(scale * (double)r);
@@ -393,7 +434,7 @@ template <int D>
 __global__ __launch_bounds__(64) void k_res_cut(Problem P, const Meta* meta, const float* pts,
                                                 const int* cutidx, const float* outputs,
                                                 float* adj, float* resid, double* lossp,
-                                                double scale) {
+                                                double scale, const float* fpre) {
   constexpr int S = 2 * D + 1;
   constexpr int NC = 1 << D;
   __shared__ double cf[8], Jn[7], fpart[12], tvol[6], tmeas[6], tmom[6][3];
@@ -509,7 +550,9 @@ __global__ __launch_bounds__(64) void k_res_cut(Problem P, const Meta* meta, con
     flux_corr += mm * an * (corr(0, F + 1) - corr(0, 0)) + mp * ap * (corr(1, F + 1) - corr(1, 0));
   }
   double mubar = csum / (2 * D);
-  double src = vneg * f_side<double, D>(P, 0, x) + (1.0 - vneg) * f_side<double, D>(P, 1, x);
+  // f^- = f^+ for the Fourier forcing (precomputed per point)
+  double src = fpre ? (double)fpre[p]
+                    : vneg * f_side<double, D>(P, 0, x) + (1.0 - vneg) * f_side<double, D>(P, 1, x);
   double bterm = 0.0;
   if (gamma > 0.0) {
     double pc[3], dc, nc[3];
@@ -1085,12 +1128,12 @@ hipError_t launch_residuals(const ResCall& c) {
   int64_t nblk = (c.n + 255) / 256, nblkb = (c.nb + 255) / 256, nblkc = c.cut_cap;
   double* lp = c.lossp;
   if (c.P.dim == 2) {
-    if (c.n) hipLaunchKernelGGL(k_res_uncut<2>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale, c.skip_inline);
-    if (c.n && nblkc) hipLaunchKernelGGL(k_res_cut<2>, dim3(nblkc), dim3(64), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale);
+    if (c.n) hipLaunchKernelGGL(k_res_uncut<2>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale, c.skip_inline, c.fpre);
+    if (c.n && nblkc) hipLaunchKernelGGL(k_res_cut<2>, dim3(nblkc), dim3(64), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale, c.fpre);
     if (c.nb) hipLaunchKernelGGL(k_res_bnd<2>, dim3(nblkb), dim3(256), 0, st, c.P, c.meta, c.bpts, c.nb, c.bcls, c.brank, c.outputs, c.adj, c.resid + c.n, lp + nblk + nblkc, c.scale);
   } else {
-    if (c.n) hipLaunchKernelGGL(k_res_uncut<3>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale, c.skip_inline);
-    if (c.n && nblkc) hipLaunchKernelGGL(k_res_cut<3>, dim3(nblkc), dim3(64), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale);
+    if (c.n) hipLaunchKernelGGL(k_res_uncut<3>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale, c.skip_inline, c.fpre);
+    if (c.n && nblkc) hipLaunchKernelGGL(k_res_cut<3>, dim3(nblkc), dim3(64), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale, c.fpre);
     if (c.nb) hipLaunchKernelGGL(k_res_bnd<3>, dim3(nblkb), dim3(256), 0, st, c.P, c.meta, c.bpts, c.nb, c.bcls, c.brank, c.outputs, c.adj, c.resid + c.n, lp + nblk + nblkc, c.scale);
   }
   if (c.loss) {
@@ -1103,6 +1146,15 @@ hipError_t launch_residuals(const ResCall& c) {
 hipError_t launch_reduce_loss(hipStream_t st, const double* lossp, int nparts, const Meta* meta,
                               double* loss) {
   hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(256), 0, st, lossp, nparts, meta, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_forcing(hipStream_t st, const Problem& P, const float* pts, int64_t n, float* f) {
+  if (n == 0) return hipSuccess;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_forcing<2>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, n, f);
+  else
+    hipLaunchKernelGGL(k_forcing<3>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, n, f);
   return hipGetLastError();
 }
 

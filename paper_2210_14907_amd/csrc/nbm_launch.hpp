@@ -33,6 +33,7 @@ typedef hipError_t (*MlpFn)(const MlpCall&);
 MlpFn find_mlp(int dim, int width, int act, int prec);
 
 struct FusedCall {
+  const float* fpre;   // precomputed forcing per interior point, or NULL
   hipStream_t stream;
   int grid;
   const Meta* meta;
@@ -54,6 +55,7 @@ typedef hipError_t (*FusedFn)(const FusedCall&);
 FusedFn find_fused(int dim, int width, int depth, int act, int prec);
 
 struct WideCall {
+  const float* fpre;   // precomputed forcing per interior point, or NULL
   hipStream_t stream;
   int grid;
   const Meta* meta;
@@ -118,12 +120,14 @@ struct ResCall {
   double scale;
   int skip_inline;
   int extra_parts;   // loss partials appended after the residual kernels' ones
+  const float* fpre; // precomputed forcing per interior point, or NULL
 };
 hipError_t launch_residuals(const ResCall& c);
 hipError_t launch_reduce_loss(hipStream_t st, const double* lossp, int nparts, const Meta* meta,
                               double* loss);
 
 hipError_t launch_fill(hipStream_t st, float* p, int64_t n, float v);
+hipError_t launch_forcing(hipStream_t st, const Problem& P, const float* pts, int64_t n, float* f);
 hipError_t launch_shadow(hipStream_t st, int prec, const float* params, int64_t off, int W, void* Wl,
                          void* WlT);
 hipError_t launch_reduce_grad(hipStream_t st, const float* partial, int G, int64_t P, float* grad,

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
                                                    const float* adj, float* resid, void* Aout_,
                                                    void* dZout_, int64_t lstride, float* partial,
                                                    int64_t Ptot, NetLayout lay, int64_t net_off1,
-                                                   double* lossp, double scale) {
+                                                   double* lossp, double scale, const float* fpre) {
   typedef typename Op<PREC>::T T;
   constexpr int S = 2 * D + 1;
   constexpr int LD = W + (PREC == 0 ? 4 : 8);
@@ -179,6 +179,17 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           if (r16 == 0) part[w][4 * g + j][s] = v;
         }
       __syncthreads();
+      __shared__ float ftile[kTile];
+      if (inl && fpre) {
+        if (tid < kTile) ftile[tid] = fpre[src[slot0 + tid]];
+      } else if (inl && P.kind == 2) {
+        // Fourier forcing: all threads, scratch in the (free) second row buffer
+        tile_fourier<D, NT>(P, xs, reinterpret_cast<float*>(&bufR[1][0][0][0]), ftile);
+      } else if (inl && tid < kTile) {
+        float x[3] = {xs[tid][0], xs[tid][1], xs[tid][2]};
+        ftile[tid] = f_side<float, D>(P, net, x);
+      }
+      __syncthreads();
       if (tid < kTile) {
         const int c = tid;
         const int64_t slot = slot0 + c;
@@ -186,8 +197,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           float eu = 0.f;
           for (int a = 0; a < D; ++a)
             for (int v = 0; v < NW; ++v) eu += part[v][c][1 + D + a];
-          float x[3] = {xs[c][0], xs[c][1], xs[c][2]};
-          float r = -eu / hh - f_side<float, D>(P, net, x) / (float)P.mu[net];
+          float r = -eu / hh - ftile[c] / (float)P.mu[net];
           resid[src[slot]] = r;
           lsum[c] += (double)r * (double)r;
           float rb = (float)(scale * (double)r);
@@ -373,7 +383,7 @@ template <int D, int W, int L, int ACT, int PREC>
 hipError_t wide_impl(const WideCall& c) {
   hipLaunchKernelGGL((k_wide_fb<D, W, L, ACT, PREC>), dim3(c.grid), dim3(W * 4), 0, c.stream, c.meta,
                      c.centres, c.src, *c.nets, c.P, c.h, c.adj, c.resid, c.A, c.dZ, c.lstride,
-                     c.partial, c.Ptot, *c.lay, c.off1, c.lossp, c.scale);
+                     c.partial, c.Ptot, *c.lay, c.off1, c.lossp, c.scale, c.fpre);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   for (int l = 2; l <= L; ++l) {
