@@ -30,7 +30,7 @@ static int fail(int code, const std::string& msg) {
 namespace {
 struct Layout {
   size_t modes32, modes64, meta, blockcnt, off, blockcnt_b, off_b, cls, rank, bcls, brank, cutidx,
-      centres, src, outputs, adj, Zst, Ast, ALst, dZ, dZw, shadow, partial, lossp, resid, lossbuf, fpre, total;
+      centres, src, outputs, adj, Zst, Ast, ALst, dZ, dZw, shadow, partial, lossp, resid, lossbuf, fpre, fside, total;
 };
 }  // namespace
 
@@ -54,7 +54,7 @@ struct nbm_ctx {
   int64_t per_net, Ptot;
   NetLayout lay;
   int64_t cap_n, cap_nb, cut_cap, cap_slots, cap_tiles, lstride;
-  int G, Gf;
+  int G, Gf, Gfz;
   bool no_fused;
   Layout lo;
   void* prepared_ws;
@@ -125,6 +125,9 @@ static void make_layout(nbm_ctx* c) {
   L.resid = take_tr(sizeof(float) * (c->cap_n + c->cap_nb));
   L.lossbuf = take(sizeof(double) * 4);
   L.fpre = take_tr(c->cfg.problem == NBM_PROB_FOURIER ? sizeof(float) * c->cap_n : 0);
+  // forcing on each uncut point's own side, for the fused paths' inline tiles
+  const bool fused_path = !c->no_fused && (c->fused || c->wide) && !c->eval_only;
+  L.fside = take_tr(fused_path && c->cfg.problem != NBM_PROB_FOURIER ? sizeof(float) * c->cap_n : 0);
   L.total = o;
 }
 
@@ -229,6 +232,7 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
   x->lstride = x->cap_tiles * (int64_t)x->S * x->W * kTile;
   x->G = 512;
   x->Gf = 256;
+  x->Gfz = 512;   // two fused work-groups per compute unit
   x->prepared_ws = nullptr;
   make_layout(x);
   *out = x;
@@ -367,6 +371,14 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
     fpre = at<float>(ws, Lo.fpre);
     if (e == hipSuccess) e = launch_forcing(st, P, pts, n, (float*)fpre);
   }
+  // the fused kernels read the forcing of their uncut centres from here
+  const float* f_inline = fpre;
+  const bool fused_step = grad != nullptr && (ctx->fused != nullptr || ctx->wide != nullptr) && !ctx->no_fused;
+  if (fused_step && !fpre && n > 0) {
+    float* fs = at<float>(ws, Lo.fside);
+    if (e == hipSuccess) e = launch_fside(st, P, pts, pc.cls, n, fs);
+    f_inline = fs;
+  }
   delete tprep;
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("prep: ") + hipGetErrorString(e));
   // network streams at every centre
@@ -427,7 +439,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
     wc.nets = &N; wc.P = P; wc.h = (float)ctx->cfg.h; wc.adj = adj; wc.resid = rc.resid;
     wc.A = at<void>(ws, Lo.Ast); wc.dZ = at<void>(ws, Lo.dZw); wc.lstride = ctx->lstride;
     wc.partial = partial; wc.Ptot = ctx->Ptot; wc.lay = &ctx->lay; wc.off1 = ctx->per_net;
-    wc.lossp = rc.lossp + nres; wc.scale = rc.scale; wc.fpre = fpre;
+    wc.lossp = rc.lossp + nres; wc.scale = rc.scale; wc.fpre = f_inline;
     {
       Timer tb(ctx, st, 3);
       e = ctx->wide(wc);
@@ -440,18 +452,18 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
     int nres = (int)((n + 255) / 256 + (n ? cut_here : 0) + (nb + 255) / 256);
     FusedCall fc;
     std::memset(&fc, 0, sizeof(fc));
-    fc.stream = st; fc.grid = ctx->Gf; fc.meta = pc.meta; fc.centres = pc.centres; fc.src = pc.src;
+    fc.stream = st; fc.grid = ctx->Gfz; fc.meta = pc.meta; fc.centres = pc.centres; fc.src = pc.src;
     fc.nets = &N; fc.P = P; fc.h = (float)ctx->cfg.h; fc.adj = adj; fc.resid = rc.resid;
     fc.partial = partial; fc.Ptot = ctx->Ptot; fc.lay = &ctx->lay; fc.off1 = ctx->per_net;
-    fc.lossp = rc.lossp + nres; fc.scale = rc.scale; fc.fpre = fpre;
+    fc.lossp = rc.lossp + nres; fc.scale = rc.scale; fc.fpre = f_inline;
     {
       Timer tb(ctx, st, 3);
       e = ctx->fused(fc);
     }
     if (e != hipSuccess) return fail(NBM_EHIP, std::string("fused: ") + hipGetErrorString(e));
-    e = launch_reduce_loss(st, rc.lossp, nres + ctx->Gf, pc.meta, loss_out);
+    e = launch_reduce_loss(st, rc.lossp, nres + ctx->Gfz, pc.meta, loss_out);
     if (e != hipSuccess) return fail(NBM_EHIP, std::string("loss: ") + hipGetErrorString(e));
-    Grows = ctx->Gf;
+    Grows = ctx->Gfz;
   } else {
     // backward through the hidden layers, gradient partials
     mc.op = MlpCall::BACKWARD;

@@ -282,17 +282,29 @@ __device__ __forceinline__ void act_bwd_impl(float z, const float* p, const floa
 }
 
 // general paths kept out of line: taken only when some lane has a large
-// difference argument (coarse h), so the common path stays register-lean
+// difference argument (coarse h), so the common path stays register-lean.
+// Scalars in, a small struct out: everything travels in registers.
+struct ActFwdOut { float a, D[3], E[3]; };
+struct ActBwdOut { float zb, pb[3], eb[3]; };
+
 template <int ACT, int D>
-__device__ __attribute__((noinline)) void act_fwd_general(float z, const float* p, const float* e,
-                                                          float& a, float* Dv, float* Ev) {
-  act_fwd_impl<ACT, D, false>(z, p, e, a, Dv, Ev);
+__device__ __attribute__((noinline)) ActFwdOut act_fwd_general(float z, float p0, float p1, float p2,
+                                                               float e0, float e1, float e2) {
+  const float p[3] = {p0, p1, p2}, e[3] = {e0, e1, e2};
+  ActFwdOut r;
+  act_fwd_impl<ACT, D, false>(z, p, e, r.a, r.D, r.E);
+  return r;
 }
 template <int ACT, int D>
-__device__ __attribute__((noinline)) void act_bwd_general(float z, const float* p, const float* e,
-                                                          float ab, const float* Db, const float* Eb,
-                                                          float& zb, float* pb, float* eb) {
-  act_bwd_impl<ACT, D, false>(z, p, e, ab, Db, Eb, zb, pb, eb);
+__device__ __attribute__((noinline)) ActBwdOut act_bwd_general(float z, float p0, float p1, float p2,
+                                                               float e0, float e1, float e2, float ab,
+                                                               float D0, float D1, float D2, float E0,
+                                                               float E1, float E2) {
+  const float p[3] = {p0, p1, p2}, e[3] = {e0, e1, e2};
+  const float Db[3] = {D0, D1, D2}, Eb[3] = {E0, E1, E2};
+  ActBwdOut r;
+  act_bwd_impl<ACT, D, false>(z, p, e, ab, Db, Eb, r.zb, r.pb, r.eb);
+  return r;
 }
 
 // forward: base a, and per-axis D, E from (z, p, e).  One wave-uniform
@@ -300,8 +312,14 @@ __device__ __attribute__((noinline)) void act_bwd_general(float z, const float* 
 template <int ACT, int D>
 __device__ __forceinline__ void act_fwd(float z, const float* p, const float* e, float& a,
                                         float* Dv, float* Ev) {
-  if (__all(fast_args<ACT, D>(p, e))) act_fwd_impl<ACT, D, true>(z, p, e, a, Dv, Ev);
-  else act_fwd_general<ACT, D>(z, p, e, a, Dv, Ev);
+  if (__all(fast_args<ACT, D>(p, e))) {
+    act_fwd_impl<ACT, D, true>(z, p, e, a, Dv, Ev);
+  } else {
+    const ActFwdOut r = act_fwd_general<ACT, D>(z, p[0], D > 1 ? p[1] : 0.f, D > 2 ? p[2] : 0.f, e[0],
+                                                D > 1 ? e[1] : 0.f, D > 2 ? e[2] : 0.f);
+    a = r.a;
+    for (int i = 0; i < D; ++i) { Dv[i] = r.D[i]; Ev[i] = r.E[i]; }
+  }
 }
 
 // backward: given stream adjoints (ab, Db, Eb) return (zb, pb, eb)
@@ -309,8 +327,16 @@ template <int ACT, int D>
 __device__ __forceinline__ void act_bwd(float z, const float* p, const float* e, float ab,
                                         const float* Db, const float* Eb, float& zb, float* pb,
                                         float* eb) {
-  if (__all(fast_args<ACT, D>(p, e))) act_bwd_impl<ACT, D, true>(z, p, e, ab, Db, Eb, zb, pb, eb);
-  else act_bwd_general<ACT, D>(z, p, e, ab, Db, Eb, zb, pb, eb);
+  if (__all(fast_args<ACT, D>(p, e))) {
+    act_bwd_impl<ACT, D, true>(z, p, e, ab, Db, Eb, zb, pb, eb);
+  } else {
+    const ActBwdOut r = act_bwd_general<ACT, D>(
+        z, p[0], D > 1 ? p[1] : 0.f, D > 2 ? p[2] : 0.f, e[0], D > 1 ? e[1] : 0.f, D > 2 ? e[2] : 0.f,
+        ab, Db[0], D > 1 ? Db[1] : 0.f, D > 2 ? Db[2] : 0.f, Eb[0], D > 1 ? Eb[1] : 0.f,
+        D > 2 ? Eb[2] : 0.f);
+    zb = r.zb;
+    for (int i = 0; i < D; ++i) { pb[i] = r.pb[i]; eb[i] = r.eb[i]; }
+  }
 }
 
 // ---------------------------------------------------------------------------

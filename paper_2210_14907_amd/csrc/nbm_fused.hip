@@ -1,8 +1,15 @@
 // Fused forward + residual + backward over difference streams for W = 64
-// networks: one persistent work-group walks 16-centre tiles, keeps every
-// activation of the tile on chip (pre-activations in registers, GEMM operands
-// in LDS in the two layouts the forward and dW contractions need) and
-// accumulates dW in MFMA accumulators; nothing per layer touches HBM.
+// networks.  A persistent work-group of four wavefronts walks 16-centre tiles;
+// two work-groups share a compute unit so that the matrix-core phase of one
+// overlaps the vector (activation) phase of the other.  Nothing per layer
+// touches HBM:
+//   * pre-activations (z and the difference streams) stay in registers;
+//   * the GEMM operands of the current layer sit in LDS in row layout
+//     [stream][centre][neuron], double-buffered between layers;
+//   * activations of the hidden layers are not stored: the backward pass
+//     recomputes them from the kept pre-activations while the matrix cores
+//     form dA = dZ W, and dW^T = A^T dZ then takes A from registers and dZ
+//     from LDS; dW accumulates in MFMA accumulators over all tiles.
 //
 // Tile classes: an "inline" tile holds 16 uncut (class A) centres, whose
 // residual -sum_i eu_i/h^2 - f/mu and adjoints are formed inside the kernel.
@@ -25,11 +32,11 @@ __device__ inline int fused_tile_net(const Meta* m, int t) {
 }
 
 template <int D, int W, int L, int ACT, int PREC>
-__global__ __launch_bounds__(256) void k_fused(const Meta* meta, const float4* centres, const int* src,
-                                               Nets nets, Problem P, float h, const float* adj,
-                                               float* resid, float* partial, int64_t Ptot,
-                                               NetLayout lay, int64_t net_off1, double* lossp,
-                                               double scale, const float* fpre) {
+__global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4* centres, const int* src,
+                                                  Nets nets, Problem P, float h, const float* adj,
+                                                  float* resid, float* partial, int64_t Ptot,
+                                                  NetLayout lay, int64_t net_off1, double* lossp,
+                                                  double scale, const float* fpre) {
   typedef typename Op<PREC>::T T;
   constexpr int S = 2 * D + 1;
   constexpr int LD = W + (PREC == 0 ? 4 : 8);
@@ -37,14 +44,13 @@ __global__ __launch_bounds__(256) void k_fused(const Meta* meta, const float4* c
   constexpr int KC = W / 4;         // K chunk per lane group
   static_assert(NOB == 4, "one 16-neuron block per wave");
   __shared__ __attribute__((aligned(16))) T bufR[2][S][kTile][LD];      // row layout [c][n]
-  constexpr int CP = kTile + (PREC == 0 ? 4 : 8);   // padded column stride
-  __shared__ __attribute__((aligned(16))) T colA[L - 1][S][W][CP];      // column layout [n][c]
-  __shared__ __attribute__((aligned(16))) float colL[S][W][kTile];   // last-layer activations (FP32)
+  // BF16 only: dZ also as [neuron][centre][stream (7 + zero)], the dW operand
+  // (8 K values per lane = the streams of one centre); the odd centre stride
+  // spreads the 16 neurons of a read over the banks
+  constexpr bool kColZ = PREC == 1;
+  __shared__ __attribute__((aligned(16))) T colZ[2][kColZ ? W : 1][kColZ ? kTile + 1 : 1][8];
+  __shared__ float part[NOB][kTile][8];
   __shared__ float adjs[kTile][8];
-  // output-layer partial sums live in the row buffers, free between the last
-  // forward layer and the first backward write
-  float (*part)[kTile][8] = reinterpret_cast<float (*)[kTile][8]>(&bufR[0][0][0][0]);
-  static_assert(sizeof(bufR) >= 4 * kTile * 8 * sizeof(float), "partials fit the row buffers");
   __shared__ float xs[kTile][4];
   __shared__ double lsum[kTile];
   __shared__ int tflag;
@@ -58,7 +64,7 @@ __global__ __launch_bounds__(256) void k_fused(const Meta* meta, const float4* c
 
   for (int net = 0; net < 2; ++net) {
     const NetPtrs& np = nets.net[net];
-    f4 accW[L - 1][NOB];
+    f4 accW[L - 1][NOB];   // dW_l^T blocks: rows = inputs of block w, cols = outputs of block ob
     float accb[L], accW1[3] = {0.f, 0.f, 0.f}, accwo = 0.f, accbo = 0.f;
     for (int l = 0; l < L - 1; ++l)
       for (int k = 0; k < NOB; ++k) accW[l][k] = f4{0.f, 0.f, 0.f, 0.f};
@@ -67,42 +73,45 @@ __global__ __launch_bounds__(256) void k_fused(const Meta* meta, const float4* c
     for (int a = 0; a < D; ++a) { W1n[a] = np.W1[n * D + a]; p1[a] = h * W1n[a]; }
     const float b1n = np.b1[n], won = np.wout[n];
     const int64_t a_end = (int64_t)meta->base[net][KIND_A] + meta->cnt[net][KIND_A];
+    const int t_lo = net == 0 ? 0 : meta->tiles[0];
+    const int t_hi = net == 0 ? meta->tiles[0] : ntiles;
 
-    for (int t = blockIdx.x; t < ntiles; t += G) {
-      if (fused_tile_net(meta, t) != net) continue;
+    for (int t = t_lo + blockIdx.x; t < t_hi; t += G) {
       const int64_t slot0 = (int64_t)t * kTile;
       const int64_t slot_end = (int64_t)meta->tile0[net] * kTile + meta->total[net];
+      const bool inl = slot0 + kTile <= a_end;   // uniform over the work-group
       if (tid < kTile) {
         float4 cc = centres[slot0 + tid];
         if (slot0 + tid >= slot_end) cc = make_float4(0.f, 0.f, 0.f, 0.f);
         xs[tid][0] = cc.x; xs[tid][1] = cc.y; xs[tid][2] = cc.z; xs[tid][3] = 0.f;
       }
-      if (tid == 0) tflag = (slot0 + kTile <= a_end) ? 1 : 0;
+      if (!inl && tid < kTile * 8) {
+        // output adjoints of a non-inline tile, written by the residual kernels
+        const int64_t slot = slot0 + tid / 8;
+        adjs[tid / 8][tid % 8] = slot < slot_end ? adj[slot0 * 8 + tid] : 0.f;
+      }
       __syncthreads();
-      const bool inl = tflag != 0;
 
       // ---------------- forward, layer 1 (VALU, accumulator mapping)
       float z1[4];
       for (int j = 0; j < 4; ++j) {
-        int c = 4 * g + j;
+        const int c = 4 * g + j;
         float z = b1n;
         for (int a = 0; a < D; ++a) z += W1n[a] * xs[c][a];
         z1[j] = z;
         float av, Dv[3], Ev[3];
         act_fwd<ACT, D>(z, p1, e0, av, Dv, Ev);
-        float vals[7];
-        vals[0] = av;
-        for (int a = 0; a < D; ++a) { vals[1 + a] = Dv[a]; vals[1 + D + a] = Ev[a]; }
-        for (int s = 0; s < S; ++s) {
-          T v = from_f<T>(vals[s]);
-          bufR[0][s][c][n] = v;
-          colA[0][s][n][c] = v;
+        bufR[0][0][c][n] = from_f<T>(av);
+        for (int a = 0; a < D; ++a) {
+          bufR[0][1 + a][c][n] = from_f<T>(Dv[a]);
+          bufR[0][1 + D + a][c][n] = from_f<T>(Ev[a]);
         }
       }
       __syncthreads();
 
       // ---------------- forward, hidden layers on MFMA
       float Z[L - 1][S][4];   // pre-activations of layers 2..L for (centres 4g+j, neuron n)
+      float eS[4];            // last layer, inline tiles: sum over axes of the E streams
       int cur = 0;
 #pragma unroll
       for (int l = 2; l <= L; ++l) {
@@ -137,71 +146,63 @@ __global__ __launch_bounds__(256) void k_fused(const Meta* meta, const float4* c
         const float bias = np.bl[l - 2][n];
         const bool last = (l == L);
         for (int j = 0; j < 4; ++j) {
-          int c = 4 * g + j;
+          const int c = 4 * g + j;
           float z = acc[0][j] + bias;
           float pp[3], ee[3], av, Dv[3], Ev[3];
           for (int a = 0; a < D; ++a) { pp[a] = acc[1 + a][j]; ee[a] = acc[1 + D + a][j]; }
           act_fwd<ACT, D>(z, pp, ee, av, Dv, Ev);
-          float vals[7];
-          vals[0] = av;
-          for (int a = 0; a < D; ++a) { vals[1 + a] = Dv[a]; vals[1 + D + a] = Ev[a]; }
           Z[l - 2][0][j] = z;
           for (int s = 1; s < S; ++s) Z[l - 2][s][j] = acc[s][j];
           if (!last) {
-            for (int s = 0; s < S; ++s) {
-              T v = from_f<T>(vals[s]);
-              bufR[cur ^ 1][s][c][n] = v;
-              colA[l - 1][s][n][c] = v;
+            bufR[cur ^ 1][0][c][n] = from_f<T>(av);
+            for (int a = 0; a < D; ++a) {
+              bufR[cur ^ 1][1 + a][c][n] = from_f<T>(Dv[a]);
+              bufR[cur ^ 1][1 + D + a][c][n] = from_f<T>(Ev[a]);
             }
           } else {
-            for (int s = 0; s < S; ++s) colL[s][n][c] = vals[s];
+            // output layer: u = sum_n w_out[n] a_L[n] (+ b_out), per stream
+            float vals[7];
+            vals[0] = av;
+            for (int a = 0; a < D; ++a) { vals[1 + a] = Dv[a]; vals[1 + D + a] = Ev[a]; }
+            for (int s = 0; s < S; ++s) {
+              float v = won * vals[s];
+              v += __shfl_xor(v, 8);
+              v += __shfl_xor(v, 4);
+              v += __shfl_xor(v, 2);
+              v += __shfl_xor(v, 1);
+              if (r16 == 0) part[w][c][s] = v;
+            }
+            // d loss / d w_out[n] = sum_c sum_s adj[c][s] a_L[s][n][c]; inline
+            // tiles carry one adjoint on all E streams, known after the residual
+            if (inl) {
+              float es = 0.f;
+              for (int a = 0; a < D; ++a) es += Ev[a];
+              eS[j] = es;
+            } else {
+              for (int s = 0; s < S; ++s) accwo += adjs[c][s] * vals[s];
+            }
           }
         }
         __syncthreads();
         cur ^= 1;
       }
 
-      // ---------------- output layer and residual / adjoints
-      for (int s = 0; s < S; ++s)
-        for (int j = 0; j < 4; ++j) {
-          float v = won * colL[s][n][4 * g + j];
-          v += __shfl_xor(v, 8);
-          v += __shfl_xor(v, 4);
-          v += __shfl_xor(v, 2);
-          v += __shfl_xor(v, 1);
-          if (r16 == 0) part[w][4 * g + j][s] = v;
-        }
-      __syncthreads();
-      __shared__ float ftile[kTile];
-      if (inl && fpre) {
-        if (tid < kTile) ftile[tid] = fpre[src[slot0 + tid]];
-      } else if (inl && P.kind == 2) {
-        // Fourier forcing: all threads, scratch in the (free) second row buffer
-        tile_fourier<D, 256>(P, xs, reinterpret_cast<float*>(&bufR[1][0][0][0]), ftile);
-      } else if (inl && tid < kTile) {
-        float x[3] = {xs[tid][0], xs[tid][1], xs[tid][2]};
-        ftile[tid] = f_side<float, D>(P, net, x);
-      }
-      __syncthreads();
-      if (tid < kTile) {
+      // ---------------- residual / adjoints of inline tiles
+      if (inl && tid < kTile) {
         const int c = tid;
         const int64_t slot = slot0 + c;
-        if (inl) {
-          float eu = 0.f;
-          for (int a = 0; a < D; ++a)
-            for (int v = 0; v < 4; ++v) eu += part[v][c][1 + D + a];
-          float r = -eu / hh - ftile[c] / (float)P.mu[net];
-          resid[src[slot]] = r;
-          lsum[c] += (double)r * (double)r;
-          float rb = (float)(scale * (double)r);
-          for (int s = 0; s < 8; ++s) adjs[c][s] = 0.f;
-          for (int a = 0; a < D; ++a) adjs[c][1 + D + a] = -rb / hh;
-        } else {
-          const bool valid = slot < slot_end;
-          for (int s = 0; s < 8; ++s) adjs[c][s] = valid ? adj[slot * 8 + s] : 0.f;
-        }
+        const float f = fpre[src[slot]];
+        float eu = 0.f;
+        for (int a = 0; a < D; ++a)
+          for (int v = 0; v < NOB; ++v) eu += part[v][c][1 + D + a];
+        float r = -eu / hh - f / (float)P.mu[net];
+        resid[src[slot]] = r;
+        lsum[c] += (double)r * (double)r;
+        float rb = (float)(scale * (double)r);
+        for (int s = 0; s < 8; ++s) adjs[c][s] = 0.f;
+        for (int a = 0; a < D; ++a) adjs[c][1 + D + a] = -rb / hh;
       }
-      __syncthreads();
+      if (inl) __syncthreads();
 
       // ---------------- backward, top layer
       float dz[S][4];
@@ -215,20 +216,29 @@ __global__ __launch_bounds__(256) void k_fused(const Meta* meta, const float4* c
         act_bwd<ACT, D>(Z[L - 2][0][j], pp, ee, won * adjs[c][0], Db, Eb, zb, pb, eb);
         dz[0][j] = zb;
         for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
-        for (int s = 0; s < S; ++s) accwo += adjs[c][s] * colL[s][n][c];
+        if (inl) accwo += adjs[c][1 + D] * eS[j];
       }
       if (tid == 0)
         for (int c = 0; c < kTile; ++c) accbo += adjs[c][0];
 
-      // ---------------- backward through the hidden layers.  Per layer: dZ_l
-      // goes to LDS in row layout, dA = dZ_l W_l runs on MFMA, then the dW_l
-      // MFMAs (independent of dA) are issued next to the VALU derivative
-      // epilogue of layer l-1 so that the two can overlap.
+      // ---------------- backward through the hidden layers.  Per layer l:
+      // dZ_l goes to LDS; dA_{l-1} = dZ_l W_l runs on the matrix cores while
+      // the VALU recomputes A_{l-1} from the kept pre-activations; then the
+      // dW_l^T = A_{l-1}^T dZ_l MFMAs run next to the derivative epilogue.
+      int bb = 0;
 #pragma unroll
       for (int l = L; l >= 2; --l) {
         for (int j = 0; j < 4; ++j) accb[l - 1] += dz[0][j];
         for (int s = 0; s < S; ++s)
-          for (int j = 0; j < 4; ++j) bufR[0][s][4 * g + j][n] = from_f<T>(dz[s][j]);
+          for (int j = 0; j < 4; ++j) bufR[bb][s][4 * g + j][n] = from_f<T>(dz[s][j]);
+        if constexpr (kColZ) {
+          for (int j = 0; j < 4; ++j) {
+            bf8 v;
+            for (int k = 0; k < S; ++k) v[k] = (__bf16)dz[k][j];
+            for (int k = S; k < 8; ++k) v[k] = (__bf16)0.f;
+            *(bf8*)(&colZ[bb][n][4 * g + j][0]) = v;
+          }
+        }
         __syncthreads();
         f4 acc[S];
         for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
@@ -240,7 +250,7 @@ __global__ __launch_bounds__(256) void k_fused(const Meta* meta, const float4* c
             bk[4 * q] = v4.x; bk[4 * q + 1] = v4.y; bk[4 * q + 2] = v4.z; bk[4 * q + 3] = v4.w;
           }
           for (int s = 0; s < S; ++s) {
-            const float4* ap = (const float4*)(&bufR[0][s][r16][g * KC]);
+            const float4* ap = (const float4*)(&bufR[bb][s][r16][g * KC]);
             for (int q = 0; q < KC / 4; ++q) {
               float4 a4 = ap[q];
               acc[s] = mfma4(a4.x, bk[4 * q], acc[s]);
@@ -254,67 +264,67 @@ __global__ __launch_bounds__(256) void k_fused(const Meta* meta, const float4* c
           const bf8* wp = (const bf8*)((const T*)np.WlT[l - 2] + (int64_t)n * W + g * KC);
           for (int q = 0; q < KC / 8; ++q) bk[q] = wp[q];
           for (int s = 0; s < S; ++s) {
-            const bf8* ap = (const bf8*)(&bufR[0][s][r16][g * KC]);
+            const bf8* ap = (const bf8*)(&bufR[bb][s][r16][g * KC]);
             for (int q = 0; q < KC / 8; ++q) acc[s] = mfma32(ap[q], bk[q], acc[s]);
           }
         }
-        // dW_l[n][:] += sum over (stream, centre) of dZ_l[.][n] A_{l-1}[.][:]
-        for (int ib = 0; ib < NOB; ++ib) {
-          const int nin = ib * 16 + r16;
-          if constexpr (PREC == 0) {
-            for (int s = 0; s < S; ++s) {
-              float4 v = *(const float4*)(&colA[l - 2][s][nin][4 * g]);
-              accW[l - 2][ib] = mfma4(dz[s][0], v.x, accW[l - 2][ib]);
-              accW[l - 2][ib] = mfma4(dz[s][1], v.y, accW[l - 2][ib]);
-              accW[l - 2][ib] = mfma4(dz[s][2], v.z, accW[l - 2][ib]);
-              accW[l - 2][ib] = mfma4(dz[s][3], v.w, accW[l - 2][ib]);
-            }
+        // per centre j: A_{l-1} recomputed from its pre-activations (layer 1:
+        // from z1), then dW_l^T[n_in][n_out] += sum over streams of
+        // A[.][n_in] dZ[.][n_out]; the VALU work of centre j+1 overlaps the
+        // matrix-core work of centre j
+        for (int j = 0; j < 4; ++j) {
+          float av[S], Dv[3], Ev[3];
+          if (l > 2) {
+            float pp[3], ee[3];
+            for (int a = 0; a < D; ++a) { pp[a] = Z[l - 3][1 + a][j]; ee[a] = Z[l - 3][1 + D + a][j]; }
+            act_fwd<ACT, D>(Z[l - 3][0][j], pp, ee, av[0], Dv, Ev);
           } else {
-            for (int s = 0; s < S; s += 2) {
-              bf4 v0 = *(const bf4*)(&colA[l - 2][s][nin][4 * g]);
-              bf4 v1 = (s + 1 < S) ? *(const bf4*)(&colA[l - 2][s + 1][nin][4 * g])
-                                   : bf4{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
-              bf8 av, bv;
-              for (int j = 0; j < 4; ++j) {
-                av[j] = (__bf16)dz[s][j];
-                av[4 + j] = (s + 1 < S) ? (__bf16)dz[s + 1][j] : (__bf16)0.f;
-                bv[j] = v0[j];
-                bv[4 + j] = v1[j];
-              }
-              accW[l - 2][ib] = mfma32(av, bv, accW[l - 2][ib]);
+            act_fwd<ACT, D>(z1[j], p1, e0, av[0], Dv, Ev);
+          }
+          for (int a = 0; a < D; ++a) { av[1 + a] = Dv[a]; av[1 + D + a] = Ev[a]; }
+          if constexpr (PREC == 0) {
+            for (int ob = 0; ob < NOB; ++ob)
+              for (int s = 0; s < S; ++s)
+                accW[l - 2][ob] = mfma4(av[s], bufR[bb][s][4 * g + j][ob * 16 + r16], accW[l - 2][ob]);
+          } else {
+            // K = 8 per MFMA: the seven streams of centre 4g+j and a zero
+            bf8 aop;
+            for (int k = 0; k < S; ++k) aop[k] = (__bf16)av[k];
+            for (int k = S; k < 8; ++k) aop[k] = (__bf16)0.f;
+            for (int ob = 0; ob < NOB; ++ob) {
+              const bf8 bop = *(const bf8*)(&colZ[bb][ob * 16 + r16][4 * g + j][0]);
+              accW[l - 2][ob] = mfma32(aop, bop, accW[l - 2][ob]);
             }
           }
         }
-        // derivative epilogue of layer l-1 (pre-activations kept in registers)
+        // derivative epilogue of layer l-1
         for (int j = 0; j < 4; ++j) {
           float pp[3], ee[3], Db[3], Eb[3], zb, pb[3], eb[3];
+          for (int a = 0; a < D; ++a) { Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j]; }
           if (l > 2) {
-            for (int a = 0; a < D; ++a) {
-              pp[a] = Z[l - 3][1 + a][j]; ee[a] = Z[l - 3][1 + D + a][j];
-              Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j];
-            }
+            for (int a = 0; a < D; ++a) { pp[a] = Z[l - 3][1 + a][j]; ee[a] = Z[l - 3][1 + D + a][j]; }
             act_bwd<ACT, D>(Z[l - 3][0][j], pp, ee, acc[0][j], Db, Eb, zb, pb, eb);
             dz[0][j] = zb;
             for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
           } else {
-            for (int a = 0; a < D; ++a) { Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j]; }
             act_bwd<ACT, D>(z1[j], p1, e0, acc[0][j], Db, Eb, zb, pb, eb);
             const int c = 4 * g + j;
             accb[0] += zb;
             for (int a = 0; a < D; ++a) accW1[a] += zb * xs[c][a] + h * pb[a];
           }
         }
-        __syncthreads();   // bufR[0] is rewritten by the next layer
+        bb ^= 1;   // the other row buffer: no barrier needed before the next write
       }
+      __syncthreads();   // xs, adjs and the row buffers are rewritten by the next tile
     }
 
     // ---------------- flush this net's partial gradient
     float* prow = partial + (int64_t)blockIdx.x * Ptot + (net == 0 ? 0 : net_off1);
     for (int l = 2; l <= L; ++l)
-      for (int ib = 0; ib < NOB; ++ib)
+      for (int ob = 0; ob < NOB; ++ob)
         for (int r = 0; r < 4; ++r) {
-          int row = w * 16 + 4 * g + r, col = ib * 16 + r16;
-          prow[lay.Wl[l - 2] + (int64_t)row * W + col] = accW[l - 2][ib][r];
+          const int nin = w * 16 + 4 * g + r, nout = ob * 16 + r16;
+          prow[lay.Wl[l - 2] + (int64_t)nout * W + nin] = accW[l - 2][ob][r];
         }
     for (int l = 0; l < L; ++l) {
       float v = accb[l];

@@ -1149,6 +1149,29 @@ hipError_t launch_reduce_loss(hipStream_t st, const double* lossp, int nparts, c
   return hipGetLastError();
 }
 
+// Forcing f/1 on the side of each uncut point (class 0: Omega^-, class 1:
+// Omega^+), for the fused kernels' inline tiles; cut points are left 0.
+template <int D>
+__global__ __launch_bounds__(256) void k_fside(Problem P, const float* pts, const int* cls, int64_t n,
+                                               float* fout) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int c = cls[i];
+  float x[3] = {0.f, 0.f, 0.f};
+  for (int a = 0; a < D; ++a) x[a] = pts[i * D + a];
+  fout[i] = c < 2 ? f_side<float, D>(P, c, x) : 0.0f;
+}
+
+hipError_t launch_fside(hipStream_t st, const Problem& P, const float* pts, const int* cls, int64_t n,
+                        float* f) {
+  if (n == 0) return hipSuccess;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_fside<2>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, cls, n, f);
+  else
+    hipLaunchKernelGGL(k_fside<3>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, cls, n, f);
+  return hipGetLastError();
+}
+
 hipError_t launch_forcing(hipStream_t st, const Problem& P, const float* pts, int64_t n, float* f) {
   if (n == 0) return hipSuccess;
   if (P.dim == 2)

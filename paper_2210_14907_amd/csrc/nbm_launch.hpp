@@ -33,7 +33,7 @@ typedef hipError_t (*MlpFn)(const MlpCall&);
 MlpFn find_mlp(int dim, int width, int act, int prec);
 
 struct FusedCall {
-  const float* fpre;   // precomputed forcing per interior point, or NULL
+  const float* fpre;   // forcing per interior point on its own side (read for uncut centres)
   hipStream_t stream;
   int grid;
   const Meta* meta;
@@ -55,7 +55,7 @@ typedef hipError_t (*FusedFn)(const FusedCall&);
 FusedFn find_fused(int dim, int width, int depth, int act, int prec);
 
 struct WideCall {
-  const float* fpre;   // precomputed forcing per interior point, or NULL
+  const float* fpre;   // forcing per interior point on its own side (read for uncut centres)
   hipStream_t stream;
   int grid;
   const Meta* meta;
@@ -128,6 +128,8 @@ hipError_t launch_reduce_loss(hipStream_t st, const double* lossp, int nparts, c
 
 hipError_t launch_fill(hipStream_t st, float* p, int64_t n, float v);
 hipError_t launch_forcing(hipStream_t st, const Problem& P, const float* pts, int64_t n, float* f);
+hipError_t launch_fside(hipStream_t st, const Problem& P, const float* pts, const int* cls, int64_t n,
+                        float* f);
 hipError_t launch_shadow(hipStream_t st, int prec, const float* params, int64_t off, int W, void* Wl,
                          void* WlT);
 hipError_t launch_reduce_grad(hipStream_t st, const float* partial, int G, int64_t P, float* grad,

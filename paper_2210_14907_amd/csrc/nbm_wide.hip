@@ -179,17 +179,6 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           if (r16 == 0) part[w][4 * g + j][s] = v;
         }
       __syncthreads();
-      __shared__ float ftile[kTile];
-      if (inl && fpre) {
-        if (tid < kTile) ftile[tid] = fpre[src[slot0 + tid]];
-      } else if (inl && P.kind == 2) {
-        // Fourier forcing: all threads, scratch in the (free) second row buffer
-        tile_fourier<D, NT>(P, xs, reinterpret_cast<float*>(&bufR[1][0][0][0]), ftile);
-      } else if (inl && tid < kTile) {
-        float x[3] = {xs[tid][0], xs[tid][1], xs[tid][2]};
-        ftile[tid] = f_side<float, D>(P, net, x);
-      }
-      __syncthreads();
       if (tid < kTile) {
         const int c = tid;
         const int64_t slot = slot0 + c;
@@ -197,7 +186,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           float eu = 0.f;
           for (int a = 0; a < D; ++a)
             for (int v = 0; v < NW; ++v) eu += part[v][c][1 + D + a];
-          float r = -eu / hh - ftile[c] / (float)P.mu[net];
+          float r = -eu / hh - fpre[src[slot]] / (float)P.mu[net];
           resid[src[slot]] = r;
           lsum[c] += (double)r * (double)r;
           float rb = (float)(scale * (double)r);
