@@ -23,6 +23,14 @@ __device__ __forceinline__ f4 mfma32(bf8 a, bf8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// Wave priority around matrix-core clusters.  Two work-groups share each
+// SIMD and run the same sequence; with equal priority they enter their MFMA
+// and VALU phases in step.  The wave issuing its MFMA block at raised
+// priority keeps the matrix core, the other falls into its VALU phase, and
+// the two units overlap instead of alternating.
+__device__ __forceinline__ void mfma_phase_begin() { __builtin_amdgcn_s_setprio(1); }
+__device__ __forceinline__ void mfma_phase_end() { __builtin_amdgcn_s_setprio(0); }
+
 template <int PREC> struct Op;
 template <> struct Op<0> { typedef float T; static constexpr int bytes = 4; };
 template <> struct Op<1> { typedef __bf16 T; static constexpr int bytes = 2; };
@@ -224,7 +232,10 @@ __device__ __forceinline__ void act_fwd_impl(float z, const float* p, const floa
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       TanhAxis f = tanh_axis<FAST>(p[i], e[i]);
-      float rP = rcp(1.0f + t * f.Tp), rM = rcp(1.0f - t * f.Tm);
+      // 1/(1 + t T_p) and 1/(1 - t T_m) from one reciprocal of their product
+      float dP = 1.0f + t * f.Tp, dM = 1.0f - t * f.Tm;
+      float R = rcp(dP * dM);
+      float rP = dM * R, rM = dP * R;
       float qP = q * rP;
       Dv[i] = f.Tp * qP;
       Ev[i] = qP * (f.Te * (1.0f - f.Tp * f.Tm) - t * f.Tm * f.Ts * (1.0f + f.Tp * f.Tm) * rM);
@@ -264,7 +275,9 @@ __device__ __forceinline__ void act_bwd_impl(float z, const float* p, const floa
     for (int i = 0; i < D; ++i) {
       TanhAxis f = tanh_axis<FAST>(p[i], e[i]);
       float Tp = f.Tp, Tm = f.Tm;
-      float rP = rcp(1.0f + t * Tp), rM = rcp(1.0f - t * Tm);
+      float dP = 1.0f + t * Tp, dM = 1.0f - t * Tm;
+      float R = rcp(dP * dM);
+      float rP = dM * R, rM = dP * R;
       float qP = q * rP, qM = q * rM;
       float Dd = Tp * qP;
       float Bd = Tm * qM;
@@ -277,6 +290,97 @@ __device__ __forceinline__ void act_bwd_impl(float z, const float* p, const floa
       zb += Db[i] * dDdz + Eb[i] * dEdz;
       pb[i] = Db[i] * dDdp + Eb[i] * dEdp;
       eb[i] = Eb[i] * dEde;
+    }
+  }
+}
+
+// First layer: the differences p = h W1[n] are constants of the network and
+// e = 0 (so m = p), hence the per-axis factors (tanh: T_p, T_{2p}; sin:
+// sin(p/2), cos(p/2)) are computed once per network and each centre only
+// needs its base evaluation.  The stream formulas below are those above with
+// e = 0 substituted.
+struct L1Axes { float u[3], v[3]; };
+
+template <int ACT, int D>
+__device__ inline L1Axes l1_axes(const float* p) {
+  L1Axes r;
+  for (int i = 0; i < 3; ++i) { r.u[i] = 0.f; r.v[i] = 0.f; }
+  for (int i = 0; i < D; ++i) {
+    if (ACT == 1) {
+      sincos_small(0.5f * p[i], &r.u[i], &r.v[i]);
+    } else {
+      r.u[i] = tanh_small(p[i]);
+      r.v[i] = tanh_small(2.0f * p[i]);
+    }
+  }
+  return r;
+}
+
+template <int ACT, int D>
+__device__ __forceinline__ void act_fwd_l1(float z, const L1Axes& f, float& a, float* Dv, float* Ev) {
+  if (ACT == 1) {
+    float S, C;
+    sincos_base(z, &S, &C);
+    a = S;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const float sp = f.u[i], cp = f.v[i];
+      Dv[i] = 2.0f * sp * (C * cp - S * sp);
+      Ev[i] = -4.0f * S * sp * sp;
+    }
+  } else {
+    TanhBase tb = tanh_base(z);
+    const float t = tb.t, q = tb.q;
+    a = t;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const float Tp = f.u[i], Ts = f.v[i];
+      const float dP = 1.0f + t * Tp, dM = 1.0f - t * Tp;
+      const float R = rcp(dP * dM);
+      const float qP = q * dM * R, rM = dP * R;
+      Dv[i] = Tp * qP;
+      Ev[i] = -qP * t * Tp * Ts * (1.0f + Tp * Tp) * rM;
+    }
+  }
+}
+
+template <int ACT, int D>
+__device__ __forceinline__ void act_bwd_l1(float z, const L1Axes& f, float ab, const float* Db,
+                                           const float* Eb, float& zb, float* pb) {
+  if (ACT == 1) {
+    float S, C;
+    sincos_base(z, &S, &C);
+    zb = ab * C;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const float sp = f.u[i], cp = f.v[i];
+      const float dDdz = -2.0f * sp * (S * cp + C * sp);
+      const float dDdp = C * (1.0f - 2.0f * sp * sp) - S * (2.0f * sp * cp);
+      const float dEdz = -4.0f * C * sp * sp;
+      const float dEdp = -4.0f * S * sp * cp;
+      zb += Db[i] * dDdz + Eb[i] * dEdz;
+      pb[i] = Db[i] * dDdp + Eb[i] * dEdp;
+    }
+  } else {
+    TanhBase tb = tanh_base(z);
+    const float t = tb.t, q = tb.q;
+    zb = ab * q;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const float Tp = f.u[i], Ts = f.v[i];
+      const float dP = 1.0f + t * Tp, dM = 1.0f - t * Tp;
+      const float R = rcp(dP * dM);
+      const float rP = dM * R, rM = dP * R;
+      const float qP = q * rP, qM = q * rM;
+      const float Dd = Tp * qP;
+      const float Bd = Tp * qM;
+      const float Ed = -qP * t * Tp * Ts * (1.0f + Tp * Tp) * rM;
+      const float dDdz = -Dd * (2.0f * t + Dd);
+      const float dDdp = qP * (1.0f - Tp * Tp) * rP;
+      const float dEdz = -2.0f * t * Ed - Dd * Dd - Bd * Bd;
+      const float dEdp = -(Dd + Bd) * (2.0f * t + Ed);
+      zb += Db[i] * dDdz + Eb[i] * dEdz;
+      pb[i] = Db[i] * dDdp + Eb[i] * dEdp;
     }
   }
 }
@@ -337,6 +441,52 @@ __device__ __forceinline__ void act_bwd(float z, const float* p, const float* e,
     zb = r.zb;
     for (int i = 0; i < D; ++i) { pb[i] = r.pb[i]; eb[i] = r.eb[i]; }
   }
+}
+
+// Forward and backward streams of one (z, p, e) together: the per-axis
+// factors are formed once and shared (used where the adjoints are at hand
+// when the activations are evaluated, or where the backward pass recomputes
+// the activations it needs).
+struct ActFBOut { float a, D[3], E[3], zb, pb[3], eb[3]; };
+
+template <int ACT, int D>
+__device__ __attribute__((noinline)) ActFBOut act_fb_general(float z, float p0, float p1, float p2,
+                                                             float e0, float e1, float e2, float ab,
+                                                             float D0, float D1, float D2, float E0,
+                                                             float E1, float E2) {
+  const float p[3] = {p0, p1, p2}, e[3] = {e0, e1, e2};
+  const float Db[3] = {D0, D1, D2}, Eb[3] = {E0, E1, E2};
+  ActFBOut r;
+  act_fwd_impl<ACT, D, false>(z, p, e, r.a, r.D, r.E);
+  act_bwd_impl<ACT, D, false>(z, p, e, ab, Db, Eb, r.zb, r.pb, r.eb);
+  return r;
+}
+
+template <int ACT, int D>
+__device__ __forceinline__ void act_fb(float z, const float* p, const float* e, float ab,
+                                       const float* Db, const float* Eb, float& a, float* Dv,
+                                       float* Ev, float& zb, float* pb, float* eb) {
+  if (__all(fast_args<ACT, D>(p, e))) {
+    act_fwd_impl<ACT, D, true>(z, p, e, a, Dv, Ev);
+    act_bwd_impl<ACT, D, true>(z, p, e, ab, Db, Eb, zb, pb, eb);
+  } else {
+    const ActFBOut r = act_fb_general<ACT, D>(
+        z, p[0], D > 1 ? p[1] : 0.f, D > 2 ? p[2] : 0.f, e[0], D > 1 ? e[1] : 0.f, D > 2 ? e[2] : 0.f,
+        ab, Db[0], D > 1 ? Db[1] : 0.f, D > 2 ? Db[2] : 0.f, Eb[0], D > 1 ? Eb[1] : 0.f,
+        D > 2 ? Eb[2] : 0.f);
+    a = r.a;
+    zb = r.zb;
+    for (int i = 0; i < D; ++i) { Dv[i] = r.D[i]; Ev[i] = r.E[i]; pb[i] = r.pb[i]; eb[i] = r.eb[i]; }
+  }
+}
+
+// first layer, forward and backward together (e = 0, constant axis factors)
+template <int ACT, int D>
+__device__ __forceinline__ void act_fb_l1(float z, const L1Axes& f, float ab, const float* Db,
+                                          const float* Eb, float& a, float* Dv, float* Ev, float& zb,
+                                          float* pb) {
+  act_fwd_l1<ACT, D>(z, f, a, Dv, Ev);
+  act_bwd_l1<ACT, D>(z, f, ab, Db, Eb, zb, pb);
 }
 
 // ---------------------------------------------------------------------------

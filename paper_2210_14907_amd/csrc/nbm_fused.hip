@@ -52,6 +52,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
   __shared__ float part[NOB][kTile][8];
   __shared__ float adjs[kTile][8];
   __shared__ float xs[kTile][4];
+  __shared__ L1Axes l1ax[W];
   __shared__ double lsum[kTile];
   __shared__ int tflag;
 
@@ -69,8 +70,11 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
     for (int l = 0; l < L - 1; ++l)
       for (int k = 0; k < NOB; ++k) accW[l][k] = f4{0.f, 0.f, 0.f, 0.f};
     for (int l = 0; l < L; ++l) accb[l] = 0.f;
-    float W1n[3], p1[3], e0[3] = {0.f, 0.f, 0.f};
+    float W1n[3], p1[3];
     for (int a = 0; a < D; ++a) { W1n[a] = np.W1[n * D + a]; p1[a] = h * W1n[a]; }
+    // first-layer axis factors, constant per net: kept in LDS, not registers
+    if (g == 0) l1ax[n] = l1_axes<ACT, D>(p1);
+    __syncthreads();
     const float b1n = np.b1[n], won = np.wout[n];
     const int64_t a_end = (int64_t)meta->base[net][KIND_A] + meta->cnt[net][KIND_A];
     const int t_lo = net == 0 ? 0 : meta->tiles[0];
@@ -100,7 +104,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
         for (int a = 0; a < D; ++a) z += W1n[a] * xs[c][a];
         z1[j] = z;
         float av, Dv[3], Ev[3];
-        act_fwd<ACT, D>(z, p1, e0, av, Dv, Ev);
+        act_fwd_l1<ACT, D>(z, l1ax[n], av, Dv, Ev);
         bufR[0][0][c][n] = from_f<T>(av);
         for (int a = 0; a < D; ++a) {
           bufR[0][1 + a][c][n] = from_f<T>(Dv[a]);
@@ -110,13 +114,17 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
       __syncthreads();
 
       // ---------------- forward, hidden layers on MFMA
-      float Z[L - 1][S][4];   // pre-activations of layers 2..L for (centres 4g+j, neuron n)
+      // pre-activations of layers 2..L-1 for (centres 4g+j, neuron n); the
+      // last layer's backward is formed in its forward epilogue instead
+      float Z[L > 2 ? L - 2 : 1][S][4];
+      float dz[S][4];         // dZ of the layer being differentiated
       float eS[4];            // last layer, inline tiles: sum over axes of the E streams
       int cur = 0;
 #pragma unroll
       for (int l = 2; l <= L; ++l) {
         f4 acc[S];
         for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+        mfma_phase_begin();
         if constexpr (PREC == 0) {
           float bk[KC];
           const float4* wp = (const float4*)((const float*)np.Wl[l - 2] + (int64_t)n * W + g * KC);
@@ -143,6 +151,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
             for (int q = 0; q < KC / 8; ++q) acc[s] = mfma32(ap[q], bk[q], acc[s]);
           }
         }
+        mfma_phase_end();
         const float bias = np.bl[l - 2][n];
         const bool last = (l == L);
         for (int j = 0; j < 4; ++j) {
@@ -150,16 +159,31 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
           float z = acc[0][j] + bias;
           float pp[3], ee[3], av, Dv[3], Ev[3];
           for (int a = 0; a < D; ++a) { pp[a] = acc[1 + a][j]; ee[a] = acc[1 + D + a][j]; }
-          act_fwd<ACT, D>(z, pp, ee, av, Dv, Ev);
-          Z[l - 2][0][j] = z;
-          for (int s = 1; s < S; ++s) Z[l - 2][s][j] = acc[s][j];
           if (!last) {
+            act_fwd<ACT, D>(z, pp, ee, av, Dv, Ev);
+            Z[l - 2][0][j] = z;
+            for (int s = 1; s < S; ++s) Z[l - 2][s][j] = acc[s][j];
             bufR[cur ^ 1][0][c][n] = from_f<T>(av);
             for (int a = 0; a < D; ++a) {
               bufR[cur ^ 1][1 + a][c][n] = from_f<T>(Dv[a]);
               bufR[cur ^ 1][1 + D + a][c][n] = from_f<T>(Ev[a]);
             }
           } else {
+            // output adjoints: known for non-inline tiles; inline tiles carry
+            // one adjoint alpha_c on every E stream, known after the residual,
+            // and the backward is linear in it: differentiate for w_out and
+            // scale by alpha_c afterwards
+            float ab, Db[3], Eb[3], zb, pb[3], eb[3];
+            if (inl) {
+              ab = 0.f;
+              for (int a = 0; a < D; ++a) { Db[a] = 0.f; Eb[a] = won; }
+            } else {
+              ab = won * adjs[c][0];
+              for (int a = 0; a < D; ++a) { Db[a] = won * adjs[c][1 + a]; Eb[a] = won * adjs[c][1 + D + a]; }
+            }
+            act_fb<ACT, D>(z, pp, ee, ab, Db, Eb, av, Dv, Ev, zb, pb, eb);
+            dz[0][j] = zb;
+            for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
             // output layer: u = sum_n w_out[n] a_L[n] (+ b_out), per stream
             float vals[7];
             vals[0] = av;
@@ -172,8 +196,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
               v += __shfl_xor(v, 1);
               if (r16 == 0) part[w][c][s] = v;
             }
-            // d loss / d w_out[n] = sum_c sum_s adj[c][s] a_L[s][n][c]; inline
-            // tiles carry one adjoint on all E streams, known after the residual
+            // d loss / d w_out[n] = sum_c sum_s adj[c][s] a_L[s][n][c]
             if (inl) {
               float es = 0.f;
               for (int a = 0; a < D; ++a) es += Ev[a];
@@ -204,27 +227,21 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
       }
       if (inl) __syncthreads();
 
-      // ---------------- backward, top layer
-      float dz[S][4];
-      for (int j = 0; j < 4; ++j) {
-        const int c = 4 * g + j;
-        float pp[3], ee[3], Db[3], Eb[3], zb, pb[3], eb[3];
-        for (int a = 0; a < D; ++a) {
-          pp[a] = Z[L - 2][1 + a][j]; ee[a] = Z[L - 2][1 + D + a][j];
-          Db[a] = won * adjs[c][1 + a]; Eb[a] = won * adjs[c][1 + D + a];
+      // ---------------- top layer of inline tiles: scale by alpha_c
+      if (inl) {
+        for (int j = 0; j < 4; ++j) {
+          const float al = adjs[4 * g + j][1 + D];
+          for (int s = 0; s < S; ++s) dz[s][j] *= al;
+          accwo += al * eS[j];
         }
-        act_bwd<ACT, D>(Z[L - 2][0][j], pp, ee, won * adjs[c][0], Db, Eb, zb, pb, eb);
-        dz[0][j] = zb;
-        for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
-        if (inl) accwo += adjs[c][1 + D] * eS[j];
       }
       if (tid == 0)
         for (int c = 0; c < kTile; ++c) accbo += adjs[c][0];
 
       // ---------------- backward through the hidden layers.  Per layer l:
-      // dZ_l goes to LDS; dA_{l-1} = dZ_l W_l runs on the matrix cores while
-      // the VALU recomputes A_{l-1} from the kept pre-activations; then the
-      // dW_l^T = A_{l-1}^T dZ_l MFMAs run next to the derivative epilogue.
+      // dZ_l goes to LDS; dA_{l-1} = dZ_l W_l runs on the matrix cores; then
+      // per centre the VALU recomputes A_{l-1} and forms dZ_{l-1}, and the
+      // dW_l^T = A_{l-1}^T dZ_l MFMAs consume A_{l-1}.
       int bb = 0;
 #pragma unroll
       for (int l = L; l >= 2; --l) {
@@ -242,6 +259,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
         __syncthreads();
         f4 acc[S];
         for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+        mfma_phase_begin();
         if constexpr (PREC == 0) {
           float bk[KC];
           const float4* wp = (const float4*)((const float*)np.WlT[l - 2] + (int64_t)n * W + g * KC);
@@ -268,18 +286,20 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
             for (int q = 0; q < KC / 8; ++q) acc[s] = mfma32(ap[q], bk[q], acc[s]);
           }
         }
+        mfma_phase_end();
         // per centre j: A_{l-1} recomputed from its pre-activations (layer 1:
-        // from z1), then dW_l^T[n_in][n_out] += sum over streams of
-        // A[.][n_in] dZ[.][n_out]; the VALU work of centre j+1 overlaps the
-        // matrix-core work of centre j
+        // from z1) together with the derivative epilogue dZ_{l-1}, sharing
+        // the activation factors; then dW_l^T[n_in][n_out] += sum over
+        // streams of A[.][n_in] dZ_l[.][n_out]
         for (int j = 0; j < 4; ++j) {
-          float av[S], Dv[3], Ev[3];
+          float av[S], Dv[3], Ev[3], Db[3], Eb[3], zb, pb[3], eb[3];
+          for (int a = 0; a < D; ++a) { Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j]; }
           if (l > 2) {
             float pp[3], ee[3];
             for (int a = 0; a < D; ++a) { pp[a] = Z[l - 3][1 + a][j]; ee[a] = Z[l - 3][1 + D + a][j]; }
-            act_fwd<ACT, D>(Z[l - 3][0][j], pp, ee, av[0], Dv, Ev);
+            act_fb<ACT, D>(Z[l - 3][0][j], pp, ee, acc[0][j], Db, Eb, av[0], Dv, Ev, zb, pb, eb);
           } else {
-            act_fwd<ACT, D>(z1[j], p1, e0, av[0], Dv, Ev);
+            act_fb_l1<ACT, D>(z1[j], l1ax[n], acc[0][j], Db, Eb, av[0], Dv, Ev, zb, pb);
           }
           for (int a = 0; a < D; ++a) { av[1 + a] = Dv[a]; av[1 + D + a] = Ev[a]; }
           if constexpr (PREC == 0) {
@@ -296,18 +316,10 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
               accW[l - 2][ob] = mfma32(aop, bop, accW[l - 2][ob]);
             }
           }
-        }
-        // derivative epilogue of layer l-1
-        for (int j = 0; j < 4; ++j) {
-          float pp[3], ee[3], Db[3], Eb[3], zb, pb[3], eb[3];
-          for (int a = 0; a < D; ++a) { Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j]; }
           if (l > 2) {
-            for (int a = 0; a < D; ++a) { pp[a] = Z[l - 3][1 + a][j]; ee[a] = Z[l - 3][1 + D + a][j]; }
-            act_bwd<ACT, D>(Z[l - 3][0][j], pp, ee, acc[0][j], Db, Eb, zb, pb, eb);
             dz[0][j] = zb;
             for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
           } else {
-            act_bwd<ACT, D>(z1[j], p1, e0, acc[0][j], Db, Eb, zb, pb, eb);
             const int c = 4 * g + j;
             accb[0] += zb;
             for (int a = 0; a < D; ++a) accW1[a] += zb * xs[c][a] + h * pb[a];

@@ -47,6 +47,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
   __shared__ float adjs[kTile][8];
   __shared__ float part[NW][kTile][8];
   __shared__ float xs[kTile][4];
+  __shared__ L1Axes l1ax[W];
   __shared__ double lsum[kTile];
   __shared__ int tflag;
   T* Aout = (T*)Aout_;
@@ -62,8 +63,11 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
     const NetPtrs& np = nets.net[net];
     float accb[L], accW1[3] = {0.f, 0.f, 0.f}, accwo = 0.f, accbo = 0.f;
     for (int l = 0; l < L; ++l) accb[l] = 0.f;
-    float W1n[3], p1[3], e0[3] = {0.f, 0.f, 0.f};
+    float W1n[3], p1[3];
     for (int a = 0; a < D; ++a) { W1n[a] = np.W1[n * D + a]; p1[a] = h * W1n[a]; }
+    // first-layer axis factors, constant per net: kept in LDS, not registers
+    if (g == 0) l1ax[n] = l1_axes<ACT, D>(p1);
+    __syncthreads();
     const float b1n = np.b1[n], won = np.wout[n];
     const int64_t a_end = (int64_t)meta->base[net][KIND_A] + meta->cnt[net][KIND_A];
 
@@ -93,7 +97,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
         float vals[S][4];
         for (int j = 0; j < 4; ++j) {
           float av, Dv[3], Ev[3];
-          act_fwd<ACT, D>(z1[j], p1, e0, av, Dv, Ev);
+          act_fwd_l1<ACT, D>(z1[j], l1ax[n], av, Dv, Ev);
           vals[0][j] = av;
           for (int a = 0; a < D; ++a) { vals[1 + a][j] = Dv[a]; vals[1 + D + a][j] = Ev[a]; }
         }
@@ -262,7 +266,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
             for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
           } else {
             for (int a = 0; a < D; ++a) { Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j]; }
-            act_bwd<ACT, D>(z1[j], p1, e0, acc[0][j], Db, Eb, zb, pb, eb);
+            act_bwd_l1<ACT, D>(z1[j], l1ax[n], acc[0][j], Db, Eb, zb, pb);
             const int c = 4 * g + j;
             accb[0] += zb;
             for (int a = 0; a < D; ++a) accW1[a] += zb * xs[c][a] + h * pb[a];
