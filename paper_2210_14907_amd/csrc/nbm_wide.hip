@@ -2,9 +2,10 @@
 //
 // Pass 1 (k_wide_fb): one persistent work-group of W/16 wavefronts per
 // 16-centre tile walks forward through every layer (pre-activations stay in
-// registers: each lane owns one neuron and four centres), forms the uncut
-// residual inline (or reads the adjoints written by the residual kernels for
-// other tiles), and walks backward computing dZ_l for every hidden layer.
+// registers: each lane owns one neuron and four centres), forms the last
+// layer's backward in its forward epilogue, the uncut residual inline (or
+// takes the adjoints written by the residual kernels for other tiles), and
+// walks backward computing dZ_l for every hidden layer.
 // The operands of the weight-gradient contraction, A_{l-1} and dZ_l, leave
 // the chip in the accumulator ("tile") layout [tile][stream][neuron][16];
 // the small gradients (biases, W_1, w_out) are accumulated per work-group.
@@ -39,17 +40,12 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
   constexpr int LD = W + (PREC == 0 ? 4 : 8);
   constexpr int NW = W / 16;     // wavefronts; wave w owns neurons 16w .. 16w+15
   constexpr int KC = W / 4;
-  constexpr int NT = NW * 64;
   __shared__ __attribute__((aligned(16))) T bufR[2][S][kTile][LD];
-  // last-layer activations: LDS for BF16 operands (room left), registers for FP32
-  constexpr bool kALinLDS = PREC == 1;
-  __shared__ float colL[kALinLDS ? S : 1][kALinLDS ? W : 1][kTile];
   __shared__ float adjs[kTile][8];
   __shared__ float part[NW][kTile][8];
   __shared__ float xs[kTile][4];
   __shared__ L1Axes l1ax[W];
   __shared__ double lsum[kTile];
-  __shared__ int tflag;
   T* Aout = (T*)Aout_;
   T* dZout = (T*)dZout_;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r16 = lane & 15, g = lane >> 4;
@@ -70,19 +66,24 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
     __syncthreads();
     const float b1n = np.b1[n], won = np.wout[n];
     const int64_t a_end = (int64_t)meta->base[net][KIND_A] + meta->cnt[net][KIND_A];
+    const int t_lo = net == 0 ? 0 : meta->tiles[0];
+    const int t_hi = net == 0 ? meta->tiles[0] : ntiles;
 
-    for (int t = blockIdx.x; t < ntiles; t += G) {
-      if (wide_tile_net(meta, t) != net) continue;
+    for (int t = t_lo + blockIdx.x; t < t_hi; t += G) {
       const int64_t slot0 = (int64_t)t * kTile;
       const int64_t slot_end = (int64_t)meta->tile0[net] * kTile + meta->total[net];
+      const bool inl = slot0 + kTile <= a_end;   // uniform over the work-group
       if (tid < kTile) {
         float4 cc = centres[slot0 + tid];
         if (slot0 + tid >= slot_end) cc = make_float4(0.f, 0.f, 0.f, 0.f);
         xs[tid][0] = cc.x; xs[tid][1] = cc.y; xs[tid][2] = cc.z; xs[tid][3] = 0.f;
       }
-      if (tid == 0) tflag = (slot0 + kTile <= a_end) ? 1 : 0;
+      if (!inl && tid < kTile * 8) {
+        // output adjoints of a non-inline tile, written by the residual kernels
+        const int64_t slot = slot0 + tid / 8;
+        adjs[tid / 8][tid % 8] = slot < slot_end ? adj[slot0 * 8 + tid] : 0.f;
+      }
       __syncthreads();
-      const bool inl = tflag != 0;
       auto tofs = [&](int s, int nn) -> int64_t { return (((int64_t)t * S + s) * W + nn) * kTile + 4 * g; };
 
       // ---- layer 1
@@ -111,18 +112,17 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
       }
       __syncthreads();
 
-      // ---- hidden layers
-      float Z[L - 1][S][4];
-      float AL[kALinLDS ? 1 : S][4];
-      auto al = [&](int s, int j) -> float& {
-        if constexpr (kALinLDS) return colL[s][n][4 * g + j];
-        else return AL[s][j];
-      };
+      // ---- hidden layers.  Pre-activations of layers 2..L-1 stay in
+      // registers; the last layer's backward is formed in its epilogue.
+      float Z[L - 2][S][4];
+      float dz[S][4];
+      float eS[4];
       int cur = 0;
 #pragma unroll
       for (int l = 2; l <= L; ++l) {
         f4 acc[S];
         for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+        mfma_phase_begin();
         if constexpr (PREC == 0) {
           const float4* wp = (const float4*)((const float*)np.Wl[l - 2] + (int64_t)n * W + g * KC);
           for (int q = 0; q < KC / 4; ++q) {
@@ -142,20 +142,20 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
             for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[cur][s][r16][g * KC + 8 * q]), bk, acc[s]);
           }
         }
+        mfma_phase_end();
         const float bias = np.bl[l - 2][n];
-        const bool last = (l == L);
-        float vals[S][4];
-        for (int j = 0; j < 4; ++j) {
-          float z = acc[0][j] + bias;
-          float pp[3], ee[3], av, Dv[3], Ev[3];
-          for (int a = 0; a < D; ++a) { pp[a] = acc[1 + a][j]; ee[a] = acc[1 + D + a][j]; }
-          act_fwd<ACT, D>(z, pp, ee, av, Dv, Ev);
-          Z[l - 2][0][j] = z;
-          for (int s = 1; s < S; ++s) Z[l - 2][s][j] = acc[s][j];
-          vals[0][j] = av;
-          for (int a = 0; a < D; ++a) { vals[1 + a][j] = Dv[a]; vals[1 + D + a][j] = Ev[a]; }
-        }
-        if (!last) {
+        if (l < L) {
+          float vals[S][4];
+          for (int j = 0; j < 4; ++j) {
+            float z = acc[0][j] + bias;
+            float pp[3], ee[3], av, Dv[3], Ev[3];
+            for (int a = 0; a < D; ++a) { pp[a] = acc[1 + a][j]; ee[a] = acc[1 + D + a][j]; }
+            act_fwd<ACT, D>(z, pp, ee, av, Dv, Ev);
+            Z[l - 2][0][j] = z;
+            for (int s = 1; s < S; ++s) Z[l - 2][s][j] = acc[s][j];
+            vals[0][j] = av;
+            for (int a = 0; a < D; ++a) { vals[1 + a][j] = Dv[a]; vals[1 + D + a][j] = Ev[a]; }
+          }
           for (int s = 0; s < S; ++s) {
             for (int j = 0; j < 4; ++j) bufR[cur ^ 1][s][4 * g + j][n] = from_f<T>(vals[s][j]);
             T* dst = Aout + (int64_t)(l - 1) * lstride + tofs(s, n);
@@ -165,28 +165,55 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
               *(bf4*)dst = bf4{(__bf16)vals[s][0], (__bf16)vals[s][1], (__bf16)vals[s][2], (__bf16)vals[s][3]};
           }
         } else {
-          for (int s = 0; s < S; ++s)
-            for (int j = 0; j < 4; ++j) al(s, j) = vals[s][j];
+          // output adjoints: known for non-inline tiles; inline tiles carry one
+          // adjoint alpha_c on every E stream (known after the residual) and
+          // the backward is linear in it
+          for (int j = 0; j < 4; ++j) {
+            const int c = 4 * g + j;
+            float z = acc[0][j] + bias;
+            float pp[3], ee[3], av, Dv[3], Ev[3], ab, Db[3], Eb[3], zb, pb[3], eb[3];
+            for (int a = 0; a < D; ++a) { pp[a] = acc[1 + a][j]; ee[a] = acc[1 + D + a][j]; }
+            if (inl) {
+              ab = 0.f;
+              for (int a = 0; a < D; ++a) { Db[a] = 0.f; Eb[a] = won; }
+            } else {
+              ab = won * adjs[c][0];
+              for (int a = 0; a < D; ++a) { Db[a] = won * adjs[c][1 + a]; Eb[a] = won * adjs[c][1 + D + a]; }
+            }
+            act_fb<ACT, D>(z, pp, ee, ab, Db, Eb, av, Dv, Ev, zb, pb, eb);
+            dz[0][j] = zb;
+            for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
+            // output layer, per stream: u = sum_n w_out[n] a_L[n] (+ b_out)
+            float vals[7];
+            vals[0] = av;
+            for (int a = 0; a < D; ++a) { vals[1 + a] = Dv[a]; vals[1 + D + a] = Ev[a]; }
+            for (int s = 0; s < S; ++s) {
+              float v = won * vals[s];
+              v += __shfl_xor(v, 8);
+              v += __shfl_xor(v, 4);
+              v += __shfl_xor(v, 2);
+              v += __shfl_xor(v, 1);
+              if (r16 == 0) part[w][c][s] = v;
+            }
+            // d loss / d w_out[n] = sum_c sum_s adj[c][s] a_L[s][n][c]
+            if (inl) {
+              float es = 0.f;
+              for (int a = 0; a < D; ++a) es += Ev[a];
+              eS[j] = es;
+            } else {
+              for (int s = 0; s < S; ++s) accwo += adjs[c][s] * vals[s];
+            }
+          }
         }
         __syncthreads();
         cur ^= 1;
       }
 
-      // ---- output layer, residual / adjoints
-      for (int s = 0; s < S; ++s)
-        for (int j = 0; j < 4; ++j) {
-          float v = won * al(s, j);
-          v += __shfl_xor(v, 8);
-          v += __shfl_xor(v, 4);
-          v += __shfl_xor(v, 2);
-          v += __shfl_xor(v, 1);
-          if (r16 == 0) part[w][4 * g + j][s] = v;
-        }
-      __syncthreads();
-      if (tid < kTile) {
-        const int c = tid;
-        const int64_t slot = slot0 + c;
-        if (inl) {
+      // ---- residual / adjoints of inline tiles
+      if (inl) {
+        if (tid < kTile) {
+          const int c = tid;
+          const int64_t slot = slot0 + c;
           float eu = 0.f;
           for (int a = 0; a < D; ++a)
             for (int v = 0; v < NW; ++v) eu += part[v][c][1 + D + a];
@@ -196,36 +223,24 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           float rb = (float)(scale * (double)r);
           for (int s = 0; s < 8; ++s) adjs[c][s] = 0.f;
           for (int a = 0; a < D; ++a) adjs[c][1 + D + a] = -rb / hh;
-        } else {
-          const bool valid = slot < slot_end;
-          for (int s = 0; s < 8; ++s) adjs[c][s] = valid ? adj[slot * 8 + s] : 0.f;
         }
-      }
-      __syncthreads();
-
-      // ---- backward, top layer
-      float dz[S][4];
-      for (int j = 0; j < 4; ++j) {
-        const int c = 4 * g + j;
-        float pp[3], ee[3], Db[3], Eb[3], zb, pb[3], eb[3];
-        for (int a = 0; a < D; ++a) {
-          pp[a] = Z[L - 2][1 + a][j]; ee[a] = Z[L - 2][1 + D + a][j];
-          Db[a] = won * adjs[c][1 + a]; Eb[a] = won * adjs[c][1 + D + a];
+        __syncthreads();
+        for (int j = 0; j < 4; ++j) {
+          const float al = adjs[4 * g + j][1 + D];
+          for (int s = 0; s < S; ++s) dz[s][j] *= al;
+          accwo += al * eS[j];
         }
-        act_bwd<ACT, D>(Z[L - 2][0][j], pp, ee, won * adjs[c][0], Db, Eb, zb, pb, eb);
-        dz[0][j] = zb;
-        for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
-        for (int s = 0; s < S; ++s) accwo += adjs[c][s] * al(s, j);
       }
       if (tid == 0)
         for (int c = 0; c < kTile; ++c) accbo += adjs[c][0];
 
-      // ---- backward through the hidden layers
+      // ---- backward through the hidden layers (dZ rows double-buffered)
+      int bb = 0;
 #pragma unroll
       for (int l = L; l >= 2; --l) {
         for (int j = 0; j < 4; ++j) accb[l - 1] += dz[0][j];
         for (int s = 0; s < S; ++s) {
-          for (int j = 0; j < 4; ++j) bufR[0][s][4 * g + j][n] = from_f<T>(dz[s][j]);
+          for (int j = 0; j < 4; ++j) bufR[bb][s][4 * g + j][n] = from_f<T>(dz[s][j]);
           T* dst = dZout + (int64_t)(l - 2) * lstride + tofs(s, n);
           if constexpr (PREC == 0)
             *(float4*)dst = make_float4(dz[s][0], dz[s][1], dz[s][2], dz[s][3]);
@@ -235,12 +250,13 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
         __syncthreads();
         f4 acc[S];
         for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+        mfma_phase_begin();
         if constexpr (PREC == 0) {
           const float4* wp = (const float4*)((const float*)np.WlT[l - 2] + (int64_t)n * W + g * KC);
           for (int q = 0; q < KC / 4; ++q) {
             float4 b4 = wp[q];
             for (int s = 0; s < S; ++s) {
-              float4 a4 = *(const float4*)(&bufR[0][s][r16][g * KC + 4 * q]);
+              float4 a4 = *(const float4*)(&bufR[bb][s][r16][g * KC + 4 * q]);
               acc[s] = mfma4(a4.x, b4.x, acc[s]);
               acc[s] = mfma4(a4.y, b4.y, acc[s]);
               acc[s] = mfma4(a4.z, b4.z, acc[s]);
@@ -251,29 +267,28 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           const bf8* wp = (const bf8*)((const T*)np.WlT[l - 2] + (int64_t)n * W + g * KC);
           for (int q = 0; q < KC / 8; ++q) {
             bf8 bk = wp[q];
-            for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[0][s][r16][g * KC + 8 * q]), bk, acc[s]);
+            for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[bb][s][r16][g * KC + 8 * q]), bk, acc[s]);
           }
         }
+        mfma_phase_end();
         for (int j = 0; j < 4; ++j) {
           float pp[3], ee[3], Db[3], Eb[3], zb, pb[3], eb[3];
+          for (int a = 0; a < D; ++a) { Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j]; }
           if (l > 2) {
-            for (int a = 0; a < D; ++a) {
-              pp[a] = Z[l - 3][1 + a][j]; ee[a] = Z[l - 3][1 + D + a][j];
-              Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j];
-            }
+            for (int a = 0; a < D; ++a) { pp[a] = Z[l - 3][1 + a][j]; ee[a] = Z[l - 3][1 + D + a][j]; }
             act_bwd<ACT, D>(Z[l - 3][0][j], pp, ee, acc[0][j], Db, Eb, zb, pb, eb);
             dz[0][j] = zb;
             for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
           } else {
-            for (int a = 0; a < D; ++a) { Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j]; }
             act_bwd_l1<ACT, D>(z1[j], l1ax[n], acc[0][j], Db, Eb, zb, pb);
             const int c = 4 * g + j;
             accb[0] += zb;
             for (int a = 0; a < D; ++a) accW1[a] += zb * xs[c][a] + h * pb[a];
           }
         }
-        __syncthreads();
+        bb ^= 1;
       }
+      __syncthreads();   // xs, adjs and the row buffers are rewritten by the next tile
     }
     // ---- flush the small gradients of this net
     float* prow = partial + (int64_t)blockIdx.x * Ptot + (net == 0 ? 0 : net_off1);
