@@ -41,6 +41,11 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
   constexpr int NW = W / 16;     // wavefronts; wave w owns neurons 16w .. 16w+15
   constexpr int KC = W / 4;
   __shared__ __attribute__((aligned(16))) T bufR[2][S][kTile][LD];
+  // BF16 operands leave room in LDS for the first hidden layer's
+  // pre-activations [stream][neuron][centre] (each lane reads back only what
+  // it wrote); FP32 operands keep them in registers
+  constexpr bool kZ0inLDS = PREC == 1;
+  __shared__ __attribute__((aligned(16))) float Zs[kZ0inLDS ? S : 1][kZ0inLDS ? W : 1][kTile];
   __shared__ float adjs[kTile][8];
   __shared__ float part[NW][kTile][8];
   __shared__ float xs[kTile][4];
@@ -156,6 +161,9 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
             vals[0][j] = av;
             for (int a = 0; a < D; ++a) { vals[1 + a][j] = Dv[a]; vals[1 + D + a][j] = Ev[a]; }
           }
+          if (kZ0inLDS && l == 2)
+            for (int s = 0; s < S; ++s)
+              *(float4*)(&Zs[s][n][4 * g]) = make_float4(Z[0][s][0], Z[0][s][1], Z[0][s][2], Z[0][s][3]);
           for (int s = 0; s < S; ++s) {
             for (int j = 0; j < 4; ++j) bufR[cur ^ 1][s][4 * g + j][n] = from_f<T>(vals[s][j]);
             T* dst = Aout + (int64_t)(l - 1) * lstride + tofs(s, n);
@@ -271,6 +279,11 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           }
         }
         mfma_phase_end();
+        if (kZ0inLDS && l == 3)
+          for (int s = 0; s < S; ++s) {
+            const float4 v = *(const float4*)(&Zs[s][n][4 * g]);
+            Z[0][s][0] = v.x; Z[0][s][1] = v.y; Z[0][s][2] = v.z; Z[0][s][3] = v.w;
+          }
         for (int j = 0; j < 4; ++j) {
           float pp[3], ee[3], Db[3], Eb[3], zb, pb[3], eb[3];
           for (int a = 0; a < D; ++a) { Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j]; }
