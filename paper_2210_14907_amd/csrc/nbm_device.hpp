@@ -154,16 +154,34 @@ __device__ __forceinline__ float tanh_short(float e) {
   return e * fmaf(fmaf(y, 2.0f / 15.0f, -1.0f / 3.0f), y, 1.0f);
 }
 
-// Per-axis trigonometric factors of the sin streams.  Fast path (whole
-// wavefront has |p|/2 <= pi/4 and |e| <= 1/32): Taylor series for p/2, short
-// series for e/2, and the half-angle m/2 = p/2 - e/2 by the addition theorem.
+// Series tiers for the difference arguments.  TIER 2 ("tiny", taken when
+// the whole wavefront has |p| <= 1/64 (tanh) or |p|/2 <= 1/64 (sin) and
+// |e| <= 1/64): tanh x = x (1 - x^2/3 + 2 x^4/15), relative truncation error
+// 17 x^6/315 < 6e-10 for |x| <= 3/64; sin x = x (1 - x^2/6) and
+// cos x = 1 - x^2/2, errors below x^4/24 < 3e-9 for |x| <= 1/64.  TIER 1:
+// the longer series above; TIER 0: library functions for large arguments.
+constexpr float kTinyP = 0.015625f;   // 1/64
+
+__device__ __forceinline__ float sin_tiny(float x) { return x * fmaf(x * x, -1.0f / 6.0f, 1.0f); }
+__device__ __forceinline__ float cos_tiny(float x) { return fmaf(x * x, -0.5f, 1.0f); }
+
+// Per-axis trigonometric factors of the sin streams.  Series tiers: Taylor
+// series for p/2, short series for e/2, and the half-angle m/2 = p/2 - e/2
+// by the addition theorem.
 struct SinAxis { float sp, cp, sm, cm, se, ce; };
 
-template <bool FAST>
+template <int TIER>
 __device__ __forceinline__ SinAxis sin_axis(float p, float e) {
   SinAxis r;
   float hp = 0.5f * p, he = 0.5f * e;
-  if (FAST) {
+  if (TIER == 2) {
+    r.sp = sin_tiny(hp);
+    r.cp = cos_tiny(hp);
+    r.se = sin_tiny(he);
+    r.ce = cos_tiny(he);
+    r.sm = r.sp * r.ce - r.cp * r.se;   // sin(p/2 - e/2)
+    r.cm = r.cp * r.ce + r.sp * r.se;   // cos(p/2 - e/2)
+  } else if (TIER == 1) {
     r.sp = sin_taylor(hp);
     r.cp = cos_taylor(hp);
     r.se = sin_short(he);
@@ -182,11 +200,16 @@ __device__ __forceinline__ SinAxis sin_axis(float p, float e) {
 // Per-axis tanh factors: T_p, T_m, T_e, T_s with m = p - e, s = p + m.
 struct TanhAxis { float Tp, Tm, Te, Ts; };
 
-template <bool FAST>
+template <int TIER>
 __device__ __forceinline__ TanhAxis tanh_axis(float p, float e) {
   TanhAxis r;
   float m = p - e;
-  if (FAST) {
+  if (TIER == 2) {
+    r.Tp = tanh_short(p);
+    r.Tm = tanh_short(m);
+    r.Ts = tanh_short(p + m);
+    r.Te = tanh_short(e);
+  } else if (TIER == 1) {
     r.Tp = tanh_taylor(p);
     r.Tm = tanh_taylor(m);
     r.Ts = tanh_taylor(p + m);
@@ -201,6 +224,17 @@ __device__ __forceinline__ TanhAxis tanh_axis(float p, float e) {
 }
 
 template <int ACT, int D>
+__device__ __forceinline__ bool tiny_args(const float* p, const float* e) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    if (ACT == 1) ok = ok && fabsf(p[i]) <= 2.0f * kTinyP && fabsf(e[i]) <= kTinyP;
+    else ok = ok && fabsf(p[i]) <= kTinyP && fabsf(e[i]) <= kTinyP;
+  }
+  return ok;
+}
+
+template <int ACT, int D>
 __device__ __forceinline__ bool fast_args(const float* p, const float* e) {
   bool ok = true;
 #pragma unroll
@@ -211,7 +245,7 @@ __device__ __forceinline__ bool fast_args(const float* p, const float* e) {
   return ok;
 }
 
-template <int ACT, int D, bool FAST>
+template <int ACT, int D, int TIER>
 __device__ __forceinline__ void act_fwd_impl(float z, const float* p, const float* e, float& a,
                                              float* Dv, float* Ev) {
   if (ACT == 1) {
@@ -220,7 +254,7 @@ __device__ __forceinline__ void act_fwd_impl(float z, const float* p, const floa
     a = S;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      SinAxis f = sin_axis<FAST>(p[i], e[i]);
+      SinAxis f = sin_axis<TIER>(p[i], e[i]);
       float cs2 = f.cp * f.cm - f.sp * f.sm;  // cos((p+m)/2)
       Dv[i] = 2.0f * f.sp * (C * f.cp - S * f.sp);
       Ev[i] = -2.0f * S * (f.sp * f.sp + f.sm * f.sm) + 2.0f * C * cs2 * f.se;
@@ -231,7 +265,7 @@ __device__ __forceinline__ void act_fwd_impl(float z, const float* p, const floa
     a = t;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      TanhAxis f = tanh_axis<FAST>(p[i], e[i]);
+      TanhAxis f = tanh_axis<TIER>(p[i], e[i]);
       // 1/(1 + t T_p) and 1/(1 - t T_m) from one reciprocal of their product
       float dP = 1.0f + t * f.Tp, dM = 1.0f - t * f.Tm;
       float R = rcp(dP * dM);
@@ -243,7 +277,7 @@ __device__ __forceinline__ void act_fwd_impl(float z, const float* p, const floa
   }
 }
 
-template <int ACT, int D, bool FAST>
+template <int ACT, int D, int TIER>
 __device__ __forceinline__ void act_bwd_impl(float z, const float* p, const float* e, float ab,
                                              const float* Db, const float* Eb, float& zb, float* pb,
                                              float* eb) {
@@ -253,7 +287,7 @@ __device__ __forceinline__ void act_bwd_impl(float z, const float* p, const floa
     zb = ab * C;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      SinAxis f = sin_axis<FAST>(p[i], e[i]);
+      SinAxis f = sin_axis<TIER>(p[i], e[i]);
       float sp = f.sp, cp = f.cp, sm = f.sm, cm = f.cm, se = f.se, ce = f.ce;
       float cs2 = cp * cm - sp * sm;        // cos(s/2), s = p + m
       float ss2 = sp * cm + cp * sm;        // sin(s/2)
@@ -273,7 +307,7 @@ __device__ __forceinline__ void act_bwd_impl(float z, const float* p, const floa
     zb = ab * q;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      TanhAxis f = tanh_axis<FAST>(p[i], e[i]);
+      TanhAxis f = tanh_axis<TIER>(p[i], e[i]);
       float Tp = f.Tp, Tm = f.Tm;
       float dP = 1.0f + t * Tp, dM = 1.0f - t * Tm;
       float R = rcp(dP * dM);
@@ -385,8 +419,9 @@ __device__ __forceinline__ void act_bwd_l1(float z, const L1Axes& f, float ab, c
   }
 }
 
-// general paths kept out of line: taken only when some lane has a large
-// difference argument (coarse h), so the common path stays register-lean.
+// Longer series and library paths kept out of line (each lane picks its
+// tier there): taken only when some lane of the wavefront has a difference
+// argument beyond the tiny tier, so the common path stays register-lean.
 // Scalars in, a small struct out: everything travels in registers.
 struct ActFwdOut { float a, D[3], E[3]; };
 struct ActBwdOut { float zb, pb[3], eb[3]; };
@@ -396,7 +431,8 @@ __device__ __attribute__((noinline)) ActFwdOut act_fwd_general(float z, float p0
                                                                float e0, float e1, float e2) {
   const float p[3] = {p0, p1, p2}, e[3] = {e0, e1, e2};
   ActFwdOut r;
-  act_fwd_impl<ACT, D, false>(z, p, e, r.a, r.D, r.E);
+  if (fast_args<ACT, D>(p, e)) act_fwd_impl<ACT, D, 1>(z, p, e, r.a, r.D, r.E);
+  else act_fwd_impl<ACT, D, 0>(z, p, e, r.a, r.D, r.E);
   return r;
 }
 template <int ACT, int D>
@@ -407,17 +443,18 @@ __device__ __attribute__((noinline)) ActBwdOut act_bwd_general(float z, float p0
   const float p[3] = {p0, p1, p2}, e[3] = {e0, e1, e2};
   const float Db[3] = {D0, D1, D2}, Eb[3] = {E0, E1, E2};
   ActBwdOut r;
-  act_bwd_impl<ACT, D, false>(z, p, e, ab, Db, Eb, r.zb, r.pb, r.eb);
+  if (fast_args<ACT, D>(p, e)) act_bwd_impl<ACT, D, 1>(z, p, e, ab, Db, Eb, r.zb, r.pb, r.eb);
+  else act_bwd_impl<ACT, D, 0>(z, p, e, ab, Db, Eb, r.zb, r.pb, r.eb);
   return r;
 }
 
 // forward: base a, and per-axis D, E from (z, p, e).  One wave-uniform
-// branch picks the series path when every lane's arguments are small.
+// branch takes the inline tiny-argument tier when every lane qualifies.
 template <int ACT, int D>
 __device__ __forceinline__ void act_fwd(float z, const float* p, const float* e, float& a,
                                         float* Dv, float* Ev) {
-  if (__all(fast_args<ACT, D>(p, e))) {
-    act_fwd_impl<ACT, D, true>(z, p, e, a, Dv, Ev);
+  if (__all(tiny_args<ACT, D>(p, e))) {
+    act_fwd_impl<ACT, D, 2>(z, p, e, a, Dv, Ev);
   } else {
     const ActFwdOut r = act_fwd_general<ACT, D>(z, p[0], D > 1 ? p[1] : 0.f, D > 2 ? p[2] : 0.f, e[0],
                                                 D > 1 ? e[1] : 0.f, D > 2 ? e[2] : 0.f);
@@ -431,8 +468,8 @@ template <int ACT, int D>
 __device__ __forceinline__ void act_bwd(float z, const float* p, const float* e, float ab,
                                         const float* Db, const float* Eb, float& zb, float* pb,
                                         float* eb) {
-  if (__all(fast_args<ACT, D>(p, e))) {
-    act_bwd_impl<ACT, D, true>(z, p, e, ab, Db, Eb, zb, pb, eb);
+  if (__all(tiny_args<ACT, D>(p, e))) {
+    act_bwd_impl<ACT, D, 2>(z, p, e, ab, Db, Eb, zb, pb, eb);
   } else {
     const ActBwdOut r = act_bwd_general<ACT, D>(
         z, p[0], D > 1 ? p[1] : 0.f, D > 2 ? p[2] : 0.f, e[0], D > 1 ? e[1] : 0.f, D > 2 ? e[2] : 0.f,
@@ -457,8 +494,13 @@ __device__ __attribute__((noinline)) ActFBOut act_fb_general(float z, float p0, 
   const float p[3] = {p0, p1, p2}, e[3] = {e0, e1, e2};
   const float Db[3] = {D0, D1, D2}, Eb[3] = {E0, E1, E2};
   ActFBOut r;
-  act_fwd_impl<ACT, D, false>(z, p, e, r.a, r.D, r.E);
-  act_bwd_impl<ACT, D, false>(z, p, e, ab, Db, Eb, r.zb, r.pb, r.eb);
+  if (fast_args<ACT, D>(p, e)) {
+    act_fwd_impl<ACT, D, 1>(z, p, e, r.a, r.D, r.E);
+    act_bwd_impl<ACT, D, 1>(z, p, e, ab, Db, Eb, r.zb, r.pb, r.eb);
+  } else {
+    act_fwd_impl<ACT, D, 0>(z, p, e, r.a, r.D, r.E);
+    act_bwd_impl<ACT, D, 0>(z, p, e, ab, Db, Eb, r.zb, r.pb, r.eb);
+  }
   return r;
 }
 
@@ -466,9 +508,9 @@ template <int ACT, int D>
 __device__ __forceinline__ void act_fb(float z, const float* p, const float* e, float ab,
                                        const float* Db, const float* Eb, float& a, float* Dv,
                                        float* Ev, float& zb, float* pb, float* eb) {
-  if (__all(fast_args<ACT, D>(p, e))) {
-    act_fwd_impl<ACT, D, true>(z, p, e, a, Dv, Ev);
-    act_bwd_impl<ACT, D, true>(z, p, e, ab, Db, Eb, zb, pb, eb);
+  if (__all(tiny_args<ACT, D>(p, e))) {
+    act_fwd_impl<ACT, D, 2>(z, p, e, a, Dv, Ev);
+    act_bwd_impl<ACT, D, 2>(z, p, e, ab, Db, Eb, zb, pb, eb);
   } else {
     const ActFBOut r = act_fb_general<ACT, D>(
         z, p[0], D > 1 ? p[1] : 0.f, D > 2 ? p[2] : 0.f, e[0], D > 1 ? e[1] : 0.f, D > 2 ? e[2] : 0.f,

@@ -75,6 +75,35 @@ def test_step_parity(name, wl, n, nb, n_near, band):
     assert e_unc <= (5 * tol if wl.prec == I.PREC_FP32 else tol)
 
 
+LARGE_ARG_CASES = [
+    # name, workload, weight gain, n, nb, n_near, band
+    ("c2_x8", I.C2, 8.0, 2048, 64, 256, 0.02),
+    ("c3_fp32_x4", I.C3.replace(prec=I.PREC_FP32), 4.0, 2048, 64, 256, 0.01),
+    ("c1_x4", I.C1, 4.0, 4096, 256, 256, 0.05),
+]
+
+
+@pytest.mark.parametrize("name,wl,gain,n,nb,n_near,band", LARGE_ARG_CASES,
+                         ids=[c[0] for c in LARGE_ARG_CASES])
+def test_step_parity_large_arguments(name, wl, gain, n, nb, n_near, band):
+    """Weights scaled up so that the difference arguments leave the tiny
+    series tier: the longer series and the library-function paths of the
+    activation streams are checked against the oracle as well (the sin net
+    at a smaller gain: the hardware sine of the base argument is accurate to
+    ~1e-7 |z| absolute, sized for pre-activations of order 1-10)."""
+    theta = (I.xavier_params(wl, 1) * gain).astype(np.float32).astype(np.float64)
+    pts, bpts = parity_batch(wl, n, nb, n_near, band, seed=11)
+    pts = pts.astype(np.float32).astype(np.float64)
+    bpts = bpts.astype(np.float32).astype(np.float64)
+    L_o, g_o, res_o = N.loss_and_grad(wl, theta, pts, bpts)
+    L_g, r_g, g_g, _, _ = _run(wl, pts, bpts, theta)
+    r_o = np.concatenate([res_o["r"], res_o["rb"]])
+    e_loss, e_res, e_grad = abs(L_g - L_o) / abs(L_o), max_rel(r_g, r_o), rel_err(g_g, g_o)
+    print(f"[parity] {name}: loss {e_loss:.2e} res {e_res:.2e} grad {e_grad:.2e}", flush=True)
+    tol = 1e-4   # larger arguments: condition of the streams grows with the gain
+    assert e_loss <= tol and e_res <= tol and e_grad <= tol
+
+
 @pytest.mark.parametrize("wl", [I.C2, I.C3.replace(prec=I.PREC_FP32)], ids=["c2_fused", "c3_two_pass"])
 def test_fused_and_layered_paths_agree(monkeypatch, wl):
     """The fused kernels (W=64 one-pass, W=128 two-pass) and the layered
