@@ -23,6 +23,43 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp32": 157.3e12, "bf16": 2.5e15}
 
+# sources the fused W=64 kernel is built from: the HBM traffic recorded in the
+# counter summary applies only while they are unchanged
+FUSED_SOURCES = ["nbm_fused.hip", "nbm_device.hpp", "nbm_internal.hpp", "nbm_launch.hpp"]
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "c2_k_fused_counters.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    hsh = hashlib.sha256()
+    for f in FUSED_SOURCES:
+        with open(os.path.join(ROOT, "paper_2210_14907_amd", "csrc", f), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources changed
+    since those counters were taken (or no summary exists)."""
+    try:
+        with open(COUNTER_SUMMARY) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    vals = {}
+    for ln in text.splitlines():
+        ln = ln.strip().lstrip("-").strip()
+        if ln.startswith(("sources_sha256:", "traffic_bytes_per_launch:")):
+            k, v = ln.split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("sources_sha256") != kernel_source_hash():
+        return None
+    try:
+        return int(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
 
 def flops_per_centre(wl):
     """Algorithmic FLOPs of evaluating one network on the 2d+1 stencil nodes
@@ -97,17 +134,22 @@ def run_workload(wl, steps, warmup, seed=1, timing=True, train_to=0):
     return out
 
 
-def accuracy(wl, res, judge_n):
+def accuracy(wl, res, judge_n, judge=None):
     """L-inf / L2 of the trained surrogate at the interior nodes of a judge
-    grid, against the closed-form solution and the FP64 grid CG oracle."""
+    grid, against the closed-form solution and the FP64 grid CG oracle.
+    `judge` = (GridSystem, solution, seconds) reuses an earlier solve."""
     import torch
     from oracle import grid as OG
 
     nbm, params = res["nbm"], res["params"]
-    gs = OG.GridSystem(wl, judge_n)
-    t0 = time.time()
-    U = gs.solve()
-    t_judge = time.time() - t0
+    if judge is None:
+        gs = OG.GridSystem(wl, judge_n)
+        t0 = time.time()
+        U = gs.solve()
+        t_judge = time.time() - t0
+    else:
+        gs, U, t_judge = judge
+    res["judge"] = (gs, U, t_judge)
     xin = gs.x[gs.interior]
     q = torch.tensor(xin, dtype=torch.float32, device=nbm.device)
     u = np.concatenate([nbm.eval(params, q[i:i + 60000]).cpu().numpy() for i in range(0, len(q), 60000)])
@@ -123,9 +165,10 @@ def accuracy(wl, res, judge_n):
     return out
 
 
-def cpu_baseline(wl, target_s=15.0):
+def cpu_baseline(wl, target_s=12.0):
     """The FP64 oracle's step (point evaluation + reverse mode) on a bounded
-    sample of the same workload, timed on the host cores."""
+    sample of the same workload, timed on the host cores: batches of up to
+    the workload's size, repeated until about target_s seconds of work."""
     from threadpoolctl import threadpool_info
 
     import nbm_inputs as I
@@ -139,14 +182,20 @@ def cpu_baseline(wl, target_s=15.0):
     rate0 = n0 / (time.time() - t)
     n = int(min(wl.n_points, max(n0, rate0 * target_s)))
     nb = int(round(n * wl.dim * wl.h))
-    pts, bpts = I.collocation_batch(wl, n, nb, seed=12)
-    t = time.time()
-    ON.loss_and_grad(wl, theta, pts, bpts)
-    dt = time.time() - t
+    reps = max(1, min(64, int(target_s * rate0 / n)))
+    dt, done = 0.0, 0
+    for k in range(reps):
+        pts, bpts = I.collocation_batch(wl, n, nb, seed=12 + k)
+        t = time.time()
+        ON.loss_and_grad(wl, theta, pts, bpts)
+        dt += time.time() - t
+        done += n
+        if dt >= target_s:
+            break
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {"value": round(n / dt, 1), "unit": "colloc pts/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n} interior + {nb} boundary points of the same workload, one FP64 step "
-                      f"(loss + gradient), {dt:.1f} s"}
+    return {"value": round(done / dt, 1), "unit": "colloc pts/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done // n} batch(es) of {n} interior + {nb} boundary points of the same workload, "
+                      f"one FP64 step (loss + gradient) each, {dt:.1f} s"}
 
 
 def main():
@@ -218,13 +267,25 @@ def main():
         "kernel_ms_per_step": {k: round(v[0] / max(1, tm["forward"][1]), 4) for k, v in tm.items() if v[1]},
         "roofline": {"bound": "mfma", "kernel": name, "achieved": achieved / 1e12,
                      "peak": PEAK[dtype] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[dtype],
-                     "traffic": None, "flop_per_launch": per_launch, "avg_launch_ms": avg},
+                     "traffic": recorded_traffic() if wl.width == 64 and wl.prec == I.PREC_FP32 else None,
+                     "flop_per_launch": per_launch, "avg_launch_ms": avg},
     }
     if not args.no_accuracy and wl.problem != I.PROB_FOURIER:
         acc = accuracy(wl, res, 64)
         acc["steps_trained"] = res["steps_trained"]
         acc["final_loss"] = res["final_loss"]
         line["accuracy"] = acc
+        if wl.prec == I.PREC_FP32:
+            # the same training in BF16 operands, judged on the same grid solution
+            wb = wl.replace(prec=I.PREC_BF16)
+            rb = run_workload(wb, 10, 3, timing=False, train_to=wb.steps)
+            ab = accuracy(wb, rb, 64, judge=res["judge"])
+            ab["steps_trained"] = rb["steps_trained"]
+            ab["final_loss"] = rb["final_loss"]
+            ab["linf_ratio_bf16_over_fp32"] = ab["linf_vs_grid"] / acc["linf_vs_grid"]
+            line["accuracy_bf16"] = ab
+            del rb
+            torch.cuda.empty_cache()
     if not args.no_extra:
         extra = {}
         for tag, w in (("c2_bf16", wl.replace(prec=I.PREC_BF16)), ("c3_bf16", I.C3),
