@@ -337,6 +337,22 @@ static int check_points(nbm_ctx* ctx, const float* pts, int64_t n, const float* 
   return NBM_OK;
 }
 
+// the hidden matrices of both networks, for one operand-copy launch
+static ShadowJobs shadow_jobs(const nbm_ctx* ctx, const float* params, const Nets& N) {
+  ShadowJobs j;
+  std::memset(&j, 0, sizeof(j));
+  j.params = params;
+  j.W = ctx->W;
+  for (int net = 0; net < 2; ++net)
+    for (int l = 0; l < ctx->L - 1; ++l) {
+      j.off[j.count] = net * ctx->per_net + ctx->lay.Wl[l];
+      j.Wl[j.count] = (void*)N.net[net].Wl[l];
+      j.WlT[j.count] = (void*)N.net[net].WlT[l];
+      ++j.count;
+    }
+  return j;
+}
+
 // forward (+ optional backward) of one batch
 static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const float* pts, int64_t n,
                     const float* bpts, int64_t nb, float* residual, double* loss, float* grad,
@@ -346,12 +362,10 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   // operand shadows of the hidden matrices
   Nets N = nets_for(ctx, params, ws);
   Timer* tprep = new Timer(ctx, st, 0);
-  for (int net = 0; net < 2; ++net)
-    for (int l = 0; l < ctx->L - 1; ++l) {
-      hipError_t e = launch_shadow(st, ctx->cfg.prec, params, net * ctx->per_net + ctx->lay.Wl[l], ctx->W,
-                                   (void*)N.net[net].Wl[l], (void*)N.net[net].WlT[l]);
-      if (e != hipSuccess) return fail(NBM_EHIP, std::string("shadow: ") + hipGetErrorString(e));
-    }
+  {
+    hipError_t e = launch_shadows(st, ctx->cfg.prec, shadow_jobs(ctx, params, N));
+    if (e != hipSuccess) return fail(NBM_EHIP, std::string("shadow: ") + hipGetErrorString(e));
+  }
   // classification and centre lists
   PrepCall pc;
   std::memset(&pc, 0, sizeof(pc));
@@ -408,7 +422,9 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   // residuals, loss and output adjoints
   float* adj = at<float>(ws, Lo.adj);
   Timer* tres = new Timer(ctx, st, 2);
-  if (grad) {
+  if (grad && !fused) {
+    // the layered backward reads every slot's adjoints (the fused kernels only
+    // those the residual kernels write in full)
     e = launch_fill(st, adj, (int64_t)grid * kTile * 8, 0.0f);
     if (e != hipSuccess) { delete tres; return fail(NBM_EHIP, std::string("fill: ") + hipGetErrorString(e)); }
   }
@@ -431,6 +447,10 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   if (!grad) return NBM_OK;
   float* partial = at<float>(ws, Lo.partial);
   int Grows = ctx->G;
+  // the fused paths' loss partials are reduced in the gradient reduction's launch
+  const double* red_lossp = nullptr;
+  int red_nparts = 0;
+  double* red_loss = nullptr;
   if (fused && ctx->wide) {
     int nres = (int)((n + 255) / 256 + (n ? cut_here : 0) + (nb + 255) / 256);
     WideCall wc;
@@ -445,8 +465,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
       e = ctx->wide(wc);
     }
     if (e != hipSuccess) return fail(NBM_EHIP, std::string("wide: ") + hipGetErrorString(e));
-    e = launch_reduce_loss(st, rc.lossp, nres + ctx->Gf, pc.meta, loss_out);
-    if (e != hipSuccess) return fail(NBM_EHIP, std::string("loss: ") + hipGetErrorString(e));
+    red_lossp = rc.lossp; red_nparts = nres + ctx->Gf; red_loss = loss_out;
     Grows = ctx->Gf;
   } else if (fused) {
     int nres = (int)((n + 255) / 256 + (n ? cut_here : 0) + (nb + 255) / 256);
@@ -461,8 +480,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
       e = ctx->fused(fc);
     }
     if (e != hipSuccess) return fail(NBM_EHIP, std::string("fused: ") + hipGetErrorString(e));
-    e = launch_reduce_loss(st, rc.lossp, nres + ctx->Gfz, pc.meta, loss_out);
-    if (e != hipSuccess) return fail(NBM_EHIP, std::string("loss: ") + hipGetErrorString(e));
+    red_lossp = rc.lossp; red_nparts = nres + ctx->Gfz; red_loss = loss_out;
     Grows = ctx->Gfz;
   } else {
     // backward through the hidden layers, gradient partials
@@ -484,7 +502,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   }
   {
     Timer tr(ctx, st, 4);
-    e = launch_reduce_grad(st, partial, Grows, ctx->Ptot, grad, 1.0);
+    e = launch_reduce(st, partial, Grows, ctx->Ptot, grad, 1.0, red_lossp, red_nparts, pc.meta, red_loss);
   }
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("reduce: ") + hipGetErrorString(e));
   return NBM_OK;
@@ -557,12 +575,10 @@ extern "C" int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const f
   Problem P = problem_for(ctx, ws);
   Nets N = nets_for(ctx, params, ws);
   Timer tev(ctx, st, 7);
-  for (int net = 0; net < 2; ++net)
-    for (int l = 0; l < ctx->L - 1; ++l) {
-      hipError_t e = launch_shadow(st, ctx->cfg.prec, params, net * ctx->per_net + ctx->lay.Wl[l], ctx->W,
-                                   (void*)N.net[net].Wl[l], (void*)N.net[net].WlT[l]);
-      if (e != hipSuccess) return fail(NBM_EHIP, std::string("shadow: ") + hipGetErrorString(e));
-    }
+  {
+    hipError_t e = launch_shadows(st, ctx->cfg.prec, shadow_jobs(ctx, params, N));
+    if (e != hipSuccess) return fail(NBM_EHIP, std::string("shadow: ") + hipGetErrorString(e));
+  }
   PrepCall pc;
   std::memset(&pc, 0, sizeof(pc));
   pc.stream = st; pc.P = P; pc.pts = query; pc.n = m; pc.bpts = nullptr; pc.nb = 0; pc.eval = true;

@@ -86,11 +86,10 @@ __device__ inline int classify_point(const Problem& P, const float* xf, double h
 // mode 0: interior points (3 classes), 1: boundary / eval points (2 sides),
 // eval points are either given (pts) or generated from a grid tile.
 template <int D>
-__global__ __launch_bounds__(256) void k_classify(Problem P, const float* pts, int64_t n, int mode,
-                                                  int64_t tile_index, int grid_n, int* cls, int* rank,
-                                                  int* blockcnt) {
-  __shared__ int wcnt[4][4];
-  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ inline void classify_block(const Problem& P, const float* pts, int64_t n, int mode,
+                                      int64_t tile_index, int grid_n, int* cls, int* rank,
+                                      int* blockcnt, int blk, int (*wcnt)[4]) {
+  int64_t i = (int64_t)blk * 256 + threadIdx.x;
   int c = 3;  // 3 = no point
   if (i < n) {
     float xf[3];
@@ -125,7 +124,7 @@ __global__ __launch_bounds__(256) void k_classify(Problem P, const float* pts, i
   if (threadIdx.x < 3) {
     int s = 0;
     for (int v = 0; v < 4; ++v) s += wcnt[v][threadIdx.x];
-    blockcnt[blockIdx.x * 4 + threadIdx.x] = s;
+    blockcnt[blk * 4 + threadIdx.x] = s;
   }
 }
 
@@ -203,15 +202,29 @@ __global__ __launch_bounds__(256) void k_scan(const int* bc_in, int nblk_in, con
 // bnd = 0: interior (or evaluation) points, class < 2 -> KIND_A of that net,
 // class 2 -> KIND_B of both nets (+ low-mu neighbour centres);
 // bnd = 1: boundary points -> KIND_BND of the net of their side.
+// one launch for both point sets: blocks [0, nblk) take the interior (or
+// evaluation) points, the remaining blocks the boundary points
 template <int D>
-__global__ __launch_bounds__(256) void k_scatter(Problem P, const Meta* meta, const float* pts,
-                                                 int64_t n, const int* cls, int* rank, const int* off,
-                                                 int bnd, int64_t tile_index, int grid_n,
-                                                 float4* centres, int* src, int* cutidx) {
-  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_classify(Problem P, const float* pts, int64_t n, int mode,
+                                                  int64_t tile_index, int grid_n, int* cls, int* rank,
+                                                  int* blockcnt, int nblk, const float* bpts, int64_t nb,
+                                                  int* bcls, int* brank, int* blockcnt_b) {
+  __shared__ int wcnt[4][4];
+  if ((int)blockIdx.x < nblk)
+    classify_block<D>(P, pts, n, mode, tile_index, grid_n, cls, rank, blockcnt, blockIdx.x, wcnt);
+  else
+    classify_block<D>(P, bpts, nb, 1, 0, 0, bcls, brank, blockcnt_b, blockIdx.x - nblk, wcnt);
+}
+
+template <int D>
+__device__ inline void scatter_block(const Problem& P, const Meta* meta, const float* pts, int64_t n,
+                                     const int* cls, int* rank, const int* off, int bnd,
+                                     int64_t tile_index, int grid_n, float4* centres, int* src,
+                                     int* cutidx, int blk) {
+  int64_t i = (int64_t)blk * 256 + threadIdx.x;
   if (i >= n) return;
   int c = cls[i];
-  int r = rank[i] + off[blockIdx.x * 4 + c];
+  int r = rank[i] + off[blk * 4 + c];
   rank[i] = r;
   float xf[3] = {0, 0, 0};
   if (pts) {
@@ -246,6 +259,21 @@ __global__ __launch_bounds__(256) void k_scatter(Problem P, const Meta* meta, co
       src[slot] = (int)i;
     }
   }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_scatter(Problem P, const Meta* meta, const float* pts,
+                                                 int64_t n, const int* cls, int* rank, const int* off,
+                                                 int64_t tile_index, int grid_n, float4* centres,
+                                                 int* src, int* cutidx, int nblk, const float* bpts,
+                                                 int64_t nb, const int* bcls, int* brank,
+                                                 const int* off_b) {
+  if ((int)blockIdx.x < nblk)
+    scatter_block<D>(P, meta, pts, n, cls, rank, off, 0, tile_index, grid_n, centres, src, cutidx,
+                     blockIdx.x);
+  else
+    scatter_block<D>(P, meta, bpts, nb, bcls, brank, off_b, 1, 0, 0, centres, src, cutidx,
+                     blockIdx.x - nblk);
 }
 
 // ===========================================================================
@@ -295,35 +323,64 @@ __global__ void k_fill(float* p, int64_t n, float v) {
   if (i < n) p[i] = v;
 }
 
+// operand copies W_l and W_l^T of every hidden matrix (blockIdx.y = matrix)
 template <class T>
-__global__ void k_shadow(const float* params, int64_t off, int W, T* Wl, T* WlT) {
+__global__ void k_shadow(ShadowJobs jobs) {
+  const int W = jobs.W;
+  const int m = blockIdx.y;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= W * W) return;
   int r = i / W, c = i % W;
-  float v = params[off + i];
-  Wl[i] = from_f<T>(v);
-  WlT[c * W + r] = from_f<T>(v);
+  float v = jobs.params[jobs.off[m] + i];
+  ((T*)jobs.Wl[m])[i] = from_f<T>(v);
+  ((T*)jobs.WlT[m])[c * W + r] = from_f<T>(v);
 }
 
-// grad[j] = sum_g partial[g][j] in FP64: 64 columns per block, the rows split
-// over 4 groups (g = k, k+4, ...), group sums added in a fixed order
-__global__ __launch_bounds__(256) void k_reduce_grad(const float* partial, int G, int64_t P,
-                                                     float* grad, double scale) {
-  __shared__ double sh[4][64];
+// grad[j] = scale * sum_g partial[g][j] in FP64: 64 columns per block, the
+// G rows split over 16 groups (g = k, k+16, ...) with four running sums each;
+// group sums are added in a fixed order.  With `loss`, one extra block sums
+// the FP64 loss partials (fixed strided order, then a fixed tree).
+__global__ __launch_bounds__(1024) void k_reduce(const float* partial, int G, int64_t P, float* grad,
+                                                 double scale, const double* lp, int nparts,
+                                                 const Meta* meta, double* loss) {
+  __shared__ double sh[16][64];
   const int c = threadIdx.x & 63, k = threadIdx.x >> 6;
+  if (loss && blockIdx.x == gridDim.x - 1) {
+    double* fl = &sh[0][0];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 1024) acc += lp[i];
+    fl[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) fl[threadIdx.x] += fl[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double L = fl[0] / (double)(meta->n + meta->nb);
+      if (meta->overflow) L = __builtin_nan("");
+      *loss = L;
+    }
+    return;
+  }
   const int64_t j = (int64_t)blockIdx.x * 64 + c;
-  double s0 = 0.0, s1 = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   if (j < P) {
     int g = k;
-    for (; g + 4 < G; g += 8) {
+    for (; g + 48 < G; g += 64) {
       s0 += (double)partial[(int64_t)g * P + j];
-      s1 += (double)partial[(int64_t)(g + 4) * P + j];
+      s1 += (double)partial[(int64_t)(g + 16) * P + j];
+      s2 += (double)partial[(int64_t)(g + 32) * P + j];
+      s3 += (double)partial[(int64_t)(g + 48) * P + j];
     }
-    for (; g < G; g += 4) s0 += (double)partial[(int64_t)g * P + j];
+    for (; g < G; g += 16) s0 += (double)partial[(int64_t)g * P + j];
   }
-  sh[k][c] = s0 + s1;
+  sh[k][c] = (s0 + s1) + (s2 + s3);
   __syncthreads();
-  if (k == 0 && j < P) grad[j] = (float)((((sh[0][c] + sh[1][c]) + sh[2][c]) + sh[3][c]) * scale);
+  if (k == 0 && j < P) {
+    double t = 0.0;
+    for (int q = 0; q < 16; ++q) t += sh[q][c];
+    grad[j] = (float)(t * scale);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_reduce_loss(const double* lp, int nparts, const Meta* meta,
@@ -420,7 +477,12 @@ __global__ __launch_bounds__(256) void k_res_uncut(Problem P, const Meta* meta, 
       if (resid) resid[i] = r;
       r2 = (double)r * (double)r;
       float rb = (float)(scale * (double)r);
-      for (int a = 0; a < D; ++a) adj[slot * 8 + 1 + D + a] = -rb / hh;
+      // the whole adjoint row (u and D streams 0, E streams -rb/h^2)
+      float row[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      for (int a = 0; a < D; ++a) row[1 + D + a] = -rb / hh;
+      float4* dst = (float4*)(adj + slot * 8);
+      dst[0] = make_float4(row[0], row[1], row[2], row[3]);
+      dst[1] = make_float4(row[4], row[5], row[6], row[7]);
     }
   }
   double s = block_sum(r2, sh);
@@ -507,6 +569,10 @@ __global__ __launch_bounds__(64) void k_res_cut(Problem P, const Meta* meta, con
     for (int a = 0; a < 3; ++a) tmom[t][a] = mom[a];
   }
   __syncthreads();
+  // the low-mu neighbour centres (2d consecutive slots) enter through the
+  // lagged normal derivative only, held fixed in the backward: zero adjoints
+  if (P.lo >= 0 && lane < 2 * D * 8)
+    adj[((int64_t)meta->base[P.lo][KIND_NBR] + 2 * D * b) * 8 + lane] = 0.0f;
   if (lane != 0) return;
   const int NT = D == 2 ? 2 : 6;
   double vneg = 0.0, meas = 0.0, mom[3] = {0.0, 0.0, 0.0};
@@ -582,7 +648,7 @@ __global__ __launch_bounds__(64) void k_res_cut(Problem P, const Meta* meta, con
     }
   }
   for (int t = 0; t < 2; ++t)
-    for (int s = 0; s < S; ++s) adj[slot[t] * 8 + s] = (float)g[t][s];
+    for (int s = 0; s < 8; ++s) adj[slot[t] * 8 + s] = s < S ? (float)g[t][s] : 0.0f;
 }
 
 // Dirichlet rows at boundary points: r_b = (2d/h^2)(u - g)
@@ -603,7 +669,9 @@ __global__ __launch_bounds__(256) void k_res_bnd(Problem P, const Meta* meta, co
     float r = w * (outputs[slot * 8] - g_dirichlet<D>(P, x));
     resid[i] = r;
     r2 = (double)r * (double)r;
-    adj[slot * 8] = (float)(scale * (double)r) * w;
+    float4* dst = (float4*)(adj + slot * 8);
+    dst[0] = make_float4((float)(scale * (double)r) * w, 0.f, 0.f, 0.f);
+    dst[1] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   double s = block_sum(r2, sh);
   if (threadIdx.x == 0) lossp[blockIdx.x] = s;
@@ -1099,21 +1167,17 @@ MlpFn find_mlp(int dim, int width, int act, int prec) {
 template <int D>
 static void prep_impl(const PrepCall& c, int64_t nblk, int64_t nblkb) {
   hipStream_t st = c.stream;
-  if (c.n)
-    hipLaunchKernelGGL(k_classify<D>, dim3(nblk), dim3(256), 0, st, c.P, c.pts, c.n, c.eval ? 1 : 0,
-                       c.tile_index, c.grid_n, c.cls, c.rank, c.blockcnt);
-  if (c.nb)
-    hipLaunchKernelGGL(k_classify<D>, dim3(nblkb), dim3(256), 0, st, c.P, c.bpts, c.nb, 1, (int64_t)0,
-                       0, c.bcls, c.brank, c.blockcnt_b);
+  if (c.n + c.nb)
+    hipLaunchKernelGGL(k_classify<D>, dim3(nblk + nblkb), dim3(256), 0, st, c.P, c.pts, c.n,
+                       c.eval ? 1 : 0, c.tile_index, c.grid_n, c.cls, c.rank, c.blockcnt, (int)nblk,
+                       c.bpts, c.nb, c.bcls, c.brank, c.blockcnt_b);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, st, c.blockcnt, (int)nblk, c.blockcnt_b,
                      (int)nblkb, c.off, c.off_b, c.meta, (int)c.n, (int)c.nb, c.cut_cap, D, c.P.lo,
                      c.eval ? 1 : 0);
-  if (c.n)
-    hipLaunchKernelGGL(k_scatter<D>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls,
-                       c.rank, c.off, 0, c.tile_index, c.grid_n, c.centres, c.src, c.cutidx);
-  if (c.nb)
-    hipLaunchKernelGGL(k_scatter<D>, dim3(nblkb), dim3(256), 0, st, c.P, c.meta, c.bpts, c.nb,
-                       c.bcls, c.brank, c.off_b, 1, (int64_t)0, 0, c.centres, c.src, c.cutidx);
+  if (c.n + c.nb)
+    hipLaunchKernelGGL(k_scatter<D>, dim3(nblk + nblkb), dim3(256), 0, st, c.P, c.meta, c.pts, c.n,
+                       c.cls, c.rank, c.off, c.tile_index, c.grid_n, c.centres, c.src, c.cutidx,
+                       (int)nblk, c.bpts, c.nb, c.bcls, c.brank, c.off_b);
 }
 
 hipError_t launch_prep(const PrepCall& c) {
@@ -1187,22 +1251,21 @@ hipError_t launch_fill(hipStream_t st, float* p, int64_t n, float v) {
   return hipGetLastError();
 }
 
-hipError_t launch_shadow(hipStream_t st, int prec, const float* params, int64_t off, int W, void* Wl,
-                         void* WlT) {
-  int n = W * W;
+hipError_t launch_shadows(hipStream_t st, int prec, const ShadowJobs& jobs) {
+  if (jobs.count == 0) return hipSuccess;
+  const int n = jobs.W * jobs.W;
   if (prec == 0)
-    hipLaunchKernelGGL(k_shadow<float>, dim3((n + 255) / 256), dim3(256), 0, st, params, off, W,
-                       (float*)Wl, (float*)WlT);
+    hipLaunchKernelGGL(k_shadow<float>, dim3((n + 255) / 256, jobs.count), dim3(256), 0, st, jobs);
   else
-    hipLaunchKernelGGL(k_shadow<__bf16>, dim3((n + 255) / 256), dim3(256), 0, st, params, off, W,
-                       (__bf16*)Wl, (__bf16*)WlT);
+    hipLaunchKernelGGL(k_shadow<__bf16>, dim3((n + 255) / 256, jobs.count), dim3(256), 0, st, jobs);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_grad(hipStream_t st, const float* partial, int G, int64_t P, float* grad,
-                              double scale) {
-  hipLaunchKernelGGL(k_reduce_grad, dim3((P + 63) / 64), dim3(256), 0, st, partial, G, P, grad,
-                     scale);
+hipError_t launch_reduce(hipStream_t st, const float* partial, int G, int64_t P, float* grad,
+                         double scale, const double* lossp, int nparts, const Meta* meta, double* loss) {
+  const int nblk = (int)((P + 63) / 64) + (loss ? 1 : 0);
+  hipLaunchKernelGGL(k_reduce, dim3(nblk), dim3(1024), 0, st, partial, G, P, grad, scale, lossp, nparts,
+                     meta, loss);
   return hipGetLastError();
 }
 

@@ -130,10 +130,21 @@ hipError_t launch_fill(hipStream_t st, float* p, int64_t n, float v);
 hipError_t launch_forcing(hipStream_t st, const Problem& P, const float* pts, int64_t n, float* f);
 hipError_t launch_fside(hipStream_t st, const Problem& P, const float* pts, const int* cls, int64_t n,
                         float* f);
-hipError_t launch_shadow(hipStream_t st, int prec, const float* params, int64_t off, int W, void* Wl,
-                         void* WlT);
-hipError_t launch_reduce_grad(hipStream_t st, const float* partial, int G, int64_t P, float* grad,
-                              double scale);
+// operand copies (W_l and W_l^T in the operand dtype) of up to 16 hidden
+// matrices (two nets of depth <= 8), one launch
+struct ShadowJobs {
+  const float* params;
+  int64_t off[16];
+  void* Wl[16];
+  void* WlT[16];
+  int count;
+  int W;
+};
+hipError_t launch_shadows(hipStream_t st, int prec, const ShadowJobs& jobs);
+// grad = scale * (FP64 fixed-order sum of the G partial rows); with `loss`,
+// the same launch also reduces the nparts FP64 loss partials
+hipError_t launch_reduce(hipStream_t st, const float* partial, int G, int64_t P, float* grad,
+                         double scale, const double* lossp, int nparts, const Meta* meta, double* loss);
 hipError_t launch_adam(hipStream_t st, float* p, float* m, float* v, const float* g, int64_t n,
                        float lr, float b1, float b2, float eps, float c1, float c2);
 hipError_t launch_sample_points(hipStream_t st, int dim, uint64_t seed, int64_t step, int64_t jh,
