@@ -81,7 +81,7 @@ def run_workload(wl, steps, warmup, seed=1, timing=True, train_to=0):
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     grad = torch.empty_like(params)
-    losses = torch.empty(max(steps + warmup + 32, train_to + 1) + 1, dtype=torch.float64, device=dev)
+    losses = torch.empty(max(2 * steps + warmup + 64, train_to + 1) + 1, dtype=torch.float64, device=dev)
     step = 0
 
     def one(k):
@@ -110,7 +110,17 @@ def run_workload(wl, steps, warmup, seed=1, timing=True, train_to=0):
     ev1.record()
     torch.cuda.synchronize()
     ms_fb = ev0.elapsed_time(ev1) / steps
-    out = {"ms_per_step": ms, "ms_fwd_res_bwd": ms_fb}
+    # per-step distribution: each step bracketed by its own events
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+    for k in range(steps):
+        step += 1
+        evs[2 * k].record()
+        one(step)
+        evs[2 * k + 1].record()
+    torch.cuda.synchronize()
+    per = np.array([evs[2 * k].elapsed_time(evs[2 * k + 1]) for k in range(steps)])
+    out = {"ms_per_step": ms, "ms_fwd_res_bwd": ms_fb,
+           "step_ms_p10_p50_p90": [round(float(np.percentile(per, q)), 4) for q in (10, 50, 90)]}
     if timing:
         counts = nbm.batch_counts().cpu().numpy()
         nbm.set_timing(True)
@@ -193,9 +203,27 @@ def cpu_baseline(wl, target_s=12.0):
         if dt >= target_s:
             break
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    # one thread, on a smaller batch
+    from threadpoolctl import threadpool_limits
+    n1 = 4096
+    pts1, bpts1 = I.collocation_batch(wl, n1, int(round(n1 * wl.dim * wl.h)), seed=40)
+    with threadpool_limits(limits=1):
+        t = time.time()
+        ON.loss_and_grad(wl, theta, pts1, bpts1)
+        dt1 = time.time() - t
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(done / dt, 1), "unit": "colloc pts/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{done // n} batch(es) of {n} interior + {nb} boundary points of the same workload, "
-                      f"one FP64 step (loss + gradient) each, {dt:.1f} s"}
+                      f"one FP64 step (loss + gradient) each, {dt:.1f} s",
+            "single_thread_value": round(n1 / dt1, 1), "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -255,6 +283,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(res["ms_per_step"], 4),
+        "step_ms_p10_p50_p90": res["step_ms_p10_p50_p90"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

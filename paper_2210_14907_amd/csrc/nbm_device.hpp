@@ -31,6 +31,21 @@ __device__ __forceinline__ f4 mfma32(bf8 a, bf8 b, f4 c) {
 __device__ __forceinline__ void mfma_phase_begin() { __builtin_amdgcn_s_setprio(1); }
 __device__ __forceinline__ void mfma_phase_end() { __builtin_amdgcn_s_setprio(0); }
 
+// Sum over the 16 lanes of a DPP row (lanes 16k .. 16k+15) by row rotations
+// (row_ror 8, 4, 2, 1): one VALU add per step, no LDS traffic; lane 16k holds
+// the row sum in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ float row_rotate(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row16_sum(float v) {
+  v += row_rotate<0x128>(v);   // row_ror:8
+  v += row_rotate<0x124>(v);   // row_ror:4
+  v += row_rotate<0x122>(v);   // row_ror:2
+  v += row_rotate<0x121>(v);   // row_ror:1
+  return v;
+}
+
 template <int PREC> struct Op;
 template <> struct Op<0> { typedef float T; static constexpr int bytes = 4; };
 template <> struct Op<1> { typedef __bf16 T; static constexpr int bytes = 2; };

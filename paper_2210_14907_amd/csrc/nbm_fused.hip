@@ -62,6 +62,23 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
   const int ntiles = meta->tiles[0] + meta->tiles[1];
   const float hh = h * h;
   if (tid < kTile) lsum[tid] = 0.0;
+  // this lane's B operand of one layer: row n of W_l (forward) or W_l^T
+  // (backward), K chunk g; loaded one phase ahead of its MFMAs
+  struct WRow { float f[PREC == 0 ? KC : 1]; bf8 b[PREC == 1 ? KC / 8 : 1]; };
+  auto load_w = [&](const void* m) {
+    WRow r;
+    if constexpr (PREC == 0) {
+      const float4* wp = (const float4*)((const float*)m + (int64_t)n * W + g * KC);
+      for (int q = 0; q < KC / 4; ++q) {
+        float4 v4 = wp[q];
+        r.f[4 * q] = v4.x; r.f[4 * q + 1] = v4.y; r.f[4 * q + 2] = v4.z; r.f[4 * q + 3] = v4.w;
+      }
+    } else {
+      const bf8* wp = (const bf8*)((const T*)m + (int64_t)n * W + g * KC);
+      for (int q = 0; q < KC / 8; ++q) r.b[q] = wp[q];
+    }
+    return r;
+  };
 
   for (int net = 0; net < 2; ++net) {
     const NetPtrs& np = nets.net[net];
@@ -111,6 +128,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
           bufR[0][1 + D + a][c][n] = from_f<T>(Ev[a]);
         }
       }
+      WRow wn = load_w(np.Wl[0]);
       __syncthreads();
 
       // ---------------- forward, hidden layers on MFMA
@@ -124,31 +142,23 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
       for (int l = 2; l <= L; ++l) {
         f4 acc[S];
         for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+        const WRow wcur = wn;
         mfma_phase_begin();
         if constexpr (PREC == 0) {
-          float bk[KC];
-          const float4* wp = (const float4*)((const float*)np.Wl[l - 2] + (int64_t)n * W + g * KC);
-          for (int q = 0; q < KC / 4; ++q) {
-            float4 v4 = wp[q];
-            bk[4 * q] = v4.x; bk[4 * q + 1] = v4.y; bk[4 * q + 2] = v4.z; bk[4 * q + 3] = v4.w;
-          }
           for (int s = 0; s < S; ++s) {
             const float4* ap = (const float4*)(&bufR[cur][s][r16][g * KC]);
             for (int q = 0; q < KC / 4; ++q) {
               float4 a4 = ap[q];
-              acc[s] = mfma4(a4.x, bk[4 * q], acc[s]);
-              acc[s] = mfma4(a4.y, bk[4 * q + 1], acc[s]);
-              acc[s] = mfma4(a4.z, bk[4 * q + 2], acc[s]);
-              acc[s] = mfma4(a4.w, bk[4 * q + 3], acc[s]);
+              acc[s] = mfma4(a4.x, wcur.f[4 * q], acc[s]);
+              acc[s] = mfma4(a4.y, wcur.f[4 * q + 1], acc[s]);
+              acc[s] = mfma4(a4.z, wcur.f[4 * q + 2], acc[s]);
+              acc[s] = mfma4(a4.w, wcur.f[4 * q + 3], acc[s]);
             }
           }
         } else {
-          bf8 bk[KC / 8];
-          const bf8* wp = (const bf8*)((const T*)np.Wl[l - 2] + (int64_t)n * W + g * KC);
-          for (int q = 0; q < KC / 8; ++q) bk[q] = wp[q];
           for (int s = 0; s < S; ++s) {
             const bf8* ap = (const bf8*)(&bufR[cur][s][r16][g * KC]);
-            for (int q = 0; q < KC / 8; ++q) acc[s] = mfma32(ap[q], bk[q], acc[s]);
+            for (int q = 0; q < KC / 8; ++q) acc[s] = mfma32(ap[q], wcur.b[q], acc[s]);
           }
         }
         mfma_phase_end();
@@ -189,11 +199,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
             vals[0] = av;
             for (int a = 0; a < D; ++a) { vals[1 + a] = Dv[a]; vals[1 + D + a] = Ev[a]; }
             for (int s = 0; s < S; ++s) {
-              float v = won * vals[s];
-              v += __shfl_xor(v, 8);
-              v += __shfl_xor(v, 4);
-              v += __shfl_xor(v, 2);
-              v += __shfl_xor(v, 1);
+              const float v = row16_sum(won * vals[s]);
               if (r16 == 0) part[w][c][s] = v;
             }
             // d loss / d w_out[n] = sum_c sum_s adj[c][s] a_L[s][n][c]
@@ -206,6 +212,8 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
             }
           }
         }
+        // next phase's weights: the following layer, or the first backward layer
+        wn = load_w(l < L ? np.Wl[l - 1] : np.WlT[L - 2]);
         __syncthreads();
         cur ^= 1;
       }
@@ -259,31 +267,24 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
         __syncthreads();
         f4 acc[S];
         for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+        const WRow wcur = wn;
+        if (l > 2) wn = load_w(np.WlT[l - 3]);   // next backward layer's weights
         mfma_phase_begin();
         if constexpr (PREC == 0) {
-          float bk[KC];
-          const float4* wp = (const float4*)((const float*)np.WlT[l - 2] + (int64_t)n * W + g * KC);
-          for (int q = 0; q < KC / 4; ++q) {
-            float4 v4 = wp[q];
-            bk[4 * q] = v4.x; bk[4 * q + 1] = v4.y; bk[4 * q + 2] = v4.z; bk[4 * q + 3] = v4.w;
-          }
           for (int s = 0; s < S; ++s) {
             const float4* ap = (const float4*)(&bufR[bb][s][r16][g * KC]);
             for (int q = 0; q < KC / 4; ++q) {
               float4 a4 = ap[q];
-              acc[s] = mfma4(a4.x, bk[4 * q], acc[s]);
-              acc[s] = mfma4(a4.y, bk[4 * q + 1], acc[s]);
-              acc[s] = mfma4(a4.z, bk[4 * q + 2], acc[s]);
-              acc[s] = mfma4(a4.w, bk[4 * q + 3], acc[s]);
+              acc[s] = mfma4(a4.x, wcur.f[4 * q], acc[s]);
+              acc[s] = mfma4(a4.y, wcur.f[4 * q + 1], acc[s]);
+              acc[s] = mfma4(a4.z, wcur.f[4 * q + 2], acc[s]);
+              acc[s] = mfma4(a4.w, wcur.f[4 * q + 3], acc[s]);
             }
           }
         } else {
-          bf8 bk[KC / 8];
-          const bf8* wp = (const bf8*)((const T*)np.WlT[l - 2] + (int64_t)n * W + g * KC);
-          for (int q = 0; q < KC / 8; ++q) bk[q] = wp[q];
           for (int s = 0; s < S; ++s) {
             const bf8* ap = (const bf8*)(&bufR[bb][s][r16][g * KC]);
-            for (int q = 0; q < KC / 8; ++q) acc[s] = mfma32(ap[q], bk[q], acc[s]);
+            for (int q = 0; q < KC / 8; ++q) acc[s] = mfma32(ap[q], wcur.b[q], acc[s]);
           }
         }
         mfma_phase_end();

@@ -196,11 +196,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
             vals[0] = av;
             for (int a = 0; a < D; ++a) { vals[1 + a] = Dv[a]; vals[1 + D + a] = Ev[a]; }
             for (int s = 0; s < S; ++s) {
-              float v = won * vals[s];
-              v += __shfl_xor(v, 8);
-              v += __shfl_xor(v, 4);
-              v += __shfl_xor(v, 2);
-              v += __shfl_xor(v, 1);
+              const float v = row16_sum(won * vals[s]);
               if (r16 == 0) part[w][c][s] = v;
             }
             // d loss / d w_out[n] = sum_c sum_s adj[c][s] a_L[s][n][c]
