@@ -22,12 +22,6 @@
 
 namespace nbm {
 
-__device__ inline int wide_tile_net(const Meta* m, int t) {
-  if (t < m->tiles[0]) return 0;
-  if (t < m->tiles[0] + m->tiles[1]) return 1;
-  return -1;
-}
-
 template <int D, int W, int L, int ACT, int PREC>
 __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float4* centres,
                                                    const int* src, Nets nets, Problem P, float h,
@@ -329,9 +323,12 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
   }
 }
 
-// dW_l partials: wave w owns out-blocks {w, w+4, ...}, all in-blocks
+// dW_l partials.  A work-group of 8 wavefronts: waves w and w+4 (one SIMD)
+// form two halves that take alternate tiles (twice the loads in flight);
+// within a half, wave w owns out-blocks {w, w+4, ...} and all in-blocks.  The
+// halves' accumulators are added in a fixed order through LDS at the end.
 template <int D, int W, int PREC>
-__global__ __launch_bounds__(256) void k_wide_dw(const Meta* meta, const void* A_, const void* dZ_,
+__global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A_, const void* dZ_,
                                                  float* partial, int64_t Ptot, int64_t woff,
                                                  int64_t net_off1) {
   typedef typename Op<PREC>::T T;
@@ -340,15 +337,17 @@ __global__ __launch_bounds__(256) void k_wide_dw(const Meta* meta, const void* A
   constexpr int OBW = NOB / 4;
   const T* A = (const T*)A_;
   const T* dZ = (const T*)dZ_;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r16 = lane & 15, g = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, w = (tid >> 6) & 3, half = tid >> 8;
+  const int r16 = lane & 15, g = lane >> 4;
   const int G = gridDim.x;
-  const int ntiles = meta->tiles[0] + meta->tiles[1];
+  __shared__ f4 xch[OBW][NOB][256];   // the second half's accumulators
   for (int net = 0; net < 2; ++net) {
+    const int t_lo = net == 0 ? 0 : meta->tiles[0];
+    const int t_hi = net == 0 ? meta->tiles[0] : meta->tiles[0] + meta->tiles[1];
     f4 acc[OBW][NOB];
     for (int i = 0; i < OBW; ++i)
       for (int k = 0; k < NOB; ++k) acc[i][k] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int t = blockIdx.x; t < ntiles; t += G) {
-      if (wide_tile_net(meta, t) != net) continue;
+    for (int t = t_lo + blockIdx.x + half * G; t < t_hi; t += 2 * G) {
       auto tofs = [&](int s, int nn) -> int64_t { return (((int64_t)t * S + s) * W + nn) * kTile + 4 * g; };
       if constexpr (PREC == 0) {
         float dzv[OBW][S][4];
@@ -386,13 +385,23 @@ __global__ __launch_bounds__(256) void k_wide_dw(const Meta* meta, const void* A
           }
       }
     }
-    float* prow = partial + (int64_t)blockIdx.x * Ptot + (net == 0 ? 0 : net_off1) + woff;
-    for (int i = 0; i < OBW; ++i)
-      for (int ib = 0; ib < NOB; ++ib)
-        for (int r = 0; r < 4; ++r) {
-          int row = (w + 4 * i) * 16 + 4 * g + r, col = ib * 16 + r16;
-          prow[(int64_t)row * W + col] = acc[i][ib][r];
+    // first half + second half, in that order
+    if (half == 1)
+      for (int i = 0; i < OBW; ++i)
+        for (int ib = 0; ib < NOB; ++ib) xch[i][ib][tid - 256] = acc[i][ib];
+    __syncthreads();
+    if (half == 0) {
+      float* prow = partial + (int64_t)blockIdx.x * Ptot + (net == 0 ? 0 : net_off1) + woff;
+      for (int i = 0; i < OBW; ++i)
+        for (int ib = 0; ib < NOB; ++ib) {
+          const f4 o = xch[i][ib][tid];
+          for (int r = 0; r < 4; ++r) {
+            int row = (w + 4 * i) * 16 + 4 * g + r, col = ib * 16 + r16;
+            prow[(int64_t)row * W + col] = acc[i][ib][r] + o[r];
+          }
         }
+    }
+    __syncthreads();
   }
 }
 
@@ -405,7 +414,7 @@ hipError_t wide_impl(const WideCall& c) {
   if (e != hipSuccess) return e;
   for (int l = 2; l <= L; ++l) {
     if (c.timer_begin) c.timer_begin(c.timer_ctx);
-    hipLaunchKernelGGL((k_wide_dw<D, W, PREC>), dim3(c.grid), dim3(256), 0, c.stream, c.meta,
+    hipLaunchKernelGGL((k_wide_dw<D, W, PREC>), dim3(c.grid), dim3(512), 0, c.stream, c.meta,
                        (const char*)c.A + (int64_t)(l - 2) * c.lstride * Op<PREC>::bytes,
                        (const char*)c.dZ + (int64_t)(l - 2) * c.lstride * Op<PREC>::bytes, c.partial,
                        c.Ptot, c.lay->Wl[l - 2], c.off1);
