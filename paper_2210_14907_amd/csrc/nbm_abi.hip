@@ -30,7 +30,7 @@ static int fail(int code, const std::string& msg) {
 namespace {
 struct Layout {
   size_t modes32, modes64, meta, blockcnt, off, blockcnt_b, off_b, cls, rank, bcls, brank, cutidx,
-      centres, src, outputs, adj, Zst, Ast, ALst, dZ, dZw, shadow, partial, lossp, resid, lossbuf, fpre, fside, total;
+      centres, src, outputs, adj, Zst, Ast, ALst, dZ, dZw, shadow, partial, lossp, resid, lossbuf, fpre, fslot, total;
 };
 }  // namespace
 
@@ -125,9 +125,10 @@ static void make_layout(nbm_ctx* c) {
   L.resid = take_tr(sizeof(float) * (c->cap_n + c->cap_nb));
   L.lossbuf = take(sizeof(double) * 4);
   L.fpre = take_tr(c->cfg.problem == NBM_PROB_FOURIER ? sizeof(float) * c->cap_n : 0);
-  // forcing on each uncut point's own side, for the fused paths' inline tiles
+  // forcing of the uncut centres in centre-slot order, for the fused paths'
+  // inline tiles
   const bool fused_path = !c->no_fused && (c->fused || c->wide) && !c->eval_only;
-  L.fside = take_tr(fused_path && c->cfg.problem != NBM_PROB_FOURIER ? sizeof(float) * c->cap_n : 0);
+  L.fslot = take_tr(fused_path ? sizeof(float) * c->cap_slots : 0);
   L.total = o;
 }
 
@@ -380,18 +381,15 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   pc.src = at<int>(ws, Lo.src);
   pc.cutidx = at<int>(ws, Lo.cutidx);
   hipError_t e = launch_prep(pc);
+  // the fused kernels read the forcing of their uncut centres in slot order
+  const bool fused_step = grad != nullptr && (ctx->fused != nullptr || ctx->wide != nullptr) && !ctx->no_fused;
+  float* f_inline = fused_step ? at<float>(ws, Lo.fslot) : nullptr;
   const float* fpre = nullptr;
   if (ctx->cfg.problem == NBM_PROB_FOURIER && n > 0) {
     fpre = at<float>(ws, Lo.fpre);
-    if (e == hipSuccess) e = launch_forcing(st, P, pts, n, (float*)fpre);
-  }
-  // the fused kernels read the forcing of their uncut centres from here
-  const float* f_inline = fpre;
-  const bool fused_step = grad != nullptr && (ctx->fused != nullptr || ctx->wide != nullptr) && !ctx->no_fused;
-  if (fused_step && !fpre && n > 0) {
-    float* fs = at<float>(ws, Lo.fside);
-    if (e == hipSuccess) e = launch_fside(st, P, pts, pc.cls, n, fs);
-    f_inline = fs;
+    if (e == hipSuccess) e = launch_forcing(st, P, pts, n, (float*)fpre, pc.meta, pc.cls, pc.rank, f_inline);
+  } else if (fused_step && n > 0) {
+    if (e == hipSuccess) e = launch_fside(st, P, pts, pc.cls, pc.rank, pc.meta, n, f_inline);
   }
   delete tprep;
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("prep: ") + hipGetErrorString(e));
@@ -459,7 +457,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
     wc.nets = &N; wc.P = P; wc.h = (float)ctx->cfg.h; wc.adj = adj; wc.resid = rc.resid;
     wc.A = at<void>(ws, Lo.Ast); wc.dZ = at<void>(ws, Lo.dZw); wc.lstride = ctx->lstride;
     wc.partial = partial; wc.Ptot = ctx->Ptot; wc.lay = &ctx->lay; wc.off1 = ctx->per_net;
-    wc.lossp = rc.lossp + nres; wc.scale = rc.scale; wc.fpre = f_inline;
+    wc.lossp = rc.lossp + nres; wc.scale = rc.scale; wc.fslot = f_inline;
     {
       Timer tb(ctx, st, 3);
       e = ctx->wide(wc);
@@ -474,7 +472,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
     fc.stream = st; fc.grid = ctx->Gfz; fc.meta = pc.meta; fc.centres = pc.centres; fc.src = pc.src;
     fc.nets = &N; fc.P = P; fc.h = (float)ctx->cfg.h; fc.adj = adj; fc.resid = rc.resid;
     fc.partial = partial; fc.Ptot = ctx->Ptot; fc.lay = &ctx->lay; fc.off1 = ctx->per_net;
-    fc.lossp = rc.lossp + nres; fc.scale = rc.scale; fc.fpre = f_inline;
+    fc.lossp = rc.lossp + nres; fc.scale = rc.scale; fc.fslot = f_inline;
     {
       Timer tb(ctx, st, 3);
       e = ctx->fused(fc);

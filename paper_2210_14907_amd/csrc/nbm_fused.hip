@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
                                                   Nets nets, Problem P, float h, const float* adj,
                                                   float* resid, float* partial, int64_t Ptot,
                                                   NetLayout lay, int64_t net_off1, double* lossp,
-                                                  double scale, const float* fpre) {
+                                                  double scale, const float* fslot) {
   typedef typename Op<PREC>::T T;
   constexpr int S = 2 * D + 1;
   constexpr int LD = W + (PREC == 0 ? 4 : 8);
@@ -97,20 +97,33 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
     const int t_lo = net == 0 ? 0 : meta->tiles[0];
     const int t_hi = net == 0 ? meta->tiles[0] : ntiles;
 
+    const int64_t slot_end = (int64_t)meta->tile0[net] * kTile + meta->total[net];
+    // per-tile global data (centres; forcing of inline tiles; adjoint rows of
+    // the others) is fetched one tile ahead, so its latency hides behind the
+    // current tile's work
+    float4 nx = make_float4(0.f, 0.f, 0.f, 0.f);
+    float nf = 0.f, na = 0.f;
+    int ns = 0;
+    auto fetch = [&](int tt) {
+      const int64_t s0 = (int64_t)tt * kTile;
+      if (tt >= t_hi) return;
+      if (tid < kTile) {
+        nx = s0 + tid < slot_end ? centres[s0 + tid] : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (s0 + kTile <= a_end) { nf = fslot[s0 + tid]; ns = src[s0 + tid]; }
+      }
+      if (s0 + kTile > a_end && tid < kTile * 8) na = s0 + tid / 8 < slot_end ? adj[s0 * 8 + tid] : 0.f;
+    };
+    fetch(t_lo + blockIdx.x);
+
     for (int t = t_lo + blockIdx.x; t < t_hi; t += G) {
       const int64_t slot0 = (int64_t)t * kTile;
-      const int64_t slot_end = (int64_t)meta->tile0[net] * kTile + meta->total[net];
       const bool inl = slot0 + kTile <= a_end;   // uniform over the work-group
-      if (tid < kTile) {
-        float4 cc = centres[slot0 + tid];
-        if (slot0 + tid >= slot_end) cc = make_float4(0.f, 0.f, 0.f, 0.f);
-        xs[tid][0] = cc.x; xs[tid][1] = cc.y; xs[tid][2] = cc.z; xs[tid][3] = 0.f;
-      }
-      if (!inl && tid < kTile * 8) {
-        // output adjoints of a non-inline tile, written by the residual kernels
-        const int64_t slot = slot0 + tid / 8;
-        adjs[tid / 8][tid % 8] = slot < slot_end ? adj[slot0 * 8 + tid] : 0.f;
-      }
+      if (tid < kTile) { xs[tid][0] = nx.x; xs[tid][1] = nx.y; xs[tid][2] = nx.z; xs[tid][3] = 0.f; }
+      // output adjoints of a non-inline tile, written by the residual kernels
+      if (!inl && tid < kTile * 8) adjs[tid / 8][tid % 8] = na;
+      const float fcur = nf;   // forcing and point index of this lane's centre (inline tiles)
+      const int scur = ns;
+      fetch(t + G);
       __syncthreads();
 
       // ---------------- forward, layer 1 (VALU, accumulator mapping)
@@ -222,12 +235,12 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
       if (inl && tid < kTile) {
         const int c = tid;
         const int64_t slot = slot0 + c;
-        const float f = fpre[src[slot]];
+        const float f = fcur;
         float eu = 0.f;
         for (int a = 0; a < D; ++a)
           for (int v = 0; v < NOB; ++v) eu += part[v][c][1 + D + a];
         float r = -eu / hh - f / (float)P.mu[net];
-        resid[src[slot]] = r;
+        resid[scur] = r;
         lsum[c] += (double)r * (double)r;
         float rb = (float)(scale * (double)r);
         for (int s = 0; s < 8; ++s) adjs[c][s] = 0.f;
@@ -372,7 +385,7 @@ template <int D, int W, int L, int ACT, int PREC>
 hipError_t fused_impl(const FusedCall& c) {
   hipLaunchKernelGGL((k_fused<D, W, L, ACT, PREC>), dim3(c.grid), dim3(256), 0, c.stream, c.meta,
                      c.centres, c.src, *c.nets, c.P, c.h, c.adj, c.resid, c.partial, c.Ptot, *c.lay,
-                     c.off1, c.lossp, c.scale, c.fpre);
+                     c.off1, c.lossp, c.scale, c.fslot);
   return hipGetLastError();
 }
 

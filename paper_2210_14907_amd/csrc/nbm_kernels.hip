@@ -282,7 +282,8 @@ __global__ __launch_bounds__(256) void k_scatter(Problem P, const Meta* meta, co
 // ===========================================================================
 template <int D>
 __global__ __launch_bounds__(256) void k_forcing(Problem P, const float* pts, int64_t n,
-                                                 float* fout) {
+                                                 float* fout, const Meta* meta, const int* cls,
+                                                 const int* rank, float* fslot) {
   __shared__ float ph[256][D][9][2];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int t = threadIdx.x;
@@ -312,7 +313,14 @@ __global__ __launch_bounds__(256) void k_forcing(Problem P, const float* pts, in
     }
     acc += md[3] * re + md[4] * im;
   }
-  if (i < n) fout[i] = acc;
+  if (i < n) {
+    fout[i] = acc;
+    // the same value in centre-slot order for uncut points (tile kernels)
+    if (fslot) {
+      const int c = cls[i];
+      if (c < 2) fslot[meta->base[c][KIND_A] + rank[i]] = acc;
+    }
+  }
 }
 
 // ===========================================================================
@@ -1213,35 +1221,38 @@ hipError_t launch_reduce_loss(hipStream_t st, const double* lossp, int nparts, c
   return hipGetLastError();
 }
 
-// Forcing f/1 on the side of each uncut point (class 0: Omega^-, class 1:
-// Omega^+), for the fused kernels' inline tiles; cut points are left 0.
+// Forcing on the side of each uncut point (class 0: Omega^-, class 1:
+// Omega^+), written in centre-slot order for the tile kernels' inline tiles.
 template <int D>
-__global__ __launch_bounds__(256) void k_fside(Problem P, const float* pts, const int* cls, int64_t n,
-                                               float* fout) {
+__global__ __launch_bounds__(256) void k_fside(Problem P, const float* pts, const int* cls,
+                                               const int* rank, const Meta* meta, int64_t n,
+                                               float* fslot) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const int c = cls[i];
+  if (c >= 2) return;
   float x[3] = {0.f, 0.f, 0.f};
   for (int a = 0; a < D; ++a) x[a] = pts[i * D + a];
-  fout[i] = c < 2 ? f_side<float, D>(P, c, x) : 0.0f;
+  fslot[meta->base[c][KIND_A] + rank[i]] = f_side<float, D>(P, c, x);
 }
 
-hipError_t launch_fside(hipStream_t st, const Problem& P, const float* pts, const int* cls, int64_t n,
-                        float* f) {
+hipError_t launch_fside(hipStream_t st, const Problem& P, const float* pts, const int* cls,
+                        const int* rank, const Meta* meta, int64_t n, float* fslot) {
   if (n == 0) return hipSuccess;
   if (P.dim == 2)
-    hipLaunchKernelGGL(k_fside<2>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, cls, n, f);
+    hipLaunchKernelGGL(k_fside<2>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, cls, rank, meta, n, fslot);
   else
-    hipLaunchKernelGGL(k_fside<3>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, cls, n, f);
+    hipLaunchKernelGGL(k_fside<3>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, cls, rank, meta, n, fslot);
   return hipGetLastError();
 }
 
-hipError_t launch_forcing(hipStream_t st, const Problem& P, const float* pts, int64_t n, float* f) {
+hipError_t launch_forcing(hipStream_t st, const Problem& P, const float* pts, int64_t n, float* f,
+                          const Meta* meta, const int* cls, const int* rank, float* fslot) {
   if (n == 0) return hipSuccess;
   if (P.dim == 2)
-    hipLaunchKernelGGL(k_forcing<2>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, n, f);
+    hipLaunchKernelGGL(k_forcing<2>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, n, f, meta, cls, rank, fslot);
   else
-    hipLaunchKernelGGL(k_forcing<3>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, n, f);
+    hipLaunchKernelGGL(k_forcing<3>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, n, f, meta, cls, rank, fslot);
   return hipGetLastError();
 }
 

@@ -33,7 +33,7 @@ typedef hipError_t (*MlpFn)(const MlpCall&);
 MlpFn find_mlp(int dim, int width, int act, int prec);
 
 struct FusedCall {
-  const float* fpre;   // forcing per interior point on its own side (read for uncut centres)
+  const float* fslot;  // forcing of uncut centres in centre-slot order
   hipStream_t stream;
   int grid;
   const Meta* meta;
@@ -55,7 +55,7 @@ typedef hipError_t (*FusedFn)(const FusedCall&);
 FusedFn find_fused(int dim, int width, int depth, int act, int prec);
 
 struct WideCall {
-  const float* fpre;   // forcing per interior point on its own side (read for uncut centres)
+  const float* fslot;  // forcing of uncut centres in centre-slot order
   hipStream_t stream;
   int grid;
   const Meta* meta;
@@ -127,9 +127,13 @@ hipError_t launch_reduce_loss(hipStream_t st, const double* lossp, int nparts, c
                               double* loss);
 
 hipError_t launch_fill(hipStream_t st, float* p, int64_t n, float v);
-hipError_t launch_forcing(hipStream_t st, const Problem& P, const float* pts, int64_t n, float* f);
-hipError_t launch_fside(hipStream_t st, const Problem& P, const float* pts, const int* cls, int64_t n,
-                        float* f);
+// Fourier forcing per interior point (f), and with fslot != NULL the same
+// values in centre-slot order for uncut points
+hipError_t launch_forcing(hipStream_t st, const Problem& P, const float* pts, int64_t n, float* f,
+                          const Meta* meta, const int* cls, const int* rank, float* fslot);
+// manufactured forcing of uncut points on their own side, in centre-slot order
+hipError_t launch_fside(hipStream_t st, const Problem& P, const float* pts, const int* cls,
+                        const int* rank, const Meta* meta, int64_t n, float* fslot);
 // operand copies (W_l and W_l^T in the operand dtype) of up to 16 hidden
 // matrices (two nets of depth <= 8), one launch
 struct ShadowJobs {

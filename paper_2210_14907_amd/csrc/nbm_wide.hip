@@ -28,7 +28,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
                                                    const float* adj, float* resid, void* Aout_,
                                                    void* dZout_, int64_t lstride, float* partial,
                                                    int64_t Ptot, NetLayout lay, int64_t net_off1,
-                                                   double* lossp, double scale, const float* fpre) {
+                                                   double* lossp, double scale, const float* fslot) {
   typedef typename Op<PREC>::T T;
   constexpr int S = 2 * D + 1;
   constexpr int LD = W + (PREC == 0 ? 4 : 8);
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           float eu = 0.f;
           for (int a = 0; a < D; ++a)
             for (int v = 0; v < NW; ++v) eu += part[v][c][1 + D + a];
-          float r = -eu / hh - fpre[src[slot]] / (float)P.mu[net];
+          float r = -eu / hh - fslot[slot] / (float)P.mu[net];
           resid[src[slot]] = r;
           lsum[c] += (double)r * (double)r;
           float rb = (float)(scale * (double)r);
@@ -409,7 +409,7 @@ template <int D, int W, int L, int ACT, int PREC>
 hipError_t wide_impl(const WideCall& c) {
   hipLaunchKernelGGL((k_wide_fb<D, W, L, ACT, PREC>), dim3(c.grid), dim3(W * 4), 0, c.stream, c.meta,
                      c.centres, c.src, *c.nets, c.P, c.h, c.adj, c.resid, c.A, c.dZ, c.lstride,
-                     c.partial, c.Ptot, *c.lay, c.off1, c.lossp, c.scale, c.fpre);
+                     c.partial, c.Ptot, *c.lay, c.off1, c.lossp, c.scale, c.fslot);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   for (int l = 2; l <= L; ++l) {
