@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/nbm.h"
@@ -29,7 +30,7 @@ static int fail(int code, const std::string& msg) {
 
 namespace {
 struct Layout {
-  size_t modes32, modes64, meta, blockcnt, off, blockcnt_b, off_b, cls, rank, bcls, brank, cutidx,
+  size_t modes32, modes64, fmodes, meta, blockcnt, off, blockcnt_b, off_b, cls, rank, bcls, brank, cutidx,
       centres, src, outputs, adj, Zst, Ast, ALst, dZ, dZw, shadow, partial, lossp, resid, lossbuf, fpre, fslot, total;
 };
 }  // namespace
@@ -46,6 +47,7 @@ struct nbm_ctx {
   nbm_config cfg;
   std::vector<float> modes32;
   std::vector<double> modes64;
+  std::vector<FMode> fmodes;
   Problem P;
   MlpFn mlp;
   FusedFn fused;
@@ -97,6 +99,7 @@ static void make_layout(nbm_ctx* c) {
   int64_t nblkc = (c->cut_cap + 255) / 256 + 1;
   L.modes32 = take(sizeof(float) * 8 * (c->cfg.n_modes + 1));
   L.modes64 = take(sizeof(double) * 5 * (c->cfg.n_modes + 1));
+  L.fmodes = take(sizeof(FMode) * (c->fmodes.size() + 1));
   L.meta = take(sizeof(Meta));
   L.blockcnt = take(sizeof(int) * 4 * nblk);
   L.off = take(sizeof(int) * 4 * nblk);
@@ -217,6 +220,38 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
       x->modes64[5 * m + 3] = c.mode_a[m];
       x->modes64[5 * m + 4] = c.mode_b[m];
     }
+    // grouped by (k_y, k_z): a*cos(pi k.x) + b*sin(pi k.x) = Re(c e^{i pi k.x}),
+    // c = a - i b; e^{-i t} = conj(e^{i t}) handles negative wave numbers
+    std::map<std::pair<int, int>, std::vector<int>> byyz;
+    for (int m = 0; m < P.n_modes; ++m) byyz[{c.mode_k[3 * m + 1], c.mode_k[3 * m + 2]}].push_back(m);
+    constexpr int kRow = 256 * 8;   // bytes per phase row
+    for (const auto& kv : byyz) {
+      const int ky = kv.first.first, kz = kv.first.second;
+      const int oy = (9 + std::abs(ky)) * kRow + (ky < 0 ? 1 : 0);
+      const int oz = (18 + std::abs(kz)) * kRow + (kz < 0 ? 1 : 0);
+      for (size_t q = 0; q < kv.second.size(); ++q) {
+        const int m = kv.second[q];
+        FMode M;
+        std::memset(&M, 0, sizeof(M));
+        const int kx = c.mode_k[3 * m];
+        const float sx = kx < 0 ? -1.0f : 1.0f;
+        M.ox = std::abs(kx) * kRow;
+        M.cr = (float)c.mode_a[m];
+        M.ci = (float)(-c.mode_b[m]);
+        M.crs = M.cr * sx;
+        M.cis = M.ci * sx;
+        M.oy = oy;
+        M.oz = oz;
+        M.end = q + 1 == kv.second.size() ? 1 : 0;
+        x->fmodes.push_back(M);
+      }
+    }
+    while (x->fmodes.size() % 8) {
+      FMode Z;
+      std::memset(&Z, 0, sizeof(Z));
+      x->fmodes.push_back(Z);
+    }
+    P.n_fmodes = (int)x->fmodes.size();
   }
   x->cfg.n_modes = P.n_modes;
   // capacities
@@ -294,6 +329,7 @@ extern "C" int nbm_prepare(nbm_ctx* ctx, void* stream, void* ws, size_t ws_bytes
   if (ctx->P.n_modes) {
     HIPCHK(hipMemcpyAsync(at<char>(ws, ctx->lo.modes32), ctx->modes32.data(), sizeof(float) * ctx->modes32.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(at<char>(ws, ctx->lo.modes64), ctx->modes64.data(), sizeof(double) * ctx->modes64.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(at<char>(ws, ctx->lo.fmodes), ctx->fmodes.data(), sizeof(FMode) * ctx->fmodes.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
   }
   ctx->prepared_ws = ws;
@@ -304,6 +340,7 @@ static Problem problem_for(nbm_ctx* ctx, void* ws) {
   Problem P = ctx->P;
   P.modes32 = at<float>(ws, ctx->lo.modes32);
   P.modes64 = at<double>(ws, ctx->lo.modes64);
+  P.fmodes = at<FMode>(ws, ctx->lo.fmodes);
   return P;
 }
 

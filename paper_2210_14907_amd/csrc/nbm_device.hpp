@@ -715,53 +715,6 @@ __device__ inline T fourier_f(const Problem& P, const T* x) {
   return acc;
 }
 
-// Fourier forcing of the 16 centres of a tile, computed by all NT threads of
-// the work-group: per-axis phase factors exp(i pi k x_a), k = 0..8, go to LDS,
-// the modes are split over thread groups and the group sums are added in a
-// fixed order.  scratch must hold kTile*(D*18 + NT/kTile) floats.  Ends with
-// a barrier; fout[c] is then valid for c < kTile.
-template <int D, int NT>
-__device__ inline void tile_fourier(const Problem& P, const float (*xs)[4], float* scratch,
-                                    float* fout) {
-  constexpr int NG = NT / kTile;
-  float* ph = scratch;                          // [c][a][k][2]
-  float* part = scratch + kTile * D * 18;       // [group][c]
-  const int tid = threadIdx.x;
-  for (int i = tid; i < kTile * D * 9; i += NT) {
-    const int c = i / (D * 9), a = (i / 9) % D, k = i % 9;
-    float sv, cv;
-    sincospif((float)k * xs[c][a], &sv, &cv);
-    ph[2 * i] = cv;
-    ph[2 * i + 1] = sv;
-  }
-  __syncthreads();
-  const int c = tid % kTile, grp = tid / kTile;
-  float acc = 0.0f;
-  for (int m = grp; m < P.n_modes; m += NG) {
-    const float* md = P.modes32 + 8 * m;
-    float re = 1.0f, im = 0.0f;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const int k = (int)md[a];
-      const int kk = k < 0 ? -k : k;
-      const float fr = ph[2 * ((c * D + a) * 9 + kk)];
-      const float fi = (k < 0 ? -1.0f : 1.0f) * ph[2 * ((c * D + a) * 9 + kk) + 1];
-      const float nr = re * fr - im * fi;
-      im = re * fi + im * fr;
-      re = nr;
-    }
-    acc += md[3] * re + md[4] * im;
-  }
-  part[grp * kTile + c] = acc;
-  __syncthreads();
-  if (tid < kTile) {
-    float sacc = 0.0f;
-    for (int g2 = 0; g2 < NG; ++g2) sacc += part[g2 * kTile + tid];
-    fout[tid] = sacc;
-  }
-  __syncthreads();
-}
-
 template <class T, int D>
 __device__ inline T f_side(const Problem& P, int s, const T* x) {
   T mu = T(P.mu[s]);

@@ -12,6 +12,18 @@ constexpr int kBlock = 256;    // threads per work-group (4 wavefronts)
 enum Kind { KIND_A = 0, KIND_B = 1, KIND_NBR = 2, KIND_BND = 3 };
 
 // Problem description passed by value to kernels (paper Sec. 2).
+// Fourier forcing modes for the per-point forcing kernel, grouped by
+// (k_y, k_z), one record per mode, padded to a multiple of 8 with zero
+// records.  Offsets address the per-thread phase table exp(i pi k x_a),
+// k = 0..8, in LDS (entry a*9+k, rows of 256 threads x 8 bytes); negative
+// wave numbers use the conjugate (bit 0 of oy/oz, sign folded into crs/cis).
+struct FMode {
+  int ox;                  // byte offset of the |k_x| phase row
+  float cr, ci, crs, cis;  // c = a - i b, and c * sign(k_x)
+  int oy, oz;              // the group's |k_y|, |k_z| rows; bit 0: negative
+  int end;                 // 1 on the last mode of a (k_y, k_z) group
+};
+
 struct Problem {
   int dim, iface, kind, lo;   // lo: side with the smaller mu (0 minus, 1 plus), -1 if equal
   double R, amp, pn[3], pc;
@@ -22,6 +34,8 @@ struct Problem {
   int n_modes;
   const float* modes32;   // [n_modes][8]: k0 k1 k2 a b - - -
   const double* modes64;  // [n_modes][5]: k0 k1 k2 a b
+  int n_fmodes;           // padded count
+  const FMode* fmodes;    // in group order
 };
 
 // Batch bookkeeping written on the device by the scan kernel.

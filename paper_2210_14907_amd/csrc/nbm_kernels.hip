@@ -277,41 +277,56 @@ __global__ __launch_bounds__(256) void k_scatter(Problem P, const Meta* meta, co
 }
 
 // ===========================================================================
-// Fourier forcing of every interior point (one thread per point): per-axis
-// phase factors exp(i pi k x_a), k = 0..8, in LDS, then the mode sum.
+// Fourier forcing of every interior point (one thread per point).  Each
+// thread keeps its phase factors exp(i pi k x_a), k = 0..8, in LDS (rows
+// [a*9+k][thread], conflict-free); the modes come grouped by (k_y, k_z):
+//   f = Re sum_groups e^{i pi (k_y y + k_z z)} sum_{k_x in group} c e^{i pi k_x x},
+// one complex multiply-add per mode and one complex product per group; the
+// mode records are read eight at a time.
 // ===========================================================================
 template <int D>
 __global__ __launch_bounds__(256) void k_forcing(Problem P, const float* pts, int64_t n,
                                                  float* fout, const Meta* meta, const int* cls,
                                                  const int* rank, float* fslot) {
-  __shared__ float ph[256][D][9][2];
+  __shared__ float2 ph[27][256];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int t = threadIdx.x;
   float x[3] = {0.f, 0.f, 0.f};
   if (i < n)
     for (int a = 0; a < D; ++a) x[a] = pts[i * D + a];
-  for (int a = 0; a < D; ++a)
+  for (int a = 0; a < 3; ++a)
     for (int k = 0; k <= 8; ++k) {
       float sv, cv;
-      sincospif((float)k * x[a], &sv, &cv);
-      ph[t][a][k][0] = cv;
-      ph[t][a][k][1] = sv;
+      sincospif((float)k * x[a], &sv, &cv);   // axes beyond D: x = 0, phase 1
+      ph[a * 9 + k][t] = make_float2(cv, sv);
     }
-  float acc = 0.0f;
-  for (int m = 0; m < P.n_modes; ++m) {
-    const float* md = P.modes32 + 8 * m;
-    float re = 1.0f, im = 0.0f;
+  // each thread reads only its own column: no barrier
+  const char* col = reinterpret_cast<const char*>(&ph[0][t]);
+  float acc = 0.0f, sre = 0.0f, sim = 0.0f;
+  for (int m0 = 0; m0 < P.n_fmodes; m0 += 8) {
+    // records, then their phase reads, then the arithmetic: the loads of a
+    // batch are in flight together
+    FMode M[8];
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const int k = (int)md[a];
-      const int kk = k < 0 ? -k : k;
-      const float fr = ph[t][a][kk][0];
-      const float fi = (k < 0 ? -1.0f : 1.0f) * ph[t][a][kk][1];
-      const float nr = re * fr - im * fi;
-      im = re * fi + im * fr;
-      re = nr;
+    for (int u = 0; u < 8; ++u) M[u] = P.fmodes[m0 + u];
+    float2 e[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) e[u] = *reinterpret_cast<const float2*>(col + M[u].ox);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sre += M[u].cr * e[u].x - M[u].cis * e[u].y;
+      sim += M[u].ci * e[u].x + M[u].crs * e[u].y;
+      if (M[u].end) {
+        // close the (k_y, k_z) group: times e^{i pi (k_y y + k_z z)}
+        const float2 ey = *reinterpret_cast<const float2*>(col + (M[u].oy & ~1));
+        const float2 ez = *reinterpret_cast<const float2*>(col + (M[u].oz & ~1));
+        const float yi = (M[u].oy & 1) ? -ey.y : ey.y, zi = (M[u].oz & 1) ? -ez.y : ez.y;
+        const float er = ey.x * ez.x - yi * zi, ei = yi * ez.x + ey.x * zi;
+        acc += sre * er - sim * ei;
+        sre = 0.0f;
+        sim = 0.0f;
+      }
     }
-    acc += md[3] * re + md[4] * im;
   }
   if (i < n) {
     fout[i] = acc;
