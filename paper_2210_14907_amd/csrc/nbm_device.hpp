@@ -11,6 +11,7 @@ namespace nbm {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 // v_mfma_f32_16x16x4f32: lane l supplies A[l%16][k], B[k][l%16] with k = l/16;
 // result lane l holds C[4*(l/16)+r][l%16], r = 0..3.

@@ -327,6 +327,9 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
 // form two halves that take alternate tiles (twice the loads in flight);
 // within a half, wave w owns out-blocks {w, w+4, ...} and all in-blocks.  The
 // halves' accumulators are added in a fixed order through LDS at the end.
+// BF16: each half stages the A block of its tile in LDS once (double-
+// buffered, the next tile's block in flight during the current MFMAs)
+// instead of every wave reading all of it from L2.
 template <int D, int W, int PREC>
 __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A_, const void* dZ_,
                                                  float* partial, int64_t Ptot, int64_t woff,
@@ -335,21 +338,30 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
   constexpr int S = 2 * D + 1;
   constexpr int NOB = W / 16;
   constexpr int OBW = NOB / 4;
+  constexpr int TA = S * W * kTile;          // elements of one tile's A block
+  constexpr int NQ = TA * 2 / 16 / 256;      // 16-byte pieces per lane of a half (BF16)
+  static_assert(PREC == 0 || TA * 2 % (16 * 256) == 0, "A block splits into 16-byte pieces");
   const T* A = (const T*)A_;
   const T* dZ = (const T*)dZ_;
-  const int tid = threadIdx.x, lane = tid & 63, w = (tid >> 6) & 3, half = tid >> 8;
+  const int tid = threadIdx.x, lane = tid & 63, w = (tid >> 6) & 3, half = tid >> 8, hl = tid & 255;
   const int r16 = lane & 15, g = lane >> 4;
   const int G = gridDim.x;
-  __shared__ f4 xch[OBW][NOB][256];   // the second half's accumulators
+  // staging [half][buffer][TA] (BF16); after the tile loop the same bytes
+  // hold the second half's accumulators
+  constexpr int kStageBytes = PREC == 1 ? 2 * 2 * TA * 2 : 0;
+  constexpr int kXchBytes = OBW * NOB * 256 * 16;
+  __shared__ __attribute__((aligned(16))) char lds[kStageBytes > kXchBytes ? kStageBytes : kXchBytes];
+  T* stage = reinterpret_cast<T*>(lds);
+  f4 (*xch)[NOB][256] = reinterpret_cast<f4 (*)[NOB][256]>(lds);
   for (int net = 0; net < 2; ++net) {
     const int t_lo = net == 0 ? 0 : meta->tiles[0];
     const int t_hi = net == 0 ? meta->tiles[0] : meta->tiles[0] + meta->tiles[1];
     f4 acc[OBW][NOB];
     for (int i = 0; i < OBW; ++i)
       for (int k = 0; k < NOB; ++k) acc[i][k] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int t = t_lo + blockIdx.x + half * G; t < t_hi; t += 2 * G) {
-      auto tofs = [&](int s, int nn) -> int64_t { return (((int64_t)t * S + s) * W + nn) * kTile + 4 * g; };
-      if constexpr (PREC == 0) {
+    if constexpr (PREC == 0) {
+      for (int t = t_lo + blockIdx.x + half * G; t < t_hi; t += 2 * G) {
+        auto tofs = [&](int s, int nn) -> int64_t { return (((int64_t)t * S + s) * W + nn) * kTile + 4 * g; };
         float dzv[OBW][S][4];
         for (int i = 0; i < OBW; ++i)
           for (int s = 0; s < S; ++s) {
@@ -366,35 +378,75 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
               acc[i][ib] = mfma4(dzv[i][s][3], a.w, acc[i][ib]);
             }
           }
-      } else {
-        bf8 dzv[OBW][(S + 1) / 2];
-        const bf4 zero4 = bf4{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
-        for (int i = 0; i < OBW; ++i)
-          for (int s = 0; s < S; s += 2) {
-            bf4 v0 = *(const bf4*)(dZ + tofs(s, (w + 4 * i) * 16 + r16));
-            bf4 v1 = s + 1 < S ? *(const bf4*)(dZ + tofs(s + 1, (w + 4 * i) * 16 + r16)) : zero4;
-            for (int j = 0; j < 4; ++j) { dzv[i][s / 2][j] = v0[j]; dzv[i][s / 2][4 + j] = v1[j]; }
-          }
-        for (int ib = 0; ib < NOB; ++ib)
-          for (int s = 0; s < S; s += 2) {
-            bf4 v0 = *(const bf4*)(A + tofs(s, ib * 16 + r16));
-            bf4 v1 = s + 1 < S ? *(const bf4*)(A + tofs(s + 1, ib * 16 + r16)) : zero4;
-            bf8 a;
-            for (int j = 0; j < 4; ++j) { a[j] = v0[j]; a[4 + j] = v1[j]; }
-            for (int i = 0; i < OBW; ++i) acc[i][ib] = mfma32(dzv[i][s / 2], a, acc[i][ib]);
-          }
+      }
+    } else {
+      // iterations: half 0 has at least as many tiles as half 1; both halves
+      // run the same count so that their barriers pair up
+      const int span = t_hi - t_lo - (int)blockIdx.x;
+      const int niter = span > 0 ? (span + 2 * G - 1) / (2 * G) : 0;
+      auto tile_of = [&](int k) { return t_lo + (int)blockIdx.x + half * G + 2 * G * k; };
+      // the next tile's A block travels through registers; a half past its
+      // last tile re-reads the net's last tile (in bounds, never used)
+      u4 pre[NQ];
+      auto src_of = [&](int k) {
+        const int t = tile_of(k) < t_hi ? tile_of(k) : t_hi - 1;
+        return (const u4*)(A + (int64_t)t * TA);
+      };
+      if (niter > 0) {
+        const u4* s4 = src_of(0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) pre[q] = s4[q * 256 + hl];
+        u4* d4 = (u4*)(stage + (half * 2) * TA);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) d4[q * 256 + hl] = pre[q];
+      }
+      __syncthreads();
+      const bf4 zero4 = bf4{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+      for (int k = 0; k < niter; ++k) {
+        const int t = tile_of(k);
+        {
+          const u4* s4 = src_of(k + 1);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) pre[q] = s4[q * 256 + hl];
+        }
+        if (t < t_hi) {
+          auto tofs = [&](int s, int nn) -> int64_t { return (((int64_t)t * S + s) * W + nn) * kTile + 4 * g; };
+          bf8 dzv[OBW][(S + 1) / 2];
+          for (int i = 0; i < OBW; ++i)
+            for (int s = 0; s < S; s += 2) {
+              bf4 v0 = *(const bf4*)(dZ + tofs(s, (w + 4 * i) * 16 + r16));
+              bf4 v1 = s + 1 < S ? *(const bf4*)(dZ + tofs(s + 1, (w + 4 * i) * 16 + r16)) : zero4;
+              for (int j = 0; j < 4; ++j) { dzv[i][s / 2][j] = v0[j]; dzv[i][s / 2][4 + j] = v1[j]; }
+            }
+          const T* As = stage + (half * 2 + (k & 1)) * TA;
+          for (int ib = 0; ib < NOB; ++ib)
+            for (int s = 0; s < S; s += 2) {
+              bf4 v0 = *(const bf4*)(As + (s * W + ib * 16 + r16) * kTile + 4 * g);
+              bf4 v1 = s + 1 < S ? *(const bf4*)(As + ((s + 1) * W + ib * 16 + r16) * kTile + 4 * g) : zero4;
+              bf8 a;
+              for (int j = 0; j < 4; ++j) { a[j] = v0[j]; a[4 + j] = v1[j]; }
+              for (int i = 0; i < OBW; ++i) acc[i][ib] = mfma32(dzv[i][s / 2], a, acc[i][ib]);
+            }
+        }
+        // the other buffer was last read in iteration k-1, before its barrier
+        {
+          u4* d4 = (u4*)(stage + (half * 2 + ((k + 1) & 1)) * TA);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) d4[q * 256 + hl] = pre[q];
+        }
+        __syncthreads();
       }
     }
     // first half + second half, in that order
     if (half == 1)
       for (int i = 0; i < OBW; ++i)
-        for (int ib = 0; ib < NOB; ++ib) xch[i][ib][tid - 256] = acc[i][ib];
+        for (int ib = 0; ib < NOB; ++ib) xch[i][ib][hl] = acc[i][ib];
     __syncthreads();
     if (half == 0) {
       float* prow = partial + (int64_t)blockIdx.x * Ptot + (net == 0 ? 0 : net_off1) + woff;
       for (int i = 0; i < OBW; ++i)
         for (int ib = 0; ib < NOB; ++ib) {
-          const f4 o = xch[i][ib][tid];
+          const f4 o = xch[i][ib][hl];
           for (int r = 0; r < 4; ++r) {
             int row = (w + 4 * i) * 16 + 4 * g + r, col = ib * 16 + r16;
             prow[(int64_t)row * W + col] = acc[i][ib][r] + o[r];
