@@ -513,20 +513,23 @@ __global__ __launch_bounds__(256) void k_res_uncut(Problem P, const Meta* meta, 
 }
 
 // cut cells: full cut-cell residual in FP64 from the two networks' streams.
-// One wavefront per cut cell: corners, node jump extensions, face pieces and
-// Kuhn simplices are evaluated by separate lanes, lane 0 assembles.
+// One work-group of four wavefronts per cut cell, each wavefront on an
+// independent piece so that the pieces run concurrently: corners / node jump
+// extensions / forcing / network outputs, then face pieces / Kuhn simplices,
+// then the interface term next to the flux assembly.
 template <int D>
-__global__ __launch_bounds__(64) void k_res_cut(Problem P, const Meta* meta, const float* pts,
-                                                const int* cutidx, const float* outputs,
-                                                float* adj, float* resid, double* lossp,
-                                                double scale, const float* fpre) {
+__global__ __launch_bounds__(256) void k_res_cut(Problem P, const Meta* meta, const float* pts,
+                                                 const int* cutidx, const float* outputs,
+                                                 float* adj, float* resid, double* lossp,
+                                                 double scale, const float* fpre) {
   constexpr int S = 2 * D + 1;
   constexpr int NC = 1 << D;
-  __shared__ double cf[8], Jn[7], fpart[12], tvol[6], tmeas[6], tmom[6][3];
+  constexpr int NT = D == 2 ? 2 : 6;
+  __shared__ double cf[8], Jn[7], fpart[12], tvol[6], tmeas[6], tmom[6][3], os[2][7], fs[2], bt;
   __shared__ int sd[7];
-  const int b = blockIdx.x, lane = threadIdx.x;
+  const int b = blockIdx.x, tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
   if (b >= meta->nB) {
-    if (lane == 0) lossp[b] = 0.0;
+    if (tid == 0) lossp[b] = 0.0;
     return;
   }
   const int p = cutidx[b];
@@ -538,116 +541,131 @@ __global__ __launch_bounds__(64) void k_res_cut(Problem P, const Meta* meta, con
   auto corner = [&](int c, double* q) {
     for (int a = 0; a < 3; ++a) q[a] = a < D ? x[a] + h * ((((c >> a) & 1) ? 0.5 : -0.5)) : 0.0;
   };
-  if (lane < NC) {
-    double q[3];
-    corner(lane, q);
-    cf[lane] = phi_at<D>(P, q);
-  } else if (lane >= 8 && lane < 8 + S) {
-    const int k = lane - 8;
-    double y[3] = {x[0], x[1], x[2]};
-    if (k > 0) y[(k - 1) >> 1] += ((k - 1) & 1) ? -h : h;
-    sd[k] = is_minus<D>(P, y) ? 0 : 1;
-    double glo[3] = {0, 0, 0};
-    if (P.lo >= 0) {
-      const float* ol = k == 0 ? outputs + slot[P.lo] * 8
-                               : outputs + ((int64_t)meta->base[P.lo][KIND_NBR] + 2 * D * b + (k - 1)) * 8;
-      for (int a = 0; a < D; ++a) glo[a] = (2.0 * (double)ol[1 + a] - (double)ol[1 + D + a]) / (2.0 * h);
+  // ---- phase 1
+  if (wv == 0) {
+    if (ln < NC) {
+      double q[3];
+      corner(ln, q);
+      cf[ln] = phi_at<D>(P, q);
     }
-    Jn[k] = jump_ext<D>(P, y, glo);
-  }
-  __syncthreads();
-  if (lane >= 16 && lane < 16 + 2 * D * (D - 1)) {
-    // face F, piece k: 2-D segment (k = 0), 3-D triangle k of the split square
-    const int F = (lane - 16) / (D - 1), k = (lane - 16) % (D - 1);
-    const int a = F >> 1, sgn = F & 1;
-    int ids[4];
-    for (int m = 0; m < (1 << (D - 1)); ++m) {
-      int c = sgn == 0 ? (1 << a) : 0, t = 0;
-      for (int bb = 0; bb < D; ++bb) {
-        if (bb == a) continue;
-        if ((m >> t) & 1) c |= 1 << bb;
-        ++t;
+  } else if (wv == 1) {
+    if (ln < S) {
+      const int k = ln;
+      double y[3] = {x[0], x[1], x[2]};
+      if (k > 0) y[(k - 1) >> 1] += ((k - 1) & 1) ? -h : h;
+      sd[k] = is_minus<D>(P, y) ? 0 : 1;
+      double glo[3] = {0, 0, 0};
+      if (P.lo >= 0) {
+        const float* ol = k == 0 ? outputs + slot[P.lo] * 8
+                                 : outputs + ((int64_t)meta->base[P.lo][KIND_NBR] + 2 * D * b + (k - 1)) * 8;
+        for (int a = 0; a < D; ++a) glo[a] = (2.0 * (double)ol[1 + a] - (double)ol[1 + D + a]) / (2.0 * h);
       }
-      ids[m] = c;
+      Jn[k] = jump_ext<D>(P, y, glo);
     }
-    fpart[lane - 16] = D == 2 ? seg_neg(cf[ids[0]], cf[ids[1]])
-                              : tri_neg(cf[ids[0]], cf[ids[k == 0 ? 1 : 2]], cf[ids[3]]);
-  } else if (lane >= 32 && lane < 32 + (D == 2 ? 2 : 6)) {
-    const int t = lane - 32;
-    double meas = 0.0, mom[3] = {0.0, 0.0, 0.0};
-    if (D == 2) {
-      const int tris[2][3] = {{0, 1, 3}, {0, 2, 3}};
-      double Pt[3][3], ft[3];
-      for (int i = 0; i < 3; ++i) { corner(tris[t][i], Pt[i]); ft[i] = cf[tris[t][i]]; }
-      tvol[t] = tri_neg(ft[0], ft[1], ft[2]);
-      iface_tri(Pt, ft, meas, mom);
-    } else {
-      const int tets[6][4] = {{0, 1, 3, 7}, {0, 1, 5, 7}, {0, 2, 3, 7}, {0, 2, 6, 7}, {0, 4, 5, 7}, {0, 4, 6, 7}};
-      double Pt[4][3], ft[4];
-      for (int i = 0; i < 4; ++i) { corner(tets[t][i], Pt[i]); ft[i] = cf[tets[t][i]]; }
-      tvol[t] = tet_neg(ft);
-      iface_tet(Pt, ft, meas, mom);
-    }
-    tmeas[t] = meas;
-    for (int a = 0; a < 3; ++a) tmom[t][a] = mom[a];
+  } else if (wv == 2) {
+    // forcing on each side (f^- = f^+ for the Fourier forcing, precomputed)
+    if (ln < 2) fs[ln] = fpre ? (double)fpre[p] : f_side<double, D>(P, ln, x);
+  } else {
+    if (ln < 2 * S) os[ln / S][ln % S] = outputs[slot[ln / S] * 8 + ln % S];
+    // the low-mu neighbour centres (2d consecutive slots) enter through the
+    // lagged normal derivative only, held fixed in the backward: zero adjoints
+    if (P.lo >= 0 && ln < 2 * D * 8)
+      adj[((int64_t)meta->base[P.lo][KIND_NBR] + 2 * D * b) * 8 + ln] = 0.0f;
   }
   __syncthreads();
-  // the low-mu neighbour centres (2d consecutive slots) enter through the
-  // lagged normal derivative only, held fixed in the backward: zero adjoints
-  if (P.lo >= 0 && lane < 2 * D * 8)
-    adj[((int64_t)meta->base[P.lo][KIND_NBR] + 2 * D * b) * 8 + lane] = 0.0f;
-  if (lane != 0) return;
-  const int NT = D == 2 ? 2 : 6;
-  double vneg = 0.0, meas = 0.0, mom[3] = {0.0, 0.0, 0.0};
-  for (int t = 0; t < NT; ++t) {
-    vneg += tvol[t];
-    meas += tmeas[t];
-    for (int a = 0; a < 3; ++a) mom[a] += tmom[t][a];
-  }
-  vneg /= NT;
-  double gamma = D == 2 ? meas / h : meas / (h * h);
-  double cen[3];
-  for (int a = 0; a < 3; ++a) cen[a] = meas > 0.0 ? mom[a] / meas : 0.0;
-  double o[2][7];
-  for (int t = 0; t < 2; ++t)
-    for (int s = 0; s < S; ++s) o[t][s] = outputs[slot[t] * 8 + s];
-  // node values of the node's own network from the centre streams, and
-  // U_F - U_0 from the difference streams when both nodes share a network
-  double dU[6];
-  for (int F = 0; F < 2 * D; ++F) {
-    const int k = F + 1, a = F >> 1;
-    if (sd[k] == sd[0]) {
-      const int t = sd[0];
-      dU[F] = (F & 1) ? o[t][1 + D + a] - o[t][1 + a] : o[t][1 + a];
-    } else {
-      const int t = sd[k];
-      double Uk = (F & 1) ? o[t][0] + o[t][1 + D + a] - o[t][1 + a] : o[t][0] + o[t][1 + a];
-      dU[F] = Uk - o[sd[0]][0];
+  // ---- phase 2
+  if (wv == 0) {
+    if (ln < 2 * D * (D - 1)) {
+      // face F, piece k: 2-D segment (k = 0), 3-D triangle k of the split square
+      const int F = ln / (D - 1), k = ln % (D - 1);
+      const int a = F >> 1, sgn = F & 1;
+      int ids[4];
+      for (int m = 0; m < (1 << (D - 1)); ++m) {
+        int c = sgn == 0 ? (1 << a) : 0, t = 0;
+        for (int bb = 0; bb < D; ++bb) {
+          if (bb == a) continue;
+          if ((m >> t) & 1) c |= 1 << bb;
+          ++t;
+        }
+        ids[m] = c;
+      }
+      fpart[ln] = D == 2 ? seg_neg(cf[ids[0]], cf[ids[1]])
+                         : tri_neg(cf[ids[0]], cf[ids[k == 0 ? 1 : 2]], cf[ids[3]]);
+    }
+  } else if (wv == 1) {
+    if (ln < NT) {
+      const int t = ln;
+      double meas = 0.0, mom[3] = {0.0, 0.0, 0.0};
+      if (D == 2) {
+        const int tris[2][3] = {{0, 1, 3}, {0, 2, 3}};
+        double Pt[3][3], ft[3];
+        for (int i = 0; i < 3; ++i) { corner(tris[t][i], Pt[i]); ft[i] = cf[tris[t][i]]; }
+        tvol[t] = tri_neg(ft[0], ft[1], ft[2]);
+        iface_tri(Pt, ft, meas, mom);
+      } else {
+        const int tets[6][4] = {{0, 1, 3, 7}, {0, 1, 5, 7}, {0, 2, 3, 7}, {0, 2, 6, 7}, {0, 4, 5, 7}, {0, 4, 6, 7}};
+        double Pt[4][3], ft[4];
+        for (int i = 0; i < 4; ++i) { corner(tets[t][i], Pt[i]); ft[i] = cf[tets[t][i]]; }
+        tvol[t] = tet_neg(ft);
+        iface_tet(Pt, ft, meas, mom);
+      }
+      tmeas[t] = meas;
+      for (int a = 0; a < 3; ++a) tmom[t][a] = mom[a];
     }
   }
-  auto corr = [&](int s, int k) -> double {
-    if (s == 0) return sd[k] == 0 ? 0.0 : -Jn[k];
-    return sd[k] == 0 ? Jn[k] : 0.0;
-  };
-  const double mm = P.mu[0], mp = P.mu[1];
-  double cF[6], csum = 0.0, flux_corr = 0.0;
-  for (int F = 0; F < 2 * D; ++F) {
-    double an = D == 2 ? fpart[F] : 0.5 * (fpart[2 * F] + fpart[2 * F + 1]);
-    double ap = 1.0 - an;
-    cF[F] = mm * an + mp * ap;
-    csum += cF[F];
-    flux_corr += mm * an * (corr(0, F + 1) - corr(0, 0)) + mp * ap * (corr(1, F + 1) - corr(1, 0));
+  __syncthreads();
+  // ---- phase 3: interface term (wave 1) next to the flux assembly (wave 0)
+  if (wv == 1 && ln == 0) {
+    double meas = 0.0, mom[3] = {0.0, 0.0, 0.0};
+    for (int t = 0; t < NT; ++t) {
+      meas += tmeas[t];
+      for (int a = 0; a < 3; ++a) mom[a] += tmom[t][a];
+    }
+    const double gamma = D == 2 ? meas / h : meas / (h * h);
+    double b_t = 0.0;
+    if (gamma > 0.0) {
+      double cen[3], pc[3], dc, nc[3];
+      for (int a = 0; a < 3; ++a) cen[a] = mom[a] / meas;
+      project<D>(P, cen, pc, dc, nc);
+      b_t = gamma * beta_at<D>(P, pc, nc) / h;
+    }
+    bt = b_t;
   }
-  double mubar = csum / (2 * D);
-  // f^- = f^+ for the Fourier forcing (precomputed per point)
-  double src = fpre ? (double)fpre[p]
-                    : vneg * f_side<double, D>(P, 0, x) + (1.0 - vneg) * f_side<double, D>(P, 1, x);
-  double bterm = 0.0;
-  if (gamma > 0.0) {
-    double pc[3], dc, nc[3];
-    project<D>(P, cen, pc, dc, nc);
-    bterm = gamma * beta_at<D>(P, pc, nc) / h;
+  double vneg = 0.0, dU[6], cF[6], csum = 0.0, flux_corr = 0.0, mubar = 1.0, src = 0.0;
+  if (tid == 0) {
+    for (int t = 0; t < NT; ++t) vneg += tvol[t];
+    vneg /= NT;
+    // node values of the node's own network from the centre streams, and
+    // U_F - U_0 from the difference streams when both nodes share a network
+    for (int F = 0; F < 2 * D; ++F) {
+      const int k = F + 1, a = F >> 1;
+      if (sd[k] == sd[0]) {
+        const int t = sd[0];
+        dU[F] = (F & 1) ? os[t][1 + D + a] - os[t][1 + a] : os[t][1 + a];
+      } else {
+        const int t = sd[k];
+        double Uk = (F & 1) ? os[t][0] + os[t][1 + D + a] - os[t][1 + a] : os[t][0] + os[t][1 + a];
+        dU[F] = Uk - os[sd[0]][0];
+      }
+    }
+    auto corr = [&](int s_, int k) -> double {
+      if (s_ == 0) return sd[k] == 0 ? 0.0 : -Jn[k];
+      return sd[k] == 0 ? Jn[k] : 0.0;
+    };
+    const double mm = P.mu[0], mp = P.mu[1];
+    for (int F = 0; F < 2 * D; ++F) {
+      double an = D == 2 ? fpart[F] : 0.5 * (fpart[2 * F] + fpart[2 * F + 1]);
+      double ap = 1.0 - an;
+      cF[F] = mm * an + mp * ap;
+      csum += cF[F];
+      flux_corr += mm * an * (corr(0, F + 1) - corr(0, 0)) + mp * ap * (corr(1, F + 1) - corr(1, 0));
+    }
+    mubar = csum / (2 * D);
+    src = vneg * fs[0] + (1.0 - vneg) * fs[1];
   }
+  __syncthreads();
+  if (tid != 0) return;
+  const double bterm = bt;
   double R = -flux_corr / (h * h) - src + bterm;
   for (int F = 0; F < 2 * D; ++F) R -= cF[F] * dU[F] / (h * h);
   double r = R / mubar;
@@ -1216,11 +1234,11 @@ hipError_t launch_residuals(const ResCall& c) {
   double* lp = c.lossp;
   if (c.P.dim == 2) {
     if (c.n) hipLaunchKernelGGL(k_res_uncut<2>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale, c.skip_inline, c.fpre);
-    if (c.n && nblkc) hipLaunchKernelGGL(k_res_cut<2>, dim3(nblkc), dim3(64), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale, c.fpre);
+    if (c.n && nblkc) hipLaunchKernelGGL(k_res_cut<2>, dim3(nblkc), dim3(256), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale, c.fpre);
     if (c.nb) hipLaunchKernelGGL(k_res_bnd<2>, dim3(nblkb), dim3(256), 0, st, c.P, c.meta, c.bpts, c.nb, c.bcls, c.brank, c.outputs, c.adj, c.resid + c.n, lp + nblk + nblkc, c.scale);
   } else {
     if (c.n) hipLaunchKernelGGL(k_res_uncut<3>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale, c.skip_inline, c.fpre);
-    if (c.n && nblkc) hipLaunchKernelGGL(k_res_cut<3>, dim3(nblkc), dim3(64), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale, c.fpre);
+    if (c.n && nblkc) hipLaunchKernelGGL(k_res_cut<3>, dim3(nblkc), dim3(256), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale, c.fpre);
     if (c.nb) hipLaunchKernelGGL(k_res_bnd<3>, dim3(nblkb), dim3(256), 0, st, c.P, c.meta, c.bpts, c.nb, c.bcls, c.brank, c.outputs, c.adj, c.resid + c.n, lp + nblk + nblkc, c.scale);
   }
   if (c.loss) {
