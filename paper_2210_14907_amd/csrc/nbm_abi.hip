@@ -400,10 +400,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   // operand shadows of the hidden matrices
   Nets N = nets_for(ctx, params, ws);
   Timer* tprep = new Timer(ctx, st, 0);
-  {
-    hipError_t e = launch_shadows(st, ctx->cfg.prec, shadow_jobs(ctx, params, N));
-    if (e != hipSuccess) return fail(NBM_EHIP, std::string("shadow: ") + hipGetErrorString(e));
-  }
+
   // classification and centre lists
   PrepCall pc;
   std::memset(&pc, 0, sizeof(pc));
@@ -417,16 +414,20 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   pc.centres = at<float4>(ws, Lo.centres);
   pc.src = at<int>(ws, Lo.src);
   pc.cutidx = at<int>(ws, Lo.cutidx);
-  hipError_t e = launch_prep(pc);
-  // the fused kernels read the forcing of their uncut centres in slot order
+  pc.shadows = shadow_jobs(ctx, params, N);
+  pc.prec = ctx->cfg.prec;
+  // the fused kernels read the forcing of their uncut centres in slot order:
+  // the manufactured forcing is written by the scatter, the Fourier forcing
+  // by its own kernel
   const bool fused_step = grad != nullptr && (ctx->fused != nullptr || ctx->wide != nullptr) && !ctx->no_fused;
   float* f_inline = fused_step ? at<float>(ws, Lo.fslot) : nullptr;
+  const bool fourier = ctx->cfg.problem == NBM_PROB_FOURIER;
+  pc.fslot = fourier ? nullptr : f_inline;
+  hipError_t e = launch_prep(pc);
   const float* fpre = nullptr;
-  if (ctx->cfg.problem == NBM_PROB_FOURIER && n > 0) {
+  if (fourier && n > 0) {
     fpre = at<float>(ws, Lo.fpre);
     if (e == hipSuccess) e = launch_forcing(st, P, pts, n, (float*)fpre, pc.meta, pc.cls, pc.rank, f_inline);
-  } else if (fused_step && n > 0) {
-    if (e == hipSuccess) e = launch_fside(st, P, pts, pc.cls, pc.rank, pc.meta, n, f_inline);
   }
   delete tprep;
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("prep: ") + hipGetErrorString(e));
@@ -610,10 +611,7 @@ extern "C" int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const f
   Problem P = problem_for(ctx, ws);
   Nets N = nets_for(ctx, params, ws);
   Timer tev(ctx, st, 7);
-  {
-    hipError_t e = launch_shadows(st, ctx->cfg.prec, shadow_jobs(ctx, params, N));
-    if (e != hipSuccess) return fail(NBM_EHIP, std::string("shadow: ") + hipGetErrorString(e));
-  }
+
   PrepCall pc;
   std::memset(&pc, 0, sizeof(pc));
   pc.stream = st; pc.P = P; pc.pts = query; pc.n = m; pc.bpts = nullptr; pc.nb = 0; pc.eval = true;
@@ -627,6 +625,8 @@ extern "C" int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const f
   pc.centres = at<float4>(ws, Lo.centres);
   pc.src = at<int>(ws, Lo.src);
   pc.cutidx = at<int>(ws, Lo.cutidx);
+  pc.shadows = shadow_jobs(ctx, params, N);
+  pc.prec = ctx->cfg.prec;
   hipError_t e = launch_prep(pc);
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("prep: ") + hipGetErrorString(e));
   int64_t slots = m + 2 * kTile;

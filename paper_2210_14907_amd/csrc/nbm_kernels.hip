@@ -133,34 +133,45 @@ __global__ __launch_bounds__(256) void k_scan(const int* bc_in, int nblk_in, con
                                               int nblk_bnd, int* off_in, int* off_bnd, Meta* meta,
                                               int n, int nb, int cut_cap, int dim, int lo,
                                               int eval_mode) {
-  __shared__ int part[256];
+  // exclusive prefix sums of the per-block class counts, all classes at once:
+  // wavefront prefix sums by lane shuffles, then the four wavefronts' totals
+  __shared__ int wsum[4][4];
   __shared__ int totals[8];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int arr = 0; arr < 2; ++arr) {
     const int* bc = arr == 0 ? bc_in : bc_bnd;
     int* off = arr == 0 ? off_in : off_bnd;
-    int nblk = arr == 0 ? nblk_in : nblk_bnd;
-    for (int k = 0; k < (arr == 0 ? 3 : 2); ++k) {
-      int carry = 0;
-      for (int base = 0; base < nblk; base += 256) {
-        int idx = base + threadIdx.x;
-        int v = idx < nblk ? bc[idx * 4 + k] : 0;
-        part[threadIdx.x] = v;
-        __syncthreads();
-        for (int s = 1; s < 256; s <<= 1) {
-          int t = threadIdx.x >= s ? part[threadIdx.x - s] : 0;
-          __syncthreads();
-          part[threadIdx.x] += t;
-          __syncthreads();
+    const int nblk = arr == 0 ? nblk_in : nblk_bnd;
+    const int ncls = arr == 0 ? 3 : 2;
+    int carry[3] = {0, 0, 0};
+    for (int base = 0; base < nblk; base += 256) {
+      const int idx = base + tid;
+      int v[3], x[3];
+      for (int k = 0; k < 3; ++k) v[k] = (idx < nblk && k < ncls) ? bc[idx * 4 + k] : 0;
+      for (int k = 0; k < 3; ++k) x[k] = v[k];
+      for (int d = 1; d < 64; d <<= 1)
+        for (int k = 0; k < 3; ++k) {
+          const int y = __shfl_up(x[k], d);
+          if (lane >= d) x[k] += y;
         }
-        if (idx < nblk) off[idx * 4 + k] = carry + part[threadIdx.x] - v;
-        int blocksum = part[255];
-        __syncthreads();
-        carry += blocksum;
+      if (lane == 63)
+        for (int k = 0; k < 3; ++k) wsum[w][k] = x[k];
+      __syncthreads();
+      for (int k = 0; k < 3; ++k) {
+        int before = 0, tot = 0;
+        for (int q = 0; q < 4; ++q) {
+          if (q < w) before += wsum[q][k];
+          tot += wsum[q][k];
+        }
+        if (idx < nblk && k < ncls) off[idx * 4 + k] = carry[k] + before + x[k] - v[k];
+        carry[k] += tot;
       }
-      if (threadIdx.x == 0) totals[arr * 4 + k] = carry;
       __syncthreads();
     }
+    if (tid == 0)
+      for (int k = 0; k < ncls; ++k) totals[arr * 4 + k] = carry[k];
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     Meta m;
     for (int a = 0; a < 2; ++a)
@@ -204,23 +215,44 @@ __global__ __launch_bounds__(256) void k_scan(const int* bc_in, int nblk_in, con
 // bnd = 1: boundary points -> KIND_BND of the net of their side.
 // one launch for both point sets: blocks [0, nblk) take the interior (or
 // evaluation) points, the remaining blocks the boundary points
+// operand copies W_l and W_l^T of hidden matrix m, elements 256*part ..
+template <class T>
+__device__ inline void shadow_block(const ShadowJobs& jobs, int m, int part) {
+  const int W = jobs.W;
+  const int i = part * 256 + threadIdx.x;
+  if (i >= W * W) return;
+  const int r = i / W, c = i % W;
+  const float v = jobs.params[jobs.off[m] + i];
+  ((T*)jobs.Wl[m])[i] = from_f<T>(v);
+  ((T*)jobs.WlT[m])[c * W + r] = from_f<T>(v);
+}
+
+// one launch for both point sets and the operand copies: blocks [0, nblk)
+// take the interior (or evaluation) points, then the boundary points up to
+// nblk_cls, then `spm` blocks per hidden matrix copy the weights
 template <int D>
 __global__ __launch_bounds__(256) void k_classify(Problem P, const float* pts, int64_t n, int mode,
                                                   int64_t tile_index, int grid_n, int* cls, int* rank,
                                                   int* blockcnt, int nblk, const float* bpts, int64_t nb,
-                                                  int* bcls, int* brank, int* blockcnt_b) {
+                                                  int* bcls, int* brank, int* blockcnt_b, int nblk_cls,
+                                                  ShadowJobs jobs, int prec, int spm) {
   __shared__ int wcnt[4][4];
-  if ((int)blockIdx.x < nblk)
-    classify_block<D>(P, pts, n, mode, tile_index, grid_n, cls, rank, blockcnt, blockIdx.x, wcnt);
+  const int blk = blockIdx.x;
+  if (blk < nblk)
+    classify_block<D>(P, pts, n, mode, tile_index, grid_n, cls, rank, blockcnt, blk, wcnt);
+  else if (blk < nblk_cls)
+    classify_block<D>(P, bpts, nb, 1, 0, 0, bcls, brank, blockcnt_b, blk - nblk, wcnt);
+  else if (prec == 0)
+    shadow_block<float>(jobs, (blk - nblk_cls) / spm, (blk - nblk_cls) % spm);
   else
-    classify_block<D>(P, bpts, nb, 1, 0, 0, bcls, brank, blockcnt_b, blockIdx.x - nblk, wcnt);
+    shadow_block<__bf16>(jobs, (blk - nblk_cls) / spm, (blk - nblk_cls) % spm);
 }
 
 template <int D>
 __device__ inline void scatter_block(const Problem& P, const Meta* meta, const float* pts, int64_t n,
                                      const int* cls, int* rank, const int* off, int bnd,
                                      int64_t tile_index, int grid_n, float4* centres, int* src,
-                                     int* cutidx, int blk) {
+                                     int* cutidx, int blk, float* fslot) {
   int64_t i = (int64_t)blk * 256 + threadIdx.x;
   if (i >= n) return;
   int c = cls[i];
@@ -238,6 +270,8 @@ __device__ inline void scatter_block(const Problem& P, const Meta* meta, const f
     int slot = meta->base[c][bnd ? KIND_BND : KIND_A] + r;
     centres[slot] = xc;
     src[slot] = (int)i;
+    // manufactured forcing of an uncut point on its own side, in slot order
+    if (fslot && !bnd) fslot[slot] = f_side<float, D>(P, c, xf);
     return;
   }
   if (r >= meta->nB) return;  // over capacity: dropped, the loss reports NaN
@@ -267,13 +301,13 @@ __global__ __launch_bounds__(256) void k_scatter(Problem P, const Meta* meta, co
                                                  int64_t tile_index, int grid_n, float4* centres,
                                                  int* src, int* cutidx, int nblk, const float* bpts,
                                                  int64_t nb, const int* bcls, int* brank,
-                                                 const int* off_b) {
+                                                 const int* off_b, float* fslot) {
   if ((int)blockIdx.x < nblk)
     scatter_block<D>(P, meta, pts, n, cls, rank, off, 0, tile_index, grid_n, centres, src, cutidx,
-                     blockIdx.x);
+                     blockIdx.x, fslot);
   else
     scatter_block<D>(P, meta, bpts, nb, bcls, brank, off_b, 1, 0, 0, centres, src, cutidx,
-                     blockIdx.x - nblk);
+                     blockIdx.x - nblk, nullptr);
 }
 
 // ===========================================================================
@@ -344,19 +378,6 @@ __global__ __launch_bounds__(256) void k_forcing(Problem P, const float* pts, in
 __global__ void k_fill(float* p, int64_t n, float v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
-}
-
-// operand copies W_l and W_l^T of every hidden matrix (blockIdx.y = matrix)
-template <class T>
-__global__ void k_shadow(ShadowJobs jobs) {
-  const int W = jobs.W;
-  const int m = blockIdx.y;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= W * W) return;
-  int r = i / W, c = i % W;
-  float v = jobs.params[jobs.off[m] + i];
-  ((T*)jobs.Wl[m])[i] = from_f<T>(v);
-  ((T*)jobs.WlT[m])[c * W + r] = from_f<T>(v);
 }
 
 // grad[j] = scale * sum_g partial[g][j] in FP64: 64 columns per block, the
@@ -474,13 +495,13 @@ __device__ inline double block_sum(double v, double* sh) {
 // ===========================================================================
 // uncut cells: r = -sum_i eu_i / h^2 - f^s(x) / mu^s
 template <int D>
-__global__ __launch_bounds__(256) void k_res_uncut(Problem P, const Meta* meta, const float* pts,
+__device__ inline void res_uncut_block(Problem P, const Meta* meta, const float* pts,
                                                    int64_t n, const int* cls, const int* rank,
                                                    const float* outputs, float* adj, float* resid,
                                                    double* lossp, double scale, int skip_inline,
-                                                   const float* fpre) {
+                                                   const float* fpre, int blk) {
   __shared__ double sh[256];
-  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t i = (int64_t)blk * 256 + threadIdx.x;
   double r2 = 0.0;
   if (i < n) {
     int c = cls[i];
@@ -509,7 +530,7 @@ __global__ __launch_bounds__(256) void k_res_uncut(Problem P, const Meta* meta, 
     }
   }
   double s = block_sum(r2, sh);
-  if (threadIdx.x == 0) lossp[blockIdx.x] = s;
+  if (threadIdx.x == 0) lossp[blk] = s;
 }
 
 // cut cells: full cut-cell residual in FP64 from the two networks' streams.
@@ -518,16 +539,16 @@ __global__ __launch_bounds__(256) void k_res_uncut(Problem P, const Meta* meta, 
 // extensions / forcing / network outputs, then face pieces / Kuhn simplices,
 // then the interface term next to the flux assembly.
 template <int D>
-__global__ __launch_bounds__(256) void k_res_cut(Problem P, const Meta* meta, const float* pts,
+__device__ inline void res_cut_block(Problem P, const Meta* meta, const float* pts,
                                                  const int* cutidx, const float* outputs,
                                                  float* adj, float* resid, double* lossp,
-                                                 double scale, const float* fpre) {
+                                                 double scale, const float* fpre, int blk) {
   constexpr int S = 2 * D + 1;
   constexpr int NC = 1 << D;
   constexpr int NT = D == 2 ? 2 : 6;
   __shared__ double cf[8], Jn[7], fpart[12], tvol[6], tmeas[6], tmom[6][3], os[2][7], fs[2], bt;
   __shared__ int sd[7];
-  const int b = blockIdx.x, tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  const int b = blk, tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
   if (b >= meta->nB) {
     if (tid == 0) lossp[b] = 0.0;
     return;
@@ -694,12 +715,12 @@ __global__ __launch_bounds__(256) void k_res_cut(Problem P, const Meta* meta, co
 
 // Dirichlet rows at boundary points: r_b = (2d/h^2)(u - g)
 template <int D>
-__global__ __launch_bounds__(256) void k_res_bnd(Problem P, const Meta* meta, const float* bpts,
+__device__ inline void res_bnd_block(Problem P, const Meta* meta, const float* bpts,
                                                  int64_t nb, const int* bcls, const int* brank,
                                                  const float* outputs, float* adj, float* resid,
-                                                 double* lossp, double scale) {
+                                                 double* lossp, double scale, int blk) {
   __shared__ double sh[256];
-  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t i = (int64_t)blk * 256 + threadIdx.x;
   double r2 = 0.0;
   if (i < nb) {
     int c = bcls[i];
@@ -715,7 +736,27 @@ __global__ __launch_bounds__(256) void k_res_bnd(Problem P, const Meta* meta, co
     dst[1] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   double s = block_sum(r2, sh);
-  if (threadIdx.x == 0) lossp[blockIdx.x] = s;
+  if (threadIdx.x == 0) lossp[blk] = s;
+}
+
+// one launch for the three residual kinds: blocks [0, nblk) uncut points,
+// then one block per cut-cell slot (up to nblkc), then the boundary points
+template <int D>
+__global__ __launch_bounds__(256) void k_residuals(Problem P, const Meta* meta, const float* pts, int64_t n,
+                                                   const int* cls, const int* rank, const int* cutidx,
+                                                   const float* bpts, int64_t nb, const int* bcls,
+                                                   const int* brank, const float* outputs, float* adj,
+                                                   float* resid, double* lossp, double scale,
+                                                   int skip_inline, const float* fpre, int nblk,
+                                                   int nblkc) {
+  const int blk = blockIdx.x;
+  if (blk < nblk)
+    res_uncut_block<D>(P, meta, pts, n, cls, rank, outputs, adj, resid, lossp, scale, skip_inline, fpre, blk);
+  else if (blk < nblk + nblkc)
+    res_cut_block<D>(P, meta, pts, cutidx, outputs, adj, resid, lossp + nblk, scale, fpre, blk - nblk);
+  else
+    res_bnd_block<D>(P, meta, bpts, nb, bcls, brank, outputs, adj, resid + n, lossp + nblk + nblkc, scale,
+                     blk - nblk - nblkc);
 }
 
 // ===========================================================================
@@ -1208,17 +1249,20 @@ MlpFn find_mlp(int dim, int width, int act, int prec) {
 template <int D>
 static void prep_impl(const PrepCall& c, int64_t nblk, int64_t nblkb) {
   hipStream_t st = c.stream;
-  if (c.n + c.nb)
-    hipLaunchKernelGGL(k_classify<D>, dim3(nblk + nblkb), dim3(256), 0, st, c.P, c.pts, c.n,
+  const int spm = c.shadows.count ? (c.shadows.W * c.shadows.W + 255) / 256 : 1;
+  const int64_t nsh = (int64_t)c.shadows.count * spm;
+  if (c.n + c.nb + nsh)
+    hipLaunchKernelGGL(k_classify<D>, dim3(nblk + nblkb + nsh), dim3(256), 0, st, c.P, c.pts, c.n,
                        c.eval ? 1 : 0, c.tile_index, c.grid_n, c.cls, c.rank, c.blockcnt, (int)nblk,
-                       c.bpts, c.nb, c.bcls, c.brank, c.blockcnt_b);
+                       c.bpts, c.nb, c.bcls, c.brank, c.blockcnt_b, (int)(nblk + nblkb), c.shadows,
+                       c.prec, spm);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, st, c.blockcnt, (int)nblk, c.blockcnt_b,
                      (int)nblkb, c.off, c.off_b, c.meta, (int)c.n, (int)c.nb, c.cut_cap, D, c.P.lo,
                      c.eval ? 1 : 0);
   if (c.n + c.nb)
     hipLaunchKernelGGL(k_scatter<D>, dim3(nblk + nblkb), dim3(256), 0, st, c.P, c.meta, c.pts, c.n,
                        c.cls, c.rank, c.off, c.tile_index, c.grid_n, c.centres, c.src, c.cutidx,
-                       (int)nblk, c.bpts, c.nb, c.bcls, c.brank, c.off_b);
+                       (int)nblk, c.bpts, c.nb, c.bcls, c.brank, c.off_b, c.fslot);
 }
 
 hipError_t launch_prep(const PrepCall& c) {
@@ -1232,14 +1276,17 @@ hipError_t launch_residuals(const ResCall& c) {
   hipStream_t st = c.stream;
   int64_t nblk = (c.n + 255) / 256, nblkb = (c.nb + 255) / 256, nblkc = c.cut_cap;
   double* lp = c.lossp;
-  if (c.P.dim == 2) {
-    if (c.n) hipLaunchKernelGGL(k_res_uncut<2>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale, c.skip_inline, c.fpre);
-    if (c.n && nblkc) hipLaunchKernelGGL(k_res_cut<2>, dim3(nblkc), dim3(256), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale, c.fpre);
-    if (c.nb) hipLaunchKernelGGL(k_res_bnd<2>, dim3(nblkb), dim3(256), 0, st, c.P, c.meta, c.bpts, c.nb, c.bcls, c.brank, c.outputs, c.adj, c.resid + c.n, lp + nblk + nblkc, c.scale);
-  } else {
-    if (c.n) hipLaunchKernelGGL(k_res_uncut<3>, dim3(nblk), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank, c.outputs, c.adj, c.resid, lp, c.scale, c.skip_inline, c.fpre);
-    if (c.n && nblkc) hipLaunchKernelGGL(k_res_cut<3>, dim3(nblkc), dim3(256), 0, st, c.P, c.meta, c.pts, c.cutidx, c.outputs, c.adj, c.resid, lp + nblk, c.scale, c.fpre);
-    if (c.nb) hipLaunchKernelGGL(k_res_bnd<3>, dim3(nblkb), dim3(256), 0, st, c.P, c.meta, c.bpts, c.nb, c.bcls, c.brank, c.outputs, c.adj, c.resid + c.n, lp + nblk + nblkc, c.scale);
+  const int nblk_u = c.n ? (int)nblk : 0, nblk_c = c.n ? (int)nblkc : 0;
+  const int64_t grid = (int64_t)nblk_u + nblk_c + (c.nb ? nblkb : 0);
+  if (grid > 0) {
+    if (c.P.dim == 2)
+      hipLaunchKernelGGL(k_residuals<2>, dim3(grid), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank,
+                         c.cutidx, c.bpts, c.nb, c.bcls, c.brank, c.outputs, c.adj, c.resid, lp, c.scale,
+                         c.skip_inline, c.fpre, nblk_u, nblk_c);
+    else
+      hipLaunchKernelGGL(k_residuals<3>, dim3(grid), dim3(256), 0, st, c.P, c.meta, c.pts, c.n, c.cls, c.rank,
+                         c.cutidx, c.bpts, c.nb, c.bcls, c.brank, c.outputs, c.adj, c.resid, lp, c.scale,
+                         c.skip_inline, c.fpre, nblk_u, nblk_c);
   }
   if (c.loss) {
     int nparts = (int)(nblk + nblkc + nblkb) + c.extra_parts;
@@ -1251,31 +1298,6 @@ hipError_t launch_residuals(const ResCall& c) {
 hipError_t launch_reduce_loss(hipStream_t st, const double* lossp, int nparts, const Meta* meta,
                               double* loss) {
   hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(256), 0, st, lossp, nparts, meta, loss);
-  return hipGetLastError();
-}
-
-// Forcing on the side of each uncut point (class 0: Omega^-, class 1:
-// Omega^+), written in centre-slot order for the tile kernels' inline tiles.
-template <int D>
-__global__ __launch_bounds__(256) void k_fside(Problem P, const float* pts, const int* cls,
-                                               const int* rank, const Meta* meta, int64_t n,
-                                               float* fslot) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const int c = cls[i];
-  if (c >= 2) return;
-  float x[3] = {0.f, 0.f, 0.f};
-  for (int a = 0; a < D; ++a) x[a] = pts[i * D + a];
-  fslot[meta->base[c][KIND_A] + rank[i]] = f_side<float, D>(P, c, x);
-}
-
-hipError_t launch_fside(hipStream_t st, const Problem& P, const float* pts, const int* cls,
-                        const int* rank, const Meta* meta, int64_t n, float* fslot) {
-  if (n == 0) return hipSuccess;
-  if (P.dim == 2)
-    hipLaunchKernelGGL(k_fside<2>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, cls, rank, meta, n, fslot);
-  else
-    hipLaunchKernelGGL(k_fside<3>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, cls, rank, meta, n, fslot);
   return hipGetLastError();
 }
 
@@ -1292,16 +1314,6 @@ hipError_t launch_forcing(hipStream_t st, const Problem& P, const float* pts, in
 hipError_t launch_fill(hipStream_t st, float* p, int64_t n, float v) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_shadows(hipStream_t st, int prec, const ShadowJobs& jobs) {
-  if (jobs.count == 0) return hipSuccess;
-  const int n = jobs.W * jobs.W;
-  if (prec == 0)
-    hipLaunchKernelGGL(k_shadow<float>, dim3((n + 255) / 256, jobs.count), dim3(256), 0, st, jobs);
-  else
-    hipLaunchKernelGGL(k_shadow<__bf16>, dim3((n + 255) / 256, jobs.count), dim3(256), 0, st, jobs);
   return hipGetLastError();
 }
 

@@ -82,6 +82,17 @@ struct WideCall {
 typedef hipError_t (*WideFn)(const WideCall&);
 WideFn find_wide(int dim, int width, int depth, int act, int prec);
 
+// operand copies (W_l and W_l^T in the operand dtype) of up to 16 hidden
+// matrices (two nets of depth <= 8), made by extra blocks of the classify launch
+struct ShadowJobs {
+  const float* params;
+  int64_t off[16];
+  void* Wl[16];
+  void* WlT[16];
+  int count;
+  int W;
+};
+
 struct PrepCall {
   hipStream_t stream;
   Problem P;
@@ -99,6 +110,9 @@ struct PrepCall {
   float4* centres;
   int* src;
   int* cutidx;
+  ShadowJobs shadows;   // operand copies made in the same launch (count 0: none)
+  int prec;
+  float* fslot;         // manufactured forcing of uncut points in slot order, or NULL
 };
 hipError_t launch_prep(const PrepCall& c);
 
@@ -131,20 +145,7 @@ hipError_t launch_fill(hipStream_t st, float* p, int64_t n, float v);
 // values in centre-slot order for uncut points
 hipError_t launch_forcing(hipStream_t st, const Problem& P, const float* pts, int64_t n, float* f,
                           const Meta* meta, const int* cls, const int* rank, float* fslot);
-// manufactured forcing of uncut points on their own side, in centre-slot order
-hipError_t launch_fside(hipStream_t st, const Problem& P, const float* pts, const int* cls,
-                        const int* rank, const Meta* meta, int64_t n, float* fslot);
-// operand copies (W_l and W_l^T in the operand dtype) of up to 16 hidden
-// matrices (two nets of depth <= 8), one launch
-struct ShadowJobs {
-  const float* params;
-  int64_t off[16];
-  void* Wl[16];
-  void* WlT[16];
-  int count;
-  int W;
-};
-hipError_t launch_shadows(hipStream_t st, int prec, const ShadowJobs& jobs);
+
 // grad = scale * (FP64 fixed-order sum of the G partial rows); with `loss`,
 // the same launch also reduces the nparts FP64 loss partials
 hipError_t launch_reduce(hipStream_t st, const float* partial, int G, int64_t P, float* grad,
