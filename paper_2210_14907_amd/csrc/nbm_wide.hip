@@ -39,7 +39,8 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
   // pre-activations [stream][neuron][centre] (each lane reads back only what
   // it wrote); FP32 operands keep them in registers
   constexpr bool kZ0inLDS = PREC == 1;
-  __shared__ __attribute__((aligned(16))) float Zs[kZ0inLDS ? S : 1][kZ0inLDS ? W : 1][kTile];
+  // [stream][centre group g][neuron][4 centres]: a wavefront's float4 accesses are contiguous
+  __shared__ __attribute__((aligned(16))) float Zs[kZ0inLDS ? S : 1][kZ0inLDS ? 4 : 1][kZ0inLDS ? W : 1][4];
   __shared__ float adjs[kTile][8];
   __shared__ float part[NW][kTile][8];
   __shared__ float xs[kTile][4];
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           }
           if (kZ0inLDS && l == 2)
             for (int s = 0; s < S; ++s)
-              *(float4*)(&Zs[s][n][4 * g]) = make_float4(Z[0][s][0], Z[0][s][1], Z[0][s][2], Z[0][s][3]);
+              *(float4*)(&Zs[s][g][n][0]) = make_float4(Z[0][s][0], Z[0][s][1], Z[0][s][2], Z[0][s][3]);
           for (int s = 0; s < S; ++s) {
             for (int j = 0; j < 4; ++j) bufR[cur ^ 1][s][4 * g + j][n] = from_f<T>(vals[s][j]);
             T* dst = Aout + (int64_t)(l - 1) * lstride + tofs(s, n);
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
         mfma_phase_end();
         if (kZ0inLDS && l == 3)
           for (int s = 0; s < S; ++s) {
-            const float4 v = *(const float4*)(&Zs[s][n][4 * g]);
+            const float4 v = *(const float4*)(&Zs[s][g][n][0]);
             Z[0][s][0] = v.x; Z[0][s][1] = v.y; Z[0][s][2] = v.z; Z[0][s][3] = v.w;
           }
         for (int j = 0; j < 4; ++j) {
