@@ -43,6 +43,8 @@ CASES = [
     ("c4", I.C4, 2048, 48, 256, 0.004),
     ("c3_fp32", I.C3.replace(prec=I.PREC_FP32), 2048, 48, 256, 0.01),
     ("c2_bf16", I.C2.replace(prec=I.PREC_BF16), 4096, 96, 512, 0.02),
+    # equal coefficients: no low-mu neighbour centres on the fused path
+    ("c2_equal_mu", I.C2.replace(mu_plus=1.0), 4096, 96, 512, 0.02),
 ]
 
 
