@@ -147,6 +147,12 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
       // ---------------- forward, hidden layers on MFMA
       // pre-activations of layers 2..L-1 for (centres 4g+j, neuron n); the
       // last layer's backward is formed in its forward epilogue instead
+      // FP32, three layers: once every wave is past the barrier that ends
+      // layer 2, row buffer 0 (A_1) is dead until the next tile, so each
+      // lane parks its layer-2 pre-activations there, in the slots
+      // [s][4g+j][n] it alone reads back and later overwrites with dZ_2;
+      // the backward's dZ_3 then uses buffer 1 (A_2 is dead after layer 3)
+      constexpr bool kZlds = PREC == 0 && L == 3;
       float Z[L > 2 ? L - 2 : 1][S][4];
       float dz[S][4];         // dZ of the layer being differentiated
       float eS[4];            // last layer, inline tiles: sum over axes of the E streams
@@ -228,6 +234,9 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
         // next phase's weights: the following layer, or the first backward layer
         wn = load_w(l < L ? np.Wl[l - 1] : np.WlT[L - 2]);
         __syncthreads();
+        if (kZlds && l == 2)
+          for (int s = 0; s < S; ++s)
+            for (int j = 0; j < 4; ++j) bufR[0][s][4 * g + j][n] = Z[0][s][j];
         cur ^= 1;
       }
 
@@ -263,7 +272,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
       // dZ_l goes to LDS; dA_{l-1} = dZ_l W_l runs on the matrix cores; then
       // per centre the VALU recomputes A_{l-1} and forms dZ_{l-1}, and the
       // dW_l^T = A_{l-1}^T dZ_l MFMAs consume A_{l-1}.
-      int bb = 0;
+      int bb = kZlds ? 1 : 0;
 #pragma unroll
       for (int l = L; l >= 2; --l) {
         for (int j = 0; j < 4; ++j) accb[l - 1] += dz[0][j];
@@ -309,9 +318,16 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
           float av[S], Dv[3], Ev[3], Db[3], Eb[3], zb, pb[3], eb[3];
           for (int a = 0; a < D; ++a) { Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j]; }
           if (l > 2) {
-            float pp[3], ee[3];
-            for (int a = 0; a < D; ++a) { pp[a] = Z[l - 3][1 + a][j]; ee[a] = Z[l - 3][1 + D + a][j]; }
-            act_fb<ACT, D>(Z[l - 3][0][j], pp, ee, acc[0][j], Db, Eb, av[0], Dv, Ev, zb, pb, eb);
+            float zz, pp[3], ee[3];
+            if constexpr (kZlds) {
+              const int c = 4 * g + j;
+              zz = bufR[0][0][c][n];
+              for (int a = 0; a < D; ++a) { pp[a] = bufR[0][1 + a][c][n]; ee[a] = bufR[0][1 + D + a][c][n]; }
+            } else {
+              zz = Z[l - 3][0][j];
+              for (int a = 0; a < D; ++a) { pp[a] = Z[l - 3][1 + a][j]; ee[a] = Z[l - 3][1 + D + a][j]; }
+            }
+            act_fb<ACT, D>(zz, pp, ee, acc[0][j], Db, Eb, av[0], Dv, Ev, zb, pb, eb);
           } else {
             act_fb_l1<ACT, D>(z1[j], l1ax[n], acc[0][j], Db, Eb, av[0], Dv, Ev, zb, pb);
           }
