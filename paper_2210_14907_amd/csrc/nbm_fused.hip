@@ -3,7 +3,8 @@
 // two work-groups share a compute unit so that the matrix-core phase of one
 // overlaps the vector (activation) phase of the other.  Nothing per layer
 // touches HBM:
-//   * pre-activations (z and the difference streams) stay in registers;
+//   * pre-activations (z and the difference streams) stay in registers
+//     (FP32: parked in a dead row buffer between forward and backward);
 //   * the GEMM operands of the current layer sit in LDS in row layout
 //     [stream][centre][neuron], double-buffered between layers;
 //   * activations of the hidden layers are not stored: the backward pass
@@ -49,9 +50,9 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
   // spreads the 16 neurons of a read over the banks
   constexpr bool kColZ = PREC == 1;
   __shared__ __attribute__((aligned(16))) T colZ[2][kColZ ? W : 1][kColZ ? kTile + 1 : 1][8];
-  __shared__ float part[NOB][kTile][8];
+  __shared__ __attribute__((aligned(16))) float part[NOB][kTile][8];
   __shared__ float adjs[kTile][8];
-  __shared__ float xs[kTile][4];
+  __shared__ float xs[2][kTile][4];   // by tile parity
   __shared__ L1Axes l1ax[W];
   __shared__ double lsum[kTile];
   __shared__ int tflag;
@@ -93,6 +94,8 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
     if (g == 0) l1ax[n] = l1_axes<ACT, D>(p1);
     __syncthreads();
     const float b1n = np.b1[n], won = np.wout[n];
+    const float inv_hh = 1.0f / hh, inv_mu = 1.0f / (float)P.mu[net];
+    const float kal = (float)(-scale / (double)hh);   // alpha_c = kal * r_c
     const int64_t a_end = (int64_t)meta->base[net][KIND_A] + meta->cnt[net][KIND_A];
     const int t_lo = net == 0 ? 0 : meta->tiles[0];
     const int t_hi = net == 0 ? meta->tiles[0] : ntiles;
@@ -115,14 +118,21 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
     };
     fetch(t_lo + blockIdx.x);
 
+    // Between tiles only xs and adjs are written before the first barrier of
+    // the next tile (the row buffers after it).  xs alternates with the tile
+    // parity X, since the last backward layer still reads it; adjs is last
+    // read before the backward's first barrier.  So one barrier per tile
+    // boundary suffices.
+    int X = 0;
     for (int t = t_lo + blockIdx.x; t < t_hi; t += G) {
       const int64_t slot0 = (int64_t)t * kTile;
       const bool inl = slot0 + kTile <= a_end;   // uniform over the work-group
-      if (tid < kTile) { xs[tid][0] = nx.x; xs[tid][1] = nx.y; xs[tid][2] = nx.z; xs[tid][3] = 0.f; }
+      // xs[c][3]: forcing of an inline tile's centre c (every wave forms the
+      // residual of the centres it holds, so no wave waits for another's)
+      if (tid < kTile) { xs[X][tid][0] = nx.x; xs[X][tid][1] = nx.y; xs[X][tid][2] = nx.z; xs[X][tid][3] = nf; }
       // output adjoints of a non-inline tile, written by the residual kernels
       if (!inl && tid < kTile * 8) adjs[tid / 8][tid % 8] = na;
-      const float fcur = nf;   // forcing and point index of this lane's centre (inline tiles)
-      const int scur = ns;
+      const int scur = ns;   // point index of this lane's centre (inline tiles)
       fetch(t + G);
       __syncthreads();
 
@@ -131,7 +141,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
       for (int j = 0; j < 4; ++j) {
         const int c = 4 * g + j;
         float z = b1n;
-        for (int a = 0; a < D; ++a) z += W1n[a] * xs[c][a];
+        for (int a = 0; a < D; ++a) z += W1n[a] * xs[X][c][a];
         z1[j] = z;
         float av, Dv[3], Ev[3];
         act_fwd_l1<ACT, D>(z, l1ax[n], av, Dv, Ev);
@@ -240,33 +250,32 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
         cur ^= 1;
       }
 
-      // ---------------- residual / adjoints of inline tiles
-      if (inl && tid < kTile) {
-        const int c = tid;
-        const int64_t slot = slot0 + c;
-        const float f = fcur;
+      // ---------------- residual / adjoints of inline tiles: the uncut
+      // residual of centre c from the second-difference sums of the four
+      // waves, and its adjoint alpha_c on every E stream.  Each lane forms
+      // it for its own centres (same order everywhere, so the same value);
+      // the first 16 lanes also store the residual and the loss term.
+      auto uncut_r = [&](int c) {
         float eu = 0.f;
-        for (int a = 0; a < D; ++a)
-          for (int v = 0; v < NOB; ++v) eu += part[v][c][1 + D + a];
-        float r = -eu / hh - f / (float)P.mu[net];
-        resid[scur] = r;
-        lsum[c] += (double)r * (double)r;
-        float rb = (float)(scale * (double)r);
-        for (int s = 0; s < 8; ++s) adjs[c][s] = 0.f;
-        for (int a = 0; a < D; ++a) adjs[c][1 + D + a] = -rb / hh;
-      }
-      if (inl) __syncthreads();
-
-      // ---------------- top layer of inline tiles: scale by alpha_c
+        for (int v = 0; v < NOB; ++v)
+          for (int a = 0; a < D; ++a) eu += part[v][c][1 + D + a];
+        return -eu * inv_hh - xs[X][c][3] * inv_mu;
+      };
       if (inl) {
+        if (tid < kTile) {
+          const float r = uncut_r(tid);
+          resid[scur] = r;
+          lsum[tid] += (double)r * (double)r;
+        }
+        // top layer of inline tiles: scale by alpha_c = d loss / d eu_c
         for (int j = 0; j < 4; ++j) {
-          const float al = adjs[4 * g + j][1 + D];
+          const float al = kal * uncut_r(4 * g + j);
           for (int s = 0; s < S; ++s) dz[s][j] *= al;
           accwo += al * eS[j];
         }
-      }
-      if (tid == 0)
+      } else if (tid == 0) {
         for (int c = 0; c < kTile; ++c) accbo += adjs[c][0];
+      }
 
       // ---------------- backward through the hidden layers.  Per layer l:
       // dZ_l goes to LDS; dA_{l-1} = dZ_l W_l runs on the matrix cores; then
@@ -352,12 +361,12 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
           } else {
             const int c = 4 * g + j;
             accb[0] += zb;
-            for (int a = 0; a < D; ++a) accW1[a] += zb * xs[c][a] + h * pb[a];
+            for (int a = 0; a < D; ++a) accW1[a] += zb * xs[X][c][a] + h * pb[a];
           }
         }
         bb ^= 1;   // the other row buffer: no barrier needed before the next write
       }
-      __syncthreads();   // xs, adjs and the row buffers are rewritten by the next tile
+      X ^= 1;
     }
 
     // ---------------- flush this net's partial gradient
