@@ -448,7 +448,9 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   if (fused) {
     // forward only over the tiles that are not 16 uncut centres
     mc.noninline = 1;
-    mc.grid = (int)(((2 + nbr) * cut_here + nb + kTile - 1) / kTile + 6);
+    // the kernel walks the tiles with the grid as stride (their number is
+    // known only on the device): two resident blocks per compute unit
+    mc.grid = (int)std::min<int64_t>(((2 + nbr) * cut_here + nb + kTile - 1) / kTile + 6, 512);
   }
   {
     Timer tf(ctx, st, 1);
@@ -488,7 +490,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   int red_nparts = 0;
   double* red_loss = nullptr;
   if (fused && ctx->wide) {
-    int nres = (int)((n + 255) / 256 + (n ? cut_here : 0) + (nb + 255) / 256);
+    int nres = (int)((n + 255) / 256 + (n ? cut_blocks(cut_here) : 0) + (nb + 255) / 256);
     WideCall wc;
     std::memset(&wc, 0, sizeof(wc));
     wc.stream = st; wc.grid = ctx->Gf; wc.meta = pc.meta; wc.centres = pc.centres; wc.src = pc.src;
@@ -504,7 +506,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
     red_lossp = rc.lossp; red_nparts = nres + ctx->Gf; red_loss = loss_out;
     Grows = ctx->Gf;
   } else if (fused) {
-    int nres = (int)((n + 255) / 256 + (n ? cut_here : 0) + (nb + 255) / 256);
+    int nres = (int)((n + 255) / 256 + (n ? cut_blocks(cut_here) : 0) + (nb + 255) / 256);
     FusedCall fc;
     std::memset(&fc, 0, sizeof(fc));
     fc.stream = st; fc.grid = ctx->Gfz; fc.meta = pc.meta; fc.centres = pc.centres; fc.src = pc.src;

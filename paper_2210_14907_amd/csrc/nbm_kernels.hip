@@ -409,12 +409,20 @@ __global__ __launch_bounds__(1024) void k_reduce(const float* partial, int G, in
   const int64_t j = (int64_t)blockIdx.x * 64 + c;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   if (j < P) {
+    // 16 rows in flight per thread before any add (the adds keep a fixed
+    // order), so a wave keeps 4 KB of loads outstanding
     int g = k;
-    for (; g + 48 < G; g += 64) {
-      s0 += (double)partial[(int64_t)g * P + j];
-      s1 += (double)partial[(int64_t)(g + 16) * P + j];
-      s2 += (double)partial[(int64_t)(g + 32) * P + j];
-      s3 += (double)partial[(int64_t)(g + 48) * P + j];
+    for (; g + 15 * 16 < G; g += 256) {
+      float v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = partial[(int64_t)(g + 16 * u) * P + j];
+#pragma unroll
+      for (int u = 0; u < 16; u += 4) {
+        s0 += (double)v[u];
+        s1 += (double)v[u + 1];
+        s2 += (double)v[u + 2];
+        s3 += (double)v[u + 3];
+      }
     }
     for (; g < G; g += 16) s0 += (double)partial[(int64_t)g * P + j];
   }
@@ -539,20 +547,15 @@ __device__ inline void res_uncut_block(Problem P, const Meta* meta, const float*
 // extensions / forcing / network outputs, then face pieces / Kuhn simplices,
 // then the interface term next to the flux assembly.
 template <int D>
-__device__ inline void res_cut_block(Problem P, const Meta* meta, const float* pts,
-                                                 const int* cutidx, const float* outputs,
-                                                 float* adj, float* resid, double* lossp,
-                                                 double scale, const float* fpre, int blk) {
+__device__ inline double res_cut_cell(Problem P, const Meta* meta, const float* pts,
+                                      const int* cutidx, const float* outputs, float* adj,
+                                      float* resid, double scale, const float* fpre, int blk) {
   constexpr int S = 2 * D + 1;
   constexpr int NC = 1 << D;
   constexpr int NT = D == 2 ? 2 : 6;
   __shared__ double cf[8], Jn[7], fpart[12], tvol[6], tmeas[6], tmom[6][3], os[2][7], fs[2], bt;
   __shared__ int sd[7];
   const int b = blk, tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
-  if (b >= meta->nB) {
-    if (tid == 0) lossp[b] = 0.0;
-    return;
-  }
   const int p = cutidx[b];
   const double h = P.h;
   double x[3] = {0, 0, 0};
@@ -685,13 +688,12 @@ __device__ inline void res_cut_block(Problem P, const Meta* meta, const float* p
     src = vneg * fs[0] + (1.0 - vneg) * fs[1];
   }
   __syncthreads();
-  if (tid != 0) return;
+  if (tid != 0) return 0.0;
   const double bterm = bt;
   double R = -flux_corr / (h * h) - src + bterm;
   for (int F = 0; F < 2 * D; ++F) R -= cF[F] * dU[F] / (h * h);
   double r = R / mubar;
   resid[p] = (float)r;
-  lossp[b] = r * r;
   // adjoints: dr/dU_F = -c_F/(h^2 mubar), dr/dU_0 = sum_F c_F/(h^2 mubar)
   double rb = scale * r;
   double Ub[7];
@@ -711,6 +713,22 @@ __device__ inline void res_cut_block(Problem P, const Meta* meta, const float* p
   }
   for (int t = 0; t < 2; ++t)
     for (int s = 0; s < 8; ++s) adj[slot[t] * 8 + s] = s < S ? (float)g[t][s] : 0.0f;
+  return r * r;
+}
+
+// Block blk of nblkc walks the cut cells blk, blk + nblkc, ... and writes
+// their squared residuals, summed in that order, as one loss partial.
+template <int D>
+__device__ inline void res_cut_block(Problem P, const Meta* meta, const float* pts,
+                                     const int* cutidx, const float* outputs, float* adj,
+                                     float* resid, double* lossp, double scale,
+                                     const float* fpre, int blk, int nblkc) {
+  double acc = 0.0;
+  for (int b = blk; b < meta->nB; b += nblkc) {
+    acc += res_cut_cell<D>(P, meta, pts, cutidx, outputs, adj, resid, scale, fpre, b);
+    __syncthreads();   // the cell's LDS scratch is rewritten by the next one
+  }
+  if (threadIdx.x == 0) lossp[blk] = acc;
 }
 
 // Dirichlet rows at boundary points: r_b = (2d/h^2)(u - g)
@@ -740,7 +758,7 @@ __device__ inline void res_bnd_block(Problem P, const Meta* meta, const float* b
 }
 
 // one launch for the three residual kinds: blocks [0, nblk) uncut points,
-// then one block per cut-cell slot (up to nblkc), then the boundary points
+// then nblkc blocks walking the cut cells, then the boundary points
 template <int D>
 __global__ __launch_bounds__(256) void k_residuals(Problem P, const Meta* meta, const float* pts, int64_t n,
                                                    const int* cls, const int* rank, const int* cutidx,
@@ -753,7 +771,8 @@ __global__ __launch_bounds__(256) void k_residuals(Problem P, const Meta* meta, 
   if (blk < nblk)
     res_uncut_block<D>(P, meta, pts, n, cls, rank, outputs, adj, resid, lossp, scale, skip_inline, fpre, blk);
   else if (blk < nblk + nblkc)
-    res_cut_block<D>(P, meta, pts, cutidx, outputs, adj, resid, lossp + nblk, scale, fpre, blk - nblk);
+    res_cut_block<D>(P, meta, pts, cutidx, outputs, adj, resid, lossp + nblk, scale, fpre, blk - nblk,
+                     nblkc);
   else
     res_bnd_block<D>(P, meta, bpts, nb, bcls, brank, outputs, adj, resid + n, lossp + nblk + nblkc, scale,
                      blk - nblk - nblkc);
@@ -781,15 +800,21 @@ __global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4*
   constexpr int KC = W / 4;  // K chunk per lane group
   __shared__ __attribute__((aligned(16))) T buf[2][S][kTile][LD];
   __shared__ float part[4][kTile][8];
-  int t = blockIdx.x;
+  // all tiles: one per block.  noninline: only the tiles that are not 16
+  // uncut centres (the fused kernel forms the residual of those itself),
+  // walked with the grid as stride: their number is known only on the
+  // device, and a grid sized for the capacity would mostly churn through
+  // empty blocks.
+  for (int it = blockIdx.x;; it += gridDim.x) {
+  int t = it;
   if (noninline) {
-    // only tiles that are not 16 uncut centres (the fused kernel forms the
-    // residual of those itself)
     int inl0 = meta->cnt[0][KIND_A] / kTile, inl1 = meta->cnt[1][KIND_A] / kTile;
     int n0 = meta->tiles[0] - inl0, n1 = meta->tiles[1] - inl1;
     if (t < n0) t = meta->tile0[0] + inl0 + t;
     else if (t < n0 + n1) t = meta->tile0[1] + inl1 + (t - n0);
     else return;
+  } else if (it != (int)blockIdx.x) {
+    return;
   }
   const int net = tile_net(meta, t);
   if (net < 0) return;
@@ -933,6 +958,8 @@ __global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4*
     float v = part[0][c][s] + part[1][c][s] + part[2][c][s] + part[3][c][s];
     if (s == 0) v += np.bout[0];
     if (slot0 + c < slot_end) outputs[(slot0 + c) * 8 + s] = v;
+  }
+  __syncthreads();   // part is rewritten by the next tile
   }
 }
 
@@ -1274,7 +1301,7 @@ hipError_t launch_prep(const PrepCall& c) {
 
 hipError_t launch_residuals(const ResCall& c) {
   hipStream_t st = c.stream;
-  int64_t nblk = (c.n + 255) / 256, nblkb = (c.nb + 255) / 256, nblkc = c.cut_cap;
+  int64_t nblk = (c.n + 255) / 256, nblkb = (c.nb + 255) / 256, nblkc = cut_blocks(c.cut_cap);
   double* lp = c.lossp;
   const int nblk_u = c.n ? (int)nblk : 0, nblk_c = c.n ? (int)nblkc : 0;
   const int64_t grid = (int64_t)nblk_u + nblk_c + (c.nb ? nblkb : 0);

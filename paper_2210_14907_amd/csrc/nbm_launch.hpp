@@ -116,6 +116,11 @@ struct PrepCall {
 };
 hipError_t launch_prep(const PrepCall& c);
 
+// Cut cells are walked by at most this many blocks of the residual launch
+// (one loss partial each); the cell count itself is known only on the device.
+constexpr int kCutBlocks = 1024;
+inline int64_t cut_blocks(int64_t cut_cap) { return cut_cap < kCutBlocks ? cut_cap : kCutBlocks; }
+
 struct ResCall {
   hipStream_t stream;
   Problem P;
