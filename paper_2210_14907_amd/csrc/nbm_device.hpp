@@ -170,16 +170,11 @@ __device__ __forceinline__ float tanh_short(float e) {
   return e * fmaf(fmaf(y, 2.0f / 15.0f, -1.0f / 3.0f), y, 1.0f);
 }
 
-// Series tiers for the difference arguments.  TIER 2 ("tiny", taken when
-// the whole wavefront has |p| <= 1/64 (tanh) or |p|/2 <= 1/64 (sin) and
-// |e| <= 1/64): tanh x = x (1 - x^2/3 + 2 x^4/15), relative truncation error
-// 17 x^6/315 < 6e-10 for |x| <= 3/64; sin x = x (1 - x^2/6) and
-// cos x = 1 - x^2/2, errors below x^4/24 < 3e-9 for |x| <= 1/64.  TIER 1:
-// the longer series above; TIER 0: library functions for large arguments.
+// Argument tiers for the difference arguments.  The tiny tier (taken when
+// the whole wavefront has |p| <= 1/64 (tanh) or |p| <= 1/32 (sin) and
+// |e| <= 1/64) is the Taylor form below; TIER 1: the longer series above;
+// TIER 0: library functions for large arguments.
 constexpr float kTinyP = 0.015625f;   // 1/64
-
-__device__ __forceinline__ float sin_tiny(float x) { return x * fmaf(x * x, -1.0f / 6.0f, 1.0f); }
-__device__ __forceinline__ float cos_tiny(float x) { return fmaf(x * x, -0.5f, 1.0f); }
 
 // Per-axis trigonometric factors of the sin streams.  Series tiers: Taylor
 // series for p/2, short series for e/2, and the half-angle m/2 = p/2 - e/2
@@ -190,14 +185,7 @@ template <int TIER>
 __device__ __forceinline__ SinAxis sin_axis(float p, float e) {
   SinAxis r;
   float hp = 0.5f * p, he = 0.5f * e;
-  if (TIER == 2) {
-    r.sp = sin_tiny(hp);
-    r.cp = cos_tiny(hp);
-    r.se = sin_tiny(he);
-    r.ce = cos_tiny(he);
-    r.sm = r.sp * r.ce - r.cp * r.se;   // sin(p/2 - e/2)
-    r.cm = r.cp * r.ce + r.sp * r.se;   // cos(p/2 - e/2)
-  } else if (TIER == 1) {
+  if (TIER == 1) {
     r.sp = sin_taylor(hp);
     r.cp = cos_taylor(hp);
     r.se = sin_short(he);
@@ -220,12 +208,7 @@ template <int TIER>
 __device__ __forceinline__ TanhAxis tanh_axis(float p, float e) {
   TanhAxis r;
   float m = p - e;
-  if (TIER == 2) {
-    r.Tp = tanh_short(p);
-    r.Tm = tanh_short(m);
-    r.Ts = tanh_short(p + m);
-    r.Te = tanh_short(e);
-  } else if (TIER == 1) {
+  if (TIER == 1) {
     r.Tp = tanh_taylor(p);
     r.Tm = tanh_taylor(m);
     r.Ts = tanh_taylor(p + m);
@@ -435,6 +418,113 @@ __device__ __forceinline__ void act_bwd_l1(float z, const L1Axes& f, float ab, c
   }
 }
 
+// Tiny tier: the streams from the Taylor series of the activation about the
+// centre's pre-activation z,
+//   a(z + x) = a(z) + sum_{k>=1} c_k x^k,   c_k = a^(k)(z) / k!,
+// truncated after k = 7.  On the tier's arguments (|x| <= |p| + |e|, at most
+// 1/32 for tanh and 3/64 for sin) the first omitted term is below 3e-14 and
+// that of the derivative series below 1e-11 (|c_k| <= 0.39 for tanh and
+// 1/k! for sin, k >= 2).  With f(x) = sum_{k>=2} c_k x^k and m = p - e:
+//   D = a(z+p) - a(z)            = c_1 p + f(p),
+//   E = a(z+p) - 2 a(z) + a(z-m) = c_1 e + f(p) + f(-m),
+// the first-order part of E taking e itself (c_1 (p - m) would cancel); the
+// higher terms are far below E's rounding level whatever cancels in them.
+// The coefficients are formed once per z and shared by the d axes.
+//   tanh (t = tanh z, q = 1 - t^2, u = t^2; from a' = 1 - a^2):
+//     c_1 = q, c_2 = -tq, c_3 = q (u - 1/3), c_4 = tq (2/3 - u),
+//     c_5 = q (u^2 - u + 2/15), c_6 = tq (-u^2 + 4u/3 - 17/45),
+//     c_7 = q (u^3 - 5u^2/3 + 11u/15 - 17/315);
+//   sin (S = sin z, C = cos z): c_k = S or C with the sign of the k-th
+//     derivative, over k!.
+struct Taylor { float a, c[8]; };   // c[1..7]
+
+template <int ACT>
+__device__ __forceinline__ Taylor taylor_at(float z) {
+  Taylor T;
+  T.c[0] = 0.f;
+  if (ACT == 1) {
+    float S, C;
+    sincos_base(z, &S, &C);
+    T.a = S;
+    T.c[1] = C;
+    T.c[2] = S * (-1.0f / 2.0f);
+    T.c[3] = C * (-1.0f / 6.0f);
+    T.c[4] = S * (1.0f / 24.0f);
+    T.c[5] = C * (1.0f / 120.0f);
+    T.c[6] = S * (-1.0f / 720.0f);
+    T.c[7] = C * (-1.0f / 5040.0f);
+  } else {
+    const TanhBase tb = tanh_base(z);
+    const float t = tb.t, q = tb.q, u = t * t, tq = t * q;
+    T.a = t;
+    T.c[1] = q;
+    T.c[2] = -tq;
+    T.c[3] = q * (u - 1.0f / 3.0f);
+    T.c[4] = tq * (2.0f / 3.0f - u);
+    T.c[5] = q * fmaf(u, u - 1.0f, 2.0f / 15.0f);
+    T.c[6] = tq * fmaf(u, 4.0f / 3.0f - u, -17.0f / 45.0f);
+    T.c[7] = q * fmaf(u, fmaf(u, u - 5.0f / 3.0f, 11.0f / 15.0f), -17.0f / 315.0f);
+  }
+  return T;
+}
+
+// f(x) = sum_{k=2..7} c_k x^k
+__device__ __forceinline__ float taylor_f(const Taylor& T, float x) {
+  float r = fmaf(x, T.c[7], T.c[6]);
+  r = fmaf(x, r, T.c[5]);
+  r = fmaf(x, r, T.c[4]);
+  r = fmaf(x, r, T.c[3]);
+  r = fmaf(x, r, T.c[2]);
+  return (x * x) * r;
+}
+// g(x) = sum_{k=3..7} k c_k x^(k-1), from d[k] = k c_k: a'(z + x) = c_1 + d_2 x + g(x)
+__device__ __forceinline__ float taylor_g(const float* d, float x) {
+  float r = fmaf(x, d[7], d[6]);
+  r = fmaf(x, r, d[5]);
+  r = fmaf(x, r, d[4]);
+  r = fmaf(x, r, d[3]);
+  return (x * x) * r;
+}
+
+template <int D>
+__device__ __forceinline__ void taylor_fwd(const Taylor& T, const float* p, const float* e, float* Dv,
+                                           float* Ev) {
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const float m = p[i] - e[i];
+    const float fp = taylor_f(T, p[i]), fm = taylor_f(T, -m);
+    Dv[i] = fmaf(T.c[1], p[i], fp);
+    Ev[i] = fmaf(T.c[1], e[i], fp + fm);
+  }
+}
+
+// the derivatives of D and E by z, p and e are values of a' = c_1 + d_2 x + g(x):
+//   dD/dz = a'(z+p) - a'(z) = d_2 p + g(p),        dD/dp = a'(z+p),
+//   dE/dz = a'(z+p) - 2a'(z) + a'(z-m) = d_2 e + g(p) + g(-m),
+//   dE/dp = a'(z+p) - a'(z-m) = d_2 (p + m) + g(p) - g(-m),   dE/de = a'(z-m)
+template <int D>
+__device__ __forceinline__ void taylor_bwd(const Taylor& T, const float* p, const float* e, float ab,
+                                           const float* Db, const float* Eb, float& zb, float* pb,
+                                           float* eb) {
+  float d[8];
+#pragma unroll
+  for (int k = 2; k <= 7; ++k) d[k] = (float)k * T.c[k];
+  zb = ab * T.c[1];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const float m = p[i] - e[i];
+    const float gp = taylor_g(d, p[i]), gm = taylor_g(d, -m);
+    const float dDdz = fmaf(d[2], p[i], gp);
+    const float dDdp = T.c[1] + dDdz;
+    const float dEdz = fmaf(d[2], e[i], gp + gm);
+    const float dEdp = fmaf(d[2], p[i] + m, gp - gm);
+    const float dEde = T.c[1] + fmaf(-d[2], m, gm);
+    zb = fmaf(Db[i], dDdz, fmaf(Eb[i], dEdz, zb));
+    pb[i] = fmaf(Db[i], dDdp, Eb[i] * dEdp);
+    eb[i] = Eb[i] * dEde;
+  }
+}
+
 // Longer series and library paths kept out of line (each lane picks its
 // tier there): taken only when some lane of the wavefront has a difference
 // argument beyond the tiny tier, so the common path stays register-lean.
@@ -470,7 +560,9 @@ template <int ACT, int D>
 __device__ __forceinline__ void act_fwd(float z, const float* p, const float* e, float& a,
                                         float* Dv, float* Ev) {
   if (__all(tiny_args<ACT, D>(p, e))) {
-    act_fwd_impl<ACT, D, 2>(z, p, e, a, Dv, Ev);
+    const Taylor T = taylor_at<ACT>(z);
+    a = T.a;
+    taylor_fwd<D>(T, p, e, Dv, Ev);
   } else {
     const ActFwdOut r = act_fwd_general<ACT, D>(z, p[0], D > 1 ? p[1] : 0.f, D > 2 ? p[2] : 0.f, e[0],
                                                 D > 1 ? e[1] : 0.f, D > 2 ? e[2] : 0.f);
@@ -485,7 +577,7 @@ __device__ __forceinline__ void act_bwd(float z, const float* p, const float* e,
                                         const float* Db, const float* Eb, float& zb, float* pb,
                                         float* eb) {
   if (__all(tiny_args<ACT, D>(p, e))) {
-    act_bwd_impl<ACT, D, 2>(z, p, e, ab, Db, Eb, zb, pb, eb);
+    taylor_bwd<D>(taylor_at<ACT>(z), p, e, ab, Db, Eb, zb, pb, eb);
   } else {
     const ActBwdOut r = act_bwd_general<ACT, D>(
         z, p[0], D > 1 ? p[1] : 0.f, D > 2 ? p[2] : 0.f, e[0], D > 1 ? e[1] : 0.f, D > 2 ? e[2] : 0.f,
@@ -525,8 +617,10 @@ __device__ __forceinline__ void act_fb(float z, const float* p, const float* e, 
                                        const float* Db, const float* Eb, float& a, float* Dv,
                                        float* Ev, float& zb, float* pb, float* eb) {
   if (__all(tiny_args<ACT, D>(p, e))) {
-    act_fwd_impl<ACT, D, 2>(z, p, e, a, Dv, Ev);
-    act_bwd_impl<ACT, D, 2>(z, p, e, ab, Db, Eb, zb, pb, eb);
+    const Taylor T = taylor_at<ACT>(z);
+    a = T.a;
+    taylor_fwd<D>(T, p, e, Dv, Ev);
+    taylor_bwd<D>(T, p, e, ab, Db, Eb, zb, pb, eb);
   } else {
     const ActFBOut r = act_fb_general<ACT, D>(
         z, p[0], D > 1 ? p[1] : 0.f, D > 2 ? p[2] : 0.f, e[0], D > 1 ? e[1] : 0.f, D > 2 ? e[2] : 0.f,
