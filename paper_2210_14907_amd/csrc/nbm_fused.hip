@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
   // spreads the 16 neurons of a read over the banks
   constexpr bool kColZ = PREC == 1;
   __shared__ __attribute__((aligned(16))) T colZ[2][kColZ ? W : 1][kColZ ? kTile + 1 : 1][8];
-  __shared__ __attribute__((aligned(16))) float part[NOB][kTile][8];
+  __shared__ float part[NOB][kTile][1];   // per wave: w_out . sum_i E_i of each centre
   __shared__ float adjs[kTile][8];
   __shared__ float xs[2][kTile][4];   // by tile parity
   __shared__ L1Axes l1ax[W];
@@ -223,21 +223,21 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
             act_fb<ACT, D>(z, pp, ee, ab, Db, Eb, av, Dv, Ev, zb, pb, eb);
             dz[0][j] = zb;
             for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
-            // output layer: u = sum_n w_out[n] a_L[n] (+ b_out), per stream
-            float vals[7];
-            vals[0] = av;
-            for (int a = 0; a < D; ++a) { vals[1 + a] = Dv[a]; vals[1 + D + a] = Ev[a]; }
-            for (int s = 0; s < S; ++s) {
-              const float v = row16_sum(won * vals[s]);
-              if (r16 == 0) part[w][c][s] = v;
-            }
+            // output layer, u = sum_n w_out[n] a_L[n] (+ b_out) per stream: the
+            // inline residual needs only sum_i eu_i, so this wave's share is one
+            // reduction over its 16 neurons of w_out * sum_i E_i (non-inline
+            // tiles take their outputs from the forward-only pass).
             // d loss / d w_out[n] = sum_c sum_s adj[c][s] a_L[s][n][c]
             if (inl) {
               float es = 0.f;
               for (int a = 0; a < D; ++a) es += Ev[a];
               eS[j] = es;
+              const float v = row16_sum(won * es);
+              if (r16 == 0) part[w][c][0] = v;
             } else {
-              for (int s = 0; s < S; ++s) accwo += adjs[c][s] * vals[s];
+              accwo += adjs[c][0] * av;
+              for (int a = 0; a < D; ++a) accwo += adjs[c][1 + a] * Dv[a];
+              for (int a = 0; a < D; ++a) accwo += adjs[c][1 + D + a] * Ev[a];
             }
           }
         }
@@ -257,8 +257,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
       // the first 16 lanes also store the residual and the loss term.
       auto uncut_r = [&](int c) {
         float eu = 0.f;
-        for (int v = 0; v < NOB; ++v)
-          for (int a = 0; a < D; ++a) eu += part[v][c][1 + D + a];
+        for (int v = 0; v < NOB; ++v) eu += part[v][c][0];
         return -eu * inv_hh - xs[X][c][3] * inv_mu;
       };
       if (inl) {
