@@ -42,7 +42,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
   // [stream][centre group g][neuron][4 centres]: a wavefront's float4 accesses are contiguous
   __shared__ __attribute__((aligned(16))) float Zs[kZ0inLDS ? S : 1][kZ0inLDS ? 4 : 1][kZ0inLDS ? W : 1][4];
   __shared__ float adjs[kTile][8];
-  __shared__ float part[NW][kTile][8];
+  __shared__ float part[NW][kTile][1];   // per wave: w_out . sum_i E_i of each centre
   __shared__ float xs[kTile][4];
   __shared__ L1Axes l1ax[W];
   __shared__ double lsum[kTile];
@@ -65,6 +65,8 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
     if (g == 0) l1ax[n] = l1_axes<ACT, D>(p1);
     __syncthreads();
     const float b1n = np.b1[n], won = np.wout[n];
+    const float inv_hh = 1.0f / hh, inv_mu = 1.0f / (float)P.mu[net];
+    const float kal = (float)(-scale / (double)hh);   // alpha_c = kal * r_c
     const int64_t a_end = (int64_t)meta->base[net][KIND_A] + meta->cnt[net][KIND_A];
     const int t_lo = net == 0 ? 0 : meta->tiles[0];
     const int t_hi = net == 0 ? meta->tiles[0] : ntiles;
@@ -76,7 +78,10 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
       if (tid < kTile) {
         float4 cc = centres[slot0 + tid];
         if (slot0 + tid >= slot_end) cc = make_float4(0.f, 0.f, 0.f, 0.f);
-        xs[tid][0] = cc.x; xs[tid][1] = cc.y; xs[tid][2] = cc.z; xs[tid][3] = 0.f;
+        // xs[c][3]: forcing of an inline tile's centre (every lane forms the
+        // residual of the centres it holds)
+        xs[tid][0] = cc.x; xs[tid][1] = cc.y; xs[tid][2] = cc.z;
+        xs[tid][3] = inl ? fslot[slot0 + tid] : 0.f;
       }
       if (!inl && tid < kTile * 8) {
         // output adjoints of a non-inline tile, written by the residual kernels
@@ -186,21 +191,21 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
             act_fb<ACT, D>(z, pp, ee, ab, Db, Eb, av, Dv, Ev, zb, pb, eb);
             dz[0][j] = zb;
             for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
-            // output layer, per stream: u = sum_n w_out[n] a_L[n] (+ b_out)
-            float vals[7];
-            vals[0] = av;
-            for (int a = 0; a < D; ++a) { vals[1 + a] = Dv[a]; vals[1 + D + a] = Ev[a]; }
-            for (int s = 0; s < S; ++s) {
-              const float v = row16_sum(won * vals[s]);
-              if (r16 == 0) part[w][c][s] = v;
-            }
+            // output layer, u = sum_n w_out[n] a_L[n] (+ b_out) per stream: the
+            // inline residual needs only sum_i eu_i, so this wave's share is one
+            // reduction over its 16 neurons of w_out * sum_i E_i (non-inline
+            // tiles take their outputs from the forward-only pass).
             // d loss / d w_out[n] = sum_c sum_s adj[c][s] a_L[s][n][c]
             if (inl) {
               float es = 0.f;
               for (int a = 0; a < D; ++a) es += Ev[a];
               eS[j] = es;
+              const float v = row16_sum(won * es);
+              if (r16 == 0) part[w][c][0] = v;
             } else {
-              for (int s = 0; s < S; ++s) accwo += adjs[c][s] * vals[s];
+              accwo += adjs[c][0] * av;
+              for (int a = 0; a < D; ++a) accwo += adjs[c][1 + a] * Dv[a];
+              for (int a = 0; a < D; ++a) accwo += adjs[c][1 + D + a] * Ev[a];
             }
           }
         }
@@ -208,30 +213,30 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
         cur ^= 1;
       }
 
-      // ---- residual / adjoints of inline tiles
+      // ---- residual / adjoints of inline tiles: the uncut residual of centre
+      // c from the waves' second-difference sums and its adjoint alpha_c on
+      // every E stream, formed by each lane for its own centres (same order
+      // everywhere, so the same value); the first 16 lanes also store the
+      // residual and the loss term
+      auto uncut_r = [&](int c) {
+        float eu = 0.f;
+        for (int v = 0; v < NW; ++v) eu += part[v][c][0];
+        return -eu * inv_hh - xs[c][3] * inv_mu;
+      };
       if (inl) {
         if (tid < kTile) {
-          const int c = tid;
-          const int64_t slot = slot0 + c;
-          float eu = 0.f;
-          for (int a = 0; a < D; ++a)
-            for (int v = 0; v < NW; ++v) eu += part[v][c][1 + D + a];
-          float r = -eu / hh - fslot[slot] / (float)P.mu[net];
-          resid[src[slot]] = r;
-          lsum[c] += (double)r * (double)r;
-          float rb = (float)(scale * (double)r);
-          for (int s = 0; s < 8; ++s) adjs[c][s] = 0.f;
-          for (int a = 0; a < D; ++a) adjs[c][1 + D + a] = -rb / hh;
+          const float r = uncut_r(tid);
+          resid[src[slot0 + tid]] = r;
+          lsum[tid] += (double)r * (double)r;
         }
-        __syncthreads();
         for (int j = 0; j < 4; ++j) {
-          const float al = adjs[4 * g + j][1 + D];
+          const float al = kal * uncut_r(4 * g + j);
           for (int s = 0; s < S; ++s) dz[s][j] *= al;
           accwo += al * eS[j];
         }
-      }
-      if (tid == 0)
+      } else if (tid == 0) {
         for (int c = 0; c < kTile; ++c) accbo += adjs[c][0];
+      }
 
       // ---- backward through the hidden layers (dZ rows double-buffered)
       int bb = 0;
