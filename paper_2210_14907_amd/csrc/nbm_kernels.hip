@@ -864,22 +864,37 @@ __global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4*
   float vout[S][4];
   for (int s = 0; s < S; ++s)
     for (int j = 0; j < 4; ++j) vout[s][j] = 0.0f;
+  // this lane's B operand (row ob*16+r16 of W_l, K chunk g); the first neuron
+  // block's rows of the next layer are fetched one layer ahead
+  struct BRow { float f[PREC == 0 ? KC : 1]; bf8 b[PREC == 1 ? KC / 8 : 1]; };
+  auto load_b = [&](int l, int ob) {
+    BRow r;
+    const int nrow = ob * 16 + r16;
+    if constexpr (PREC == 0) {
+      const float4* wp = (const float4*)((const float*)np.Wl[l - 2] + (int64_t)nrow * W + g * KC);
+      for (int q = 0; q < KC / 4; ++q) {
+        float4 v4 = wp[q];
+        r.f[4 * q] = v4.x; r.f[4 * q + 1] = v4.y; r.f[4 * q + 2] = v4.z; r.f[4 * q + 3] = v4.w;
+      }
+    } else {
+      const bf8* wp = (const bf8*)((const T*)np.Wl[l - 2] + (int64_t)nrow * W + g * KC);
+      for (int q = 0; q < KC / 8; ++q) r.b[q] = wp[q];
+    }
+    return r;
+  };
+  BRow bnext = load_b(2, w);
   int cur = 0;
   for (int l = 2; l <= L; ++l) {
-    const T* Wm = (const T*)np.Wl[l - 2];
     const float* bl = np.bl[l - 2];
     const bool last = (l == L);
     for (int ob = w; ob < NOB; ob += 4) {
       const int nrow = ob * 16 + r16;
       f4 acc[S];
       for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+      const BRow bcur = ob == w ? bnext : load_b(l, ob);
+      if (ob + 4 >= NOB && l < L) bnext = load_b(l + 1, w);
       if constexpr (PREC == 0) {
-        float bk[KC];
-        const float4* wp = (const float4*)((const float*)Wm + (int64_t)nrow * W + g * KC);
-        for (int q = 0; q < KC / 4; ++q) {
-          float4 v4 = wp[q];
-          bk[4 * q] = v4.x; bk[4 * q + 1] = v4.y; bk[4 * q + 2] = v4.z; bk[4 * q + 3] = v4.w;
-        }
+        const float* bk = bcur.f;
         for (int s = 0; s < S; ++s) {
           const float4* ap = (const float4*)(&buf[cur][s][r16][g * KC]);
           for (int q = 0; q < KC / 4; ++q) {
@@ -891,9 +906,7 @@ __global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4*
           }
         }
       } else {
-        bf8 bk[KC / 8];
-        const bf8* wp = (const bf8*)((const T*)Wm + (int64_t)nrow * W + g * KC);
-        for (int q = 0; q < KC / 8; ++q) bk[q] = wp[q];
+        const bf8* bk = bcur.b;
         for (int s = 0; s < S; ++s) {
           const bf8* ap = (const bf8*)(&buf[cur][s][r16][g * KC]);
           for (int q = 0; q < KC / 8; ++q) acc[s] = mfma32(ap[q], bk[q], acc[s]);
