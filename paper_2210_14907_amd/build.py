@@ -10,7 +10,7 @@ HERE = Path(__file__).resolve().parent
 CSRC = HERE / "csrc"
 BUILD = HERE / "_build"
 LIB = HERE / "libnbm.so"
-SOURCES = ["nbm_kernels.hip", "nbm_fused.hip", "nbm_wide.hip", "nbm_abi.hip"]
+SOURCES = ["nbm_kernels.hip", "nbm_fused.hip", "nbm_wide.hip", "nbm_eval.hip", "nbm_abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

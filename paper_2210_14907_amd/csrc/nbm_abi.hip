@@ -50,6 +50,7 @@ struct nbm_ctx {
   std::vector<FMode> fmodes;
   Problem P;
   MlpFn mlp;
+  EvalFn evalfn;   // persistent evaluation kernel, or null: the per-tile forward
   FusedFn fused;
   WideFn wide;
   int D, W, L, S, opbytes;
@@ -177,6 +178,7 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
   x->cfg.mode_k = nullptr;
   x->cfg.mode_a = x->cfg.mode_b = nullptr;
   x->mlp = fn;
+  x->evalfn = find_eval(c.dim, c.width, c.depth, c.act, c.prec);
   x->fused = find_fused(c.dim, c.width, c.depth, c.act, c.prec);
   x->wide = find_wide(c.dim, c.width, c.depth, c.act, c.prec);
   x->no_fused = std::getenv("NBM_NO_FUSED") != nullptr;
@@ -631,6 +633,16 @@ extern "C" int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const f
   pc.prec = ctx->cfg.prec;
   hipError_t e = launch_prep(pc);
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("prep: ") + hipGetErrorString(e));
+  if (ctx->evalfn) {
+    EvalCall ec;
+    std::memset(&ec, 0, sizeof(ec));
+    ec.stream = st;
+    ec.max_grid = (int)std::min<int64_t>((m + 63) / 64 + 2, 1 << 20);   // tiles of 64 centres, both nets
+    ec.meta = pc.meta; ec.centres = pc.centres; ec.src = pc.src; ec.nets = &N; ec.u_out = u_out;
+    e = ctx->evalfn(ec);
+    if (e != hipSuccess) return fail(NBM_EHIP, std::string("eval: ") + hipGetErrorString(e));
+    return NBM_OK;
+  }
   int64_t slots = m + 2 * kTile;
   int grid = (int)((slots + kTile - 1) / kTile + 2);
   MlpCall mc;

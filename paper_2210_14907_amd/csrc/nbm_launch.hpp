@@ -32,6 +32,19 @@ struct MlpCall {
 typedef hipError_t (*MlpFn)(const MlpCall&);
 MlpFn find_mlp(int dim, int width, int act, int prec);
 
+// base-stream forward of the evaluation path (persistent work-groups)
+struct EvalCall {
+  hipStream_t stream;
+  int max_grid;              // upper bound on useful work-groups (tiles of 64 centres)
+  const Meta* meta;
+  const float4* centres;
+  const int* src;
+  const Nets* nets;
+  float* u_out;              // [m], indexed by query
+};
+typedef hipError_t (*EvalFn)(const EvalCall&);
+EvalFn find_eval(int dim, int width, int depth, int act, int prec);
+
 struct FusedCall {
   const float* fslot;  // forcing of uncut centres in centre-slot order
   hipStream_t stream;
