@@ -4,16 +4,18 @@
 // grid tile index).
 //
 // Persistent work-groups of W/16 wavefronts; wavefront w owns neurons
-// 16w..16w+15 of every layer and keeps its MFMA B operands of all hidden
-// layers in registers for the whole launch (one load per network instead of
-// one per tile).  Work-groups walk 64-centre tiles:
-//   * layer 1 (K = d) on the VALU, activations to LDS rows [centre][neuron];
-//   * hidden layers on MFMA, four 16-centre row blocks per wavefront, A rows
-//     from LDS (double-buffered between layers), bias + activation in the
-//     accumulator layout;
-//   * output layer: w_out . a_L as one row sum per wavefront and centre, the
-//     wavefronts' partials added in a fixed order, u written straight to the
-//     query's position.
+// 16w..16w+15 of every layer and keeps its rows of all hidden weight
+// matrices in registers for the whole launch (one load per network instead
+// of one per tile).  Each product is formed transposed, Z^T = W A^T: the
+// weights are the MFMA's A operand and the activation rows [centre][neuron]
+// in LDS its B operand, so a lane's accumulators hold four consecutive
+// neurons of one centre.  Work-groups walk 64-centre tiles:
+//   * layer 1 (K = d) on the VALU;
+//   * hidden layers on MFMA over four 16-centre blocks, activations written
+//     back as one 4-neuron vector per lane and block (double-buffered rows);
+//   * output layer: w_out . a_L over the lane's four neurons, then across
+//     the lane groups and, in a fixed order, the wavefronts; u is written
+//     straight to the query's position.
 // The next tile's centres and query indices are fetched one tile ahead.
 #include <hip/hip_runtime.h>
 
@@ -26,7 +28,7 @@ namespace nbm {
 constexpr int kEvalTile = 64;   // centres per tile: four MFMA row blocks
 
 template <int D, int W, int L, int ACT, int PREC>
-__global__ __launch_bounds__(W * 4, PREC == 1 ? 2 : 1) void k_eval_mlp(const Meta* meta, const float4* centres,
+__global__ __launch_bounds__(W * 4, PREC == 1 ? 4 : 2) void k_eval_mlp(const Meta* meta, const float4* centres,
                                                     const int* src, Nets nets, float* u_out) {
   typedef typename Op<PREC>::T T;
   constexpr int NW = W / 16;              // wavefronts = 16-neuron blocks
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(W * 4, PREC == 1 ? 2 : 1) void k_eval_mlp(const Met
   __shared__ float part[NW][kEvalTile];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r16 = lane & 15, g = lane >> 4;
-  const int n = w * 16 + r16;             // neuron owned by this lane
+  const int n = w * 16 + r16;             // weight row held by this lane
   const int G = gridDim.x;
 
   for (int net = 0; net < 2; ++net) {
@@ -52,9 +54,9 @@ __global__ __launch_bounds__(W * 4, PREC == 1 ? 2 : 1) void k_eval_mlp(const Met
     const int ntiles = (int)((meta->total[net] + kEvalTile - 1) / kEvalTile);
     if (ntiles == 0) continue;
 
-    // this lane's B operands (row n of W_l, K chunk g) of every hidden layer
-    struct BRows { float f[PREC == 0 ? L - 1 : 1][PREC == 0 ? NB : 1]; bf8 b[PREC == 1 ? L - 1 : 1][PREC == 1 ? NB : 1]; };
-    BRows B;
+    // this lane's A operands (row n of W_l, K chunk g) of every hidden layer
+    struct WRows { float f[PREC == 0 ? L - 1 : 1][PREC == 0 ? NB : 1]; bf8 b[PREC == 1 ? L - 1 : 1][PREC == 1 ? NB : 1]; };
+    WRows A;
 #pragma unroll
     for (int l = 0; l < L - 1; ++l) {
       if constexpr (PREC == 0) {
@@ -62,20 +64,26 @@ __global__ __launch_bounds__(W * 4, PREC == 1 ? 2 : 1) void k_eval_mlp(const Met
 #pragma unroll
         for (int q = 0; q < KC / 4; ++q) {
           const float4 v = wp[q];
-          B.f[l][4 * q] = v.x; B.f[l][4 * q + 1] = v.y; B.f[l][4 * q + 2] = v.z; B.f[l][4 * q + 3] = v.w;
+          A.f[l][4 * q] = v.x; A.f[l][4 * q + 1] = v.y; A.f[l][4 * q + 2] = v.z; A.f[l][4 * q + 3] = v.w;
         }
       } else {
         const bf8* wp = (const bf8*)((const T*)np.Wl[l] + (int64_t)n * W + g * KC);
 #pragma unroll
-        for (int q = 0; q < NB; ++q) B.b[l][q] = wp[q];
+        for (int q = 0; q < NB; ++q) A.b[l][q] = wp[q];
       }
     }
-    float bl[L - 1];
+    // the four output neurons of this lane's accumulators: n4 + j
+    const int n4 = w * 16 + 4 * g;
+    float bl[L - 1][4], W1n[4][3], b1n[4], won[4];
 #pragma unroll
-    for (int l = 0; l < L - 1; ++l) bl[l] = np.bl[l][n];
-    float W1n[3] = {0.f, 0.f, 0.f};
-    for (int a = 0; a < D; ++a) W1n[a] = np.W1[n * D + a];
-    const float b1n = np.b1[n], won = np.wout[n], bout = np.bout[0];
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int l = 0; l < L - 1; ++l) bl[l][j] = np.bl[l][n4 + j];
+      for (int a = 0; a < 3; ++a) W1n[j][a] = a < D ? np.W1[(n4 + j) * D + a] : 0.f;
+      b1n[j] = np.b1[n4 + j];
+      won[j] = np.wout[n4 + j];
+    }
+    const float bout = np.bout[0];
 
     // next tile's centre and query index (thread c < kEvalTile holds centre c)
     float4 nx = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -97,20 +105,29 @@ __global__ __launch_bounds__(W * 4, PREC == 1 ? 2 : 1) void k_eval_mlp(const Met
       fetch(t + G);
       __syncthreads();
 
-      // ---- layer 1 (VALU): centres 16 rb + 4 g + j of neuron n
+      // stores of a lane's four consecutive neurons n4..n4+3 of centre c
+      auto put4 = [&](int b, int c, const float* v) {
+        if constexpr (PREC == 0) *(float4*)(&buf[b][c][n4]) = make_float4(v[0], v[1], v[2], v[3]);
+        else *(bf4*)(&buf[b][c][n4]) = bf4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+      };
+
+      // ---- layer 1 (VALU): centre 16 rb + r16, neurons n4 + j
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+      for (int rb = 0; rb < RB; ++rb) {
+        const int c = 16 * rb + r16;
+        float v[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int c = 16 * rb + 4 * g + j;
-          float z = b1n;
-          for (int a = 0; a < D; ++a) z = fmaf(W1n[a], xs[c][a], z);
-          buf[0][c][n] = from_f<T>(act_base<ACT>(z));
+          float z = b1n[j];
+          for (int a = 0; a < D; ++a) z = fmaf(W1n[j][a], xs[c][a], z);
+          v[j] = act_base<ACT>(z);
         }
+        put4(0, c, v);
+      }
       __syncthreads();
 
-      // ---- hidden layers on MFMA; the last one feeds the output row sums
-      float outp[RB][4];
+      // ---- hidden layers on MFMA; the last one feeds the output sums
+      float outp[RB];
       int cur = 0;
 #pragma unroll
       for (int l = 0; l < L - 1; ++l) {
@@ -120,42 +137,49 @@ __global__ __launch_bounds__(W * 4, PREC == 1 ? 2 : 1) void k_eval_mlp(const Met
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           if constexpr (PREC == 0) {
-            const float4* ap = (const float4*)(&buf[cur][16 * rb + r16][g * KC]);
+            const float4* bp = (const float4*)(&buf[cur][16 * rb + r16][g * KC]);
 #pragma unroll
             for (int q = 0; q < KC / 4; ++q) {
-              const float4 a4 = ap[q];
-              acc[rb] = mfma4(a4.x, B.f[l][4 * q], acc[rb]);
-              acc[rb] = mfma4(a4.y, B.f[l][4 * q + 1], acc[rb]);
-              acc[rb] = mfma4(a4.z, B.f[l][4 * q + 2], acc[rb]);
-              acc[rb] = mfma4(a4.w, B.f[l][4 * q + 3], acc[rb]);
+              const float4 b4 = bp[q];
+              acc[rb] = mfma4(A.f[l][4 * q], b4.x, acc[rb]);
+              acc[rb] = mfma4(A.f[l][4 * q + 1], b4.y, acc[rb]);
+              acc[rb] = mfma4(A.f[l][4 * q + 2], b4.z, acc[rb]);
+              acc[rb] = mfma4(A.f[l][4 * q + 3], b4.w, acc[rb]);
             }
           } else {
-            const bf8* ap = (const bf8*)(&buf[cur][16 * rb + r16][g * KC]);
+            const bf8* bp = (const bf8*)(&buf[cur][16 * rb + r16][g * KC]);
 #pragma unroll
-            for (int q = 0; q < NB; ++q) acc[rb] = mfma32(ap[q], B.b[l][q], acc[rb]);
+            for (int q = 0; q < NB; ++q) acc[rb] = mfma32(A.b[l][q], bp[q], acc[rb]);
           }
         }
         const bool last = l == L - 2;
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+        for (int rb = 0; rb < RB; ++rb) {
+          float v[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const float a = act_base<ACT>(acc[rb][j] + bl[l]);
-            if (last) outp[rb][j] = won * a;
-            else buf[cur ^ 1][16 * rb + 4 * g + j][n] = from_f<T>(a);
+          for (int j = 0; j < 4; ++j) v[j] = act_base<ACT>(acc[rb][j] + bl[l][j]);
+          if (last) {
+            float o = won[0] * v[0];
+#pragma unroll
+            for (int j = 1; j < 4; ++j) o = fmaf(won[j], v[j], o);
+            outp[rb] = o;
+          } else {
+            put4(cur ^ 1, 16 * rb + r16, v);
           }
+        }
         if (!last) __syncthreads();
         cur ^= 1;
       }
 
-      // ---- output layer: this wavefront's 16 neurons, then the wavefronts in order
+      // ---- output layer: the four lane groups (same centre), then the
+      // wavefronts in order
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float v = row16_sum(outp[rb][j]);
-          if (r16 == 0) part[w][16 * rb + 4 * g + j] = v;
-        }
+      for (int rb = 0; rb < RB; ++rb) {
+        float v = outp[rb];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (g == 0) part[w][16 * rb + r16] = v;
+      }
       __syncthreads();
       if (tid < kEvalTile && qs[tid] >= 0) {
         float u = part[0][tid];
