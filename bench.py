@@ -226,6 +226,38 @@ def cpu_baseline(wl, target_s=12.0):
             "single_thread_value": round(n1 / dt1, 1), "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
+def eval_rate(tiles=6, warm=2):
+    """Evaluation throughput of the 1024^3 grid workload: the star-interface
+    networks (3 -> 128x4 -> 1 sin, BF16 MFMA operands) on 2^24-point tiles of the
+    grid, coordinates generated in-kernel.  Per query: 2*3*128 (layer 1) +
+    3*2*128^2 (hidden layers) + 2*128 (output) = 99,328 FLOP, 98,304 of them on MFMA."""
+    import torch
+    import nbm_inputs as I
+    from paper_2210_14907_amd.binding import NBM
+    wl, m, gn = I.C4, 1 << 24, 1024
+    nbm = NBM(wl, max_points=m, max_boundary=0, eval_only=True)
+    params = torch.tensor(I.xavier_params(wl, 0), dtype=torch.float32, device=nbm.device)
+    out = torch.empty(m, dtype=torch.float32, device=nbm.device)
+    for k in range(warm):
+        nbm.eval(params, m=m, tile_index=k, grid_n=gn, out=out)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for k in range(tiles):
+        nbm.eval(params, m=m, tile_index=warm + k, grid_n=gn, out=out)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / tiles
+    flop_q, mfma_q = 99328, 98304
+    del nbm, out
+    torch.cuda.empty_cache()
+    return {"workload": "c5_grid1024_eval (star networks 3->128x4->1 sin, BF16, 2^24-point tiles)",
+            "tile_points": m, "ms_per_tile": round(ms, 4), "pts_per_s": round(m / (ms * 1e-3), 1),
+            "grid_1024_cubed_s": round(ms * 64 * 1e-3, 4), "flop_per_query": flop_q,
+            "tflops": round(flop_q * m / (ms * 1e-3) / 1e12, 2),
+            "mfma_frac_bf16_peak": round(mfma_q * m / (ms * 1e-3) / PEAK["bf16"], 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +358,7 @@ def main():
             del r
             torch.cuda.empty_cache()
         line["same_step_other_precisions"] = extra
+        line["eval_c5"] = eval_rate()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)
