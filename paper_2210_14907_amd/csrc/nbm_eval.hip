@@ -3,9 +3,9 @@
 // kernels compacted per network (queries, or coordinates generated from a
 // grid tile index).
 //
-// Persistent work-groups of W/16 wavefronts; wavefront w owns neurons
-// 16w..16w+15 of every layer and keeps its rows of all hidden weight
-// matrices in registers for the whole launch (one load per network instead
+// Persistent work-groups; each wavefront owns two 16-neuron blocks of every
+// layer (one for FP32 operands of 128-wide nets) and keeps its rows of all
+// hidden weight matrices in registers for the whole launch (one load per network instead
 // of one per tile).  Each product is formed transposed, Z^T = W A^T: the
 // weights are the MFMA's A operand and the activation rows [centre][neuron]
 // in LDS its B operand, so a lane's accumulators hold four consecutive
@@ -27,16 +27,26 @@ namespace nbm {
 
 constexpr int kEvalTile = 64;   // centres per tile: four MFMA row blocks
 
+// 16-neuron blocks per wavefront: two, so that each activation operand read
+// from LDS feeds two products (half the LDS traffic of one block per
+// wavefront), unless the FP32 operands of a 128-wide net would not fit
+template <int W, int PREC> struct EvalShape {
+  static constexpr int NBW = (PREC == 0 && W >= 128) ? 1 : 2;
+  static constexpr int NW = W / (16 * NBW);   // wavefronts
+  static constexpr int NT = NW * 64;          // threads
+};
+
 template <int D, int W, int L, int ACT, int PREC>
-__global__ __launch_bounds__(W * 4, PREC == 1 ? 4 : 2) void k_eval_mlp(const Meta* meta, const float4* centres,
-                                                    const int* src, Nets nets, float* u_out) {
+__global__ __launch_bounds__((EvalShape<W, PREC>::NT), 2) void k_eval_mlp(const Meta* meta, const float4* centres,
+                                                                       const int* src, Nets nets, float* u_out) {
   typedef typename Op<PREC>::T T;
-  constexpr int NW = W / 16;              // wavefronts = 16-neuron blocks
-  constexpr int NT = W * 4;               // threads
+  constexpr int NBW = EvalShape<W, PREC>::NBW;
+  constexpr int NW = EvalShape<W, PREC>::NW;
+  constexpr int NT = EvalShape<W, PREC>::NT;
   constexpr int RB = kEvalTile / 16;      // MFMA row blocks per tile
   constexpr int KC = W / 4;               // K chunk per lane group
   constexpr int LD = W + (PREC == 0 ? 4 : 8);
-  constexpr int NB = PREC == 0 ? KC : KC / 8;   // B operand registers per layer
+  constexpr int NB = PREC == 0 ? KC : KC / 8;   // operand registers per layer and block
   static_assert(kEvalTile <= NT, "one thread per centre for the tile's bookkeeping");
   __shared__ __attribute__((aligned(16))) T buf[2][kEvalTile][LD];
   __shared__ float xs[kEvalTile][4];
@@ -44,8 +54,9 @@ __global__ __launch_bounds__(W * 4, PREC == 1 ? 4 : 2) void k_eval_mlp(const Met
   __shared__ float part[NW][kEvalTile];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r16 = lane & 15, g = lane >> 4;
-  const int n = w * 16 + r16;             // weight row held by this lane
   const int G = gridDim.x;
+  // neuron block k of this wavefront: neurons 16 (NBW w + k) + 0..15
+  auto blk = [&](int k) { return NBW * w + k; };
 
   for (int net = 0; net < 2; ++net) {
     const NetPtrs& np = nets.net[net];
@@ -54,35 +65,41 @@ __global__ __launch_bounds__(W * 4, PREC == 1 ? 4 : 2) void k_eval_mlp(const Met
     const int ntiles = (int)((meta->total[net] + kEvalTile - 1) / kEvalTile);
     if (ntiles == 0) continue;
 
-    // this lane's A operands (row n of W_l, K chunk g) of every hidden layer
-    struct WRows { float f[PREC == 0 ? L - 1 : 1][PREC == 0 ? NB : 1]; bf8 b[PREC == 1 ? L - 1 : 1][PREC == 1 ? NB : 1]; };
+    // this lane's A operands (row 16 blk(k) + r16 of W_l, K chunk g) of every
+    // hidden layer and block
+    struct WRows { float f[PREC == 0 ? L - 1 : 1][NBW][PREC == 0 ? NB : 1]; bf8 b[PREC == 1 ? L - 1 : 1][NBW][PREC == 1 ? NB : 1]; };
     WRows A;
 #pragma unroll
-    for (int l = 0; l < L - 1; ++l) {
-      if constexpr (PREC == 0) {
-        const float4* wp = (const float4*)((const float*)np.Wl[l] + (int64_t)n * W + g * KC);
+    for (int l = 0; l < L - 1; ++l)
 #pragma unroll
-        for (int q = 0; q < KC / 4; ++q) {
-          const float4 v = wp[q];
-          A.f[l][4 * q] = v.x; A.f[l][4 * q + 1] = v.y; A.f[l][4 * q + 2] = v.z; A.f[l][4 * q + 3] = v.w;
+      for (int k = 0; k < NBW; ++k) {
+        const int64_t row = 16 * blk(k) + r16;
+        if constexpr (PREC == 0) {
+          const float4* wp = (const float4*)((const float*)np.Wl[l] + row * W + g * KC);
+#pragma unroll
+          for (int q = 0; q < KC / 4; ++q) {
+            const float4 v = wp[q];
+            A.f[l][k][4 * q] = v.x; A.f[l][k][4 * q + 1] = v.y; A.f[l][k][4 * q + 2] = v.z; A.f[l][k][4 * q + 3] = v.w;
+          }
+        } else {
+          const bf8* wp = (const bf8*)((const T*)np.Wl[l] + row * W + g * KC);
+#pragma unroll
+          for (int q = 0; q < NB; ++q) A.b[l][k][q] = wp[q];
         }
-      } else {
-        const bf8* wp = (const bf8*)((const T*)np.Wl[l] + (int64_t)n * W + g * KC);
-#pragma unroll
-        for (int q = 0; q < NB; ++q) A.b[l][q] = wp[q];
       }
-    }
-    // the four output neurons of this lane's accumulators: n4 + j
-    const int n4 = w * 16 + 4 * g;
-    float bl[L - 1][4], W1n[4][3], b1n[4], won[4];
+    // the output neurons of this lane's accumulators: 16 blk(k) + 4 g + j
+    float bl[L - 1][NBW][4], W1n[NBW][4][3], b1n[NBW][4], won[NBW][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int k = 0; k < NBW; ++k)
 #pragma unroll
-      for (int l = 0; l < L - 1; ++l) bl[l][j] = np.bl[l][n4 + j];
-      for (int a = 0; a < 3; ++a) W1n[j][a] = a < D ? np.W1[(n4 + j) * D + a] : 0.f;
-      b1n[j] = np.b1[n4 + j];
-      won[j] = np.wout[n4 + j];
-    }
+      for (int j = 0; j < 4; ++j) {
+        const int nn = 16 * blk(k) + 4 * g + j;
+#pragma unroll
+        for (int l = 0; l < L - 1; ++l) bl[l][k][j] = np.bl[l][nn];
+        for (int a = 0; a < 3; ++a) W1n[k][j][a] = a < D ? np.W1[nn * D + a] : 0.f;
+        b1n[k][j] = np.b1[nn];
+        won[k][j] = np.wout[nn];
+      }
     const float bout = np.bout[0];
 
     // next tile's centre and query index (thread c < kEvalTile holds centre c)
@@ -105,24 +122,28 @@ __global__ __launch_bounds__(W * 4, PREC == 1 ? 4 : 2) void k_eval_mlp(const Met
       fetch(t + G);
       __syncthreads();
 
-      // stores of a lane's four consecutive neurons n4..n4+3 of centre c
-      auto put4 = [&](int b, int c, const float* v) {
-        if constexpr (PREC == 0) *(float4*)(&buf[b][c][n4]) = make_float4(v[0], v[1], v[2], v[3]);
-        else *(bf4*)(&buf[b][c][n4]) = bf4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+      // stores of a lane's four consecutive neurons of block k at centre c
+      auto put4 = [&](int b, int c, int k, const float* v) {
+        const int n0 = 16 * blk(k) + 4 * g;
+        if constexpr (PREC == 0) *(float4*)(&buf[b][c][n0]) = make_float4(v[0], v[1], v[2], v[3]);
+        else *(bf4*)(&buf[b][c][n0]) = bf4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
       };
 
-      // ---- layer 1 (VALU): centre 16 rb + r16, neurons n4 + j
+      // ---- layer 1 (VALU): centre 16 rb + r16, neurons 16 blk(k) + 4 g + j
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
         const int c = 16 * rb + r16;
-        float v[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          float z = b1n[j];
-          for (int a = 0; a < D; ++a) z = fmaf(W1n[j][a], xs[c][a], z);
-          v[j] = act_base<ACT>(z);
+        for (int k = 0; k < NBW; ++k) {
+          float v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            float z = b1n[k][j];
+            for (int a = 0; a < D; ++a) z = fmaf(W1n[k][j][a], xs[c][a], z);
+            v[j] = act_base<ACT>(z);
+          }
+          put4(0, c, k, v);
         }
-        put4(0, c, v);
       }
       __syncthreads();
 
@@ -131,9 +152,11 @@ __global__ __launch_bounds__(W * 4, PREC == 1 ? 4 : 2) void k_eval_mlp(const Met
       int cur = 0;
 #pragma unroll
       for (int l = 0; l < L - 1; ++l) {
-        f4 acc[RB];
+        f4 acc[NBW][RB];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) acc[rb] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int k = 0; k < NBW; ++k)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) acc[k][rb] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           if constexpr (PREC == 0) {
@@ -141,31 +164,41 @@ __global__ __launch_bounds__(W * 4, PREC == 1 ? 4 : 2) void k_eval_mlp(const Met
 #pragma unroll
             for (int q = 0; q < KC / 4; ++q) {
               const float4 b4 = bp[q];
-              acc[rb] = mfma4(A.f[l][4 * q], b4.x, acc[rb]);
-              acc[rb] = mfma4(A.f[l][4 * q + 1], b4.y, acc[rb]);
-              acc[rb] = mfma4(A.f[l][4 * q + 2], b4.z, acc[rb]);
-              acc[rb] = mfma4(A.f[l][4 * q + 3], b4.w, acc[rb]);
+#pragma unroll
+              for (int k = 0; k < NBW; ++k) {
+                acc[k][rb] = mfma4(A.f[l][k][4 * q], b4.x, acc[k][rb]);
+                acc[k][rb] = mfma4(A.f[l][k][4 * q + 1], b4.y, acc[k][rb]);
+                acc[k][rb] = mfma4(A.f[l][k][4 * q + 2], b4.z, acc[k][rb]);
+                acc[k][rb] = mfma4(A.f[l][k][4 * q + 3], b4.w, acc[k][rb]);
+              }
             }
           } else {
             const bf8* bp = (const bf8*)(&buf[cur][16 * rb + r16][g * KC]);
 #pragma unroll
-            for (int q = 0; q < NB; ++q) acc[rb] = mfma32(A.b[l][q], bp[q], acc[rb]);
+            for (int q = 0; q < NB; ++q) {
+              const bf8 b8 = bp[q];
+#pragma unroll
+              for (int k = 0; k < NBW; ++k) acc[k][rb] = mfma32(A.b[l][k][q], b8, acc[k][rb]);
+            }
           }
         }
         const bool last = l == L - 2;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-          float v[4];
+          float o = 0.f;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) v[j] = act_base<ACT>(acc[rb][j] + bl[l][j]);
-          if (last) {
-            float o = won[0] * v[0];
+          for (int k = 0; k < NBW; ++k) {
+            float v[4];
 #pragma unroll
-            for (int j = 1; j < 4; ++j) o = fmaf(won[j], v[j], o);
-            outp[rb] = o;
-          } else {
-            put4(cur ^ 1, 16 * rb + r16, v);
+            for (int j = 0; j < 4; ++j) v[j] = act_base<ACT>(acc[k][rb][j] + bl[l][k][j]);
+            if (last) {
+#pragma unroll
+              for (int j = 0; j < 4; ++j) o = fmaf(won[k][j], v[j], o);
+            } else {
+              put4(cur ^ 1, 16 * rb + r16, k, v);
+            }
           }
+          if (last) outp[rb] = o;
         }
         if (!last) __syncthreads();
         cur ^= 1;
@@ -206,12 +239,13 @@ hipError_t eval_impl(const EvalCall& c) {
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eval_mlp<D, W, L, ACT, PREC>, W * 4, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eval_mlp<D, W, L, ACT, PREC>,
+                                                       EvalShape<W, PREC>::NT, 0);
     if (e != hipSuccess) return e;
     resident = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
   }
   const int grid = c.max_grid < resident ? c.max_grid : resident;
-  hipLaunchKernelGGL((k_eval_mlp<D, W, L, ACT, PREC>), dim3(grid), dim3(W * 4), 0, c.stream, c.meta,
+  hipLaunchKernelGGL((k_eval_mlp<D, W, L, ACT, PREC>), dim3(grid), dim3(EvalShape<W, PREC>::NT), 0, c.stream, c.meta,
                      c.centres, c.src, *c.nets, c.u_out);
   return hipGetLastError();
 }
