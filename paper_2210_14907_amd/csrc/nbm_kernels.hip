@@ -129,13 +129,16 @@ __device__ inline void classify_block(const Problem& P, const float* pts, int64_
 }
 
 // exclusive scans of the block counts and the batch bookkeeping
-__global__ __launch_bounds__(256) void k_scan(const int* bc_in, int nblk_in, const int* bc_bnd,
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_scan(const int* bc_in, int nblk_in, const int* bc_bnd,
                                               int nblk_bnd, int* off_in, int* off_bnd, Meta* meta,
                                               int n, int nb, int cut_cap, int dim, int lo,
                                               int eval_mode) {
   // exclusive prefix sums of the per-block class counts, all classes at once:
-  // wavefront prefix sums by lane shuffles, then the four wavefronts' totals
-  __shared__ int wsum[4][4];
+  // wavefront prefix sums by lane shuffles, then the wavefronts' totals
+  // (256 threads for small batches, kScanThreads for large ones)
+  __shared__ int wsum[kScanThreads / 64][4];
+  const int nws = blockDim.x / 64;
   __shared__ int totals[8];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int arr = 0; arr < 2; ++arr) {
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(256) void k_scan(const int* bc_in, int nblk_in, con
     const int nblk = arr == 0 ? nblk_in : nblk_bnd;
     const int ncls = arr == 0 ? 3 : 2;
     int carry[3] = {0, 0, 0};
-    for (int base = 0; base < nblk; base += 256) {
+    for (int base = 0; base < nblk; base += (int)blockDim.x) {
       const int idx = base + tid;
       int v[3], x[3];
       for (int k = 0; k < 3; ++k) v[k] = (idx < nblk && k < ncls) ? bc[idx * 4 + k] : 0;
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(256) void k_scan(const int* bc_in, int nblk_in, con
       __syncthreads();
       for (int k = 0; k < 3; ++k) {
         int before = 0, tot = 0;
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < nws; ++q) {
           if (q < w) before += wsum[q][k];
           tot += wsum[q][k];
         }
@@ -1296,7 +1299,8 @@ static void prep_impl(const PrepCall& c, int64_t nblk, int64_t nblkb) {
                        c.eval ? 1 : 0, c.tile_index, c.grid_n, c.cls, c.rank, c.blockcnt, (int)nblk,
                        c.bpts, c.nb, c.bcls, c.brank, c.blockcnt_b, (int)(nblk + nblkb), c.shadows,
                        c.prec, spm);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, st, c.blockcnt, (int)nblk, c.blockcnt_b,
+  const int scan_threads = nblk + nblkb > 2048 ? kScanThreads : 256;
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(scan_threads), 0, st, c.blockcnt, (int)nblk, c.blockcnt_b,
                      (int)nblkb, c.off, c.off_b, c.meta, (int)c.n, (int)c.nb, c.cut_cap, D, c.P.lo,
                      c.eval ? 1 : 0);
   if (c.n + c.nb)
