@@ -267,16 +267,21 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--workload", default="c2", help="c2 (default, the headline line) or c1/c3/c4 for profiling")
+    ap.add_argument("--only-eval", action="store_true",
+                    help="print only the evaluation throughput of the 1024^3 grid workload (profiling)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the data-parallel path across GPUs is not part of "
-              "this build (see DESIGN.md, 'Sharding').", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU (data-parallel) path.",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     import nbm_inputs as I
 
+    if args.only_eval:
+        print(json.dumps({"eval_c5": eval_rate()}), flush=True)
+        return
     wl = I.WORKLOADS[args.workload]
     if args.calib_copy_mb:
         nbytes = args.calib_copy_mb << 20

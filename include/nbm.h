@@ -9,7 +9,7 @@
  * evaluated on implicit cells centred at random collocation points, with
  * automatic differentiation through the residual kernels and Adam.
  * The paper's loss equation is missing from its text; the residual computed
- * here is the cut-cell reading stated in the design doc (vertex-centred cell of
+ * here is this library's cut-cell reading of it (vertex-centred cell of
  * side h at each point, face/volume fractions of the piecewise-linear level
  * set, jump extension J = alpha + dist * [d_n u], Jacobi preconditioning,
  * loss = mean of squared point residuals, interior and boundary points).

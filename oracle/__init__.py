@@ -7,7 +7,7 @@ library: the only common dependency is `nbm_inputs`, which holds seeded input
 data and no arithmetic of the method.
 
 Parts (paper, Sec. 3 and Sec. 4.1; the loss equation of Sec. 3 is missing from
-the text, so the discretisation follows the readings listed in the design doc):
+the text, so the discretisation is this project's reading, stated in `scheme`):
   geometry  - level sets, projection onto the interface, simplex clipping
   problems  - coefficients, forcing, jump data and exact solutions
   scheme    - cut-cell finite-volume residual at arbitrary cell centres

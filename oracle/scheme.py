@@ -4,7 +4,7 @@ Paper Sec. 3: an implicit compute cell of a given resolution is placed at each
 collocation point, the solution values at the stencil vertices come from the
 networks, and each point contributes r_p = |M^-1 A u - M^-1 b|.  The paper's
 loss equation and the coefficients of the bootstrapped scheme are not in the
-text, so the scheme below is this project's reading (listed in the design doc):
+text, so the scheme below is this project's reading of them:
 
   cell C_p = x_p + [-h/2, h/2]^d, nodes y_0 = x_p, y_(+-i) = x_p +- h e_i;
   U(y) = u^{sigma(y)}(y);  two-sided values u~^s(y) = U(y) (+-) J(y) when y is
