@@ -23,9 +23,9 @@ def _nbm(wl, n, nb, **kw):
     return NBM(wl, max_points=max(n, 16), max_boundary=max(nb, 1), **kw)
 
 
-def _run(wl, pts, bpts, theta):
+def _run(wl, pts, bpts, theta, **kw):
     dev = torch.device("cuda:0")
-    m = _nbm(wl, pts.shape[0], bpts.shape[0])
+    m = _nbm(wl, pts.shape[0], bpts.shape[0], **kw)
     p = torch.tensor(theta, dtype=torch.float32, device=dev)
     tp = torch.tensor(pts, dtype=torch.float32, device=dev)
     tb = torch.tensor(bpts, dtype=torch.float32, device=dev).reshape(-1, wl.dim)
@@ -75,6 +75,28 @@ def test_step_parity(name, wl, n, nb, n_near, band):
           f"(cut {ncut})", flush=True)
     assert e_loss <= tol and e_res <= tol and e_grad <= tol
     assert e_unc <= (5 * tol if wl.prec == I.PREC_FP32 else tol)
+
+
+def test_step_parity_many_cut_cells():
+    """More cut cells than the residual launch's 1,024 cut-cell blocks and
+    more non-inline tiles than the forward-only pass's 512 blocks: both walk
+    their work with the grid as stride, checked against the oracle."""
+    wl = I.C2
+    theta = I.xavier_params(wl, 2).astype(np.float32).astype(np.float64)
+    pts, bpts = parity_batch(wl, 2048, 64, 2600, 0.003, seed=21)
+    pts = pts.astype(np.float32).astype(np.float64)
+    bpts = bpts.astype(np.float32).astype(np.float64)
+    L_o, g_o, res_o = N.loss_and_grad(wl, theta, pts, bpts)
+    L_g, r_g, g_g, counts, _ = _run(wl, pts, bpts, theta, cut_capacity=pts.shape[0])
+    ncut = int((res_o["cls"] == S.CLASS_CUT).sum())
+    nonin_tiles = ((2 + 2 * wl.dim) * ncut + bpts.shape[0]) // 16
+    assert counts[2] == ncut and counts[5] == 0
+    assert ncut > 1024 and nonin_tiles > 512
+    r_o = np.concatenate([res_o["r"], res_o["rb"]])
+    e_loss, e_res, e_grad = abs(L_g - L_o) / abs(L_o), max_rel(r_g, r_o), rel_err(g_g, g_o)
+    print(f"[parity] c2_many_cut: loss {e_loss:.2e} res {e_res:.2e} grad {e_grad:.2e} (cut {ncut})", flush=True)
+    tol = TOL[wl.prec]
+    assert e_loss <= tol and e_res <= tol and e_grad <= tol
 
 
 LARGE_ARG_CASES = [
