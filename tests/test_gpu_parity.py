@@ -237,3 +237,40 @@ def test_cut_capacity_overflow_gives_nan():
                                     torch.tensor(bpts, dtype=torch.float32, device=dev))
     assert math.isnan(loss.item())
     assert m.batch_counts().cpu().numpy()[5] == 1
+
+
+def test_forward_residual_replays_in_a_graph():
+    """forward_residual allocates nothing and records no memset, so the whole
+    step (prep, forward, residuals, fused backward, reductions) can be
+    captured in a HIP graph.  Every replay, with eager work of the program
+    between replays, must reproduce the eager loss and gradient bit for bit."""
+    from paper_2210_14907_amd import NBM
+    wl = I.C2
+    theta = I.xavier_params(wl, 6).astype(np.float32)
+    pts, bpts = parity_batch(wl, 4096, 96, 256, 0.02, seed=9)
+    m = NBM(wl, max_points=pts.shape[0], max_boundary=bpts.shape[0])
+    dev = torch.device("cuda:0")
+    p = torch.tensor(theta, device=dev)
+    tp = torch.tensor(pts, dtype=torch.float32, device=dev)
+    tb = torch.tensor(bpts, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    grad = torch.empty(m.P, dtype=torch.float32, device=dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        m.forward_residual(p, tp, tb, want_grad=True, loss=loss, grad=grad)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    loss_ref, grad_ref = loss.clone(), grad.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        m.forward_residual(p, tp, tb, want_grad=True, loss=loss, grad=grad)
+    for k in range(3):
+        loss.zero_()
+        grad.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(loss, loss_ref) and torch.equal(grad, grad_ref), f"replay {k}"
+        # eager work of the program between replays
+        m.forward_residual(p * 1.01, tp, tb, want_grad=True)
+        torch.cuda.synchronize()
