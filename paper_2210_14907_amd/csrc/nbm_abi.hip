@@ -360,6 +360,7 @@ static Nets nets_for(nbm_ctx* ctx, const float* params, void* ws) {
     np.bout = p + ctx->lay.bout;
     for (int l = 0; l < ctx->L - 1; ++l) {
       np.bl[l] = p + ctx->lay.bl[l];
+      np.Wf[l] = p + ctx->lay.Wl[l];
       np.Wl[l] = sh + ((size_t)(net * (ctx->L - 1) + l) * 2 + 0) * wsz;
       np.WlT[l] = sh + ((size_t)(net * (ctx->L - 1) + l) * 2 + 1) * wsz;
     }

@@ -57,6 +57,13 @@ __global__ __launch_bounds__((EvalShape<W, PREC>::NT), 2) void k_eval_mlp(const 
   const int G = gridDim.x;
   // neuron block k of this wavefront: neurons 16 (NBW w + k) + 0..15
   auto blk = [&](int k) { return NBW * w + k; };
+  // sin networks: weights and biases of layers 1..L times 1/(2 pi), so every
+  // pre-activation is in revolutions, the unit of the hardware sine
+  constexpr float ks = ACT == 1 ? 0.15915494309189535f : 1.0f;
+  auto act = [](float z) {
+    if constexpr (ACT == 1) return __builtin_amdgcn_sinf(z);
+    else return tanh_base(z).t;
+  };
 
   for (int net = 0; net < 2; ++net) {
     const NetPtrs& np = nets.net[net];
@@ -66,25 +73,24 @@ __global__ __launch_bounds__((EvalShape<W, PREC>::NT), 2) void k_eval_mlp(const 
     if (ntiles == 0) continue;
 
     // this lane's A operands (row 16 blk(k) + r16 of W_l, K chunk g) of every
-    // hidden layer and block
+    // hidden layer and block, from the FP32 master weights times ks, rounded
+    // once to the operand type
     struct WRows { float f[PREC == 0 ? L - 1 : 1][NBW][PREC == 0 ? NB : 1]; bf8 b[PREC == 1 ? L - 1 : 1][NBW][PREC == 1 ? NB : 1]; };
     WRows A;
 #pragma unroll
     for (int l = 0; l < L - 1; ++l)
 #pragma unroll
       for (int k = 0; k < NBW; ++k) {
-        const int64_t row = 16 * blk(k) + r16;
-        if constexpr (PREC == 0) {
-          const float4* wp = (const float4*)((const float*)np.Wl[l] + row * W + g * KC);
+        const float4* wp = (const float4*)(np.Wf[l] + (int64_t)(16 * blk(k) + r16) * W + g * KC);
 #pragma unroll
-          for (int q = 0; q < KC / 4; ++q) {
-            const float4 v = wp[q];
-            A.f[l][k][4 * q] = v.x; A.f[l][k][4 * q + 1] = v.y; A.f[l][k][4 * q + 2] = v.z; A.f[l][k][4 * q + 3] = v.w;
+        for (int q = 0; q < KC / 4; ++q) {
+          const float4 v = wp[q];
+          const float e[4] = {ks * v.x, ks * v.y, ks * v.z, ks * v.w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if constexpr (PREC == 0) A.f[l][k][4 * q + i] = e[i];
+            else A.b[l][k][q / 2][4 * (q & 1) + i] = (__bf16)e[i];
           }
-        } else {
-          const bf8* wp = (const bf8*)((const T*)np.Wl[l] + row * W + g * KC);
-#pragma unroll
-          for (int q = 0; q < NB; ++q) A.b[l][k][q] = wp[q];
         }
       }
     // the output neurons of this lane's accumulators: 16 blk(k) + 4 g + j
@@ -95,9 +101,9 @@ __global__ __launch_bounds__((EvalShape<W, PREC>::NT), 2) void k_eval_mlp(const 
       for (int j = 0; j < 4; ++j) {
         const int nn = 16 * blk(k) + 4 * g + j;
 #pragma unroll
-        for (int l = 0; l < L - 1; ++l) bl[l][k][j] = np.bl[l][nn];
-        for (int a = 0; a < 3; ++a) W1n[k][j][a] = a < D ? np.W1[nn * D + a] : 0.f;
-        b1n[k][j] = np.b1[nn];
+        for (int l = 0; l < L - 1; ++l) bl[l][k][j] = ks * np.bl[l][nn];
+        for (int a = 0; a < 3; ++a) W1n[k][j][a] = a < D ? ks * np.W1[nn * D + a] : 0.f;
+        b1n[k][j] = ks * np.b1[nn];
         won[k][j] = np.wout[nn];
       }
     const float bout = np.bout[0];
@@ -140,7 +146,7 @@ __global__ __launch_bounds__((EvalShape<W, PREC>::NT), 2) void k_eval_mlp(const 
           for (int j = 0; j < 4; ++j) {
             float z = b1n[k][j];
             for (int a = 0; a < D; ++a) z = fmaf(W1n[k][j][a], xs[c][a], z);
-            v[j] = act_base<ACT>(z);
+            v[j] = act(z);
           }
           put4(0, c, k, v);
         }
@@ -190,7 +196,7 @@ __global__ __launch_bounds__((EvalShape<W, PREC>::NT), 2) void k_eval_mlp(const 
           for (int k = 0; k < NBW; ++k) {
             float v[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = act_base<ACT>(acc[k][rb][j] + bl[l][k][j]);
+            for (int j = 0; j < 4; ++j) v[j] = act(acc[k][rb][j] + bl[l][k][j]);
             if (last) {
 #pragma unroll
               for (int j = 0; j < 4; ++j) o = fmaf(won[k][j], v[j], o);

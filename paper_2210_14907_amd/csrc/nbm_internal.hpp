@@ -61,6 +61,7 @@ struct NetPtrs {
   const float* bout;
   const void* Wl[kMaxDepth];    // shadow W_l [W][W] (operand dtype), l = 1..L-1 index = l-1
   const void* WlT[kMaxDepth];   // shadow W_l^T
+  const float* Wf[kMaxDepth];   // FP32 master W_l (row-major), same index as Wl
 };
 
 struct Nets {
