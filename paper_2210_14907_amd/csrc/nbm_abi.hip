@@ -226,7 +226,7 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
     // c = a - i b; e^{-i t} = conj(e^{i t}) handles negative wave numbers
     std::map<std::pair<int, int>, std::vector<int>> byyz;
     for (int m = 0; m < P.n_modes; ++m) byyz[{c.mode_k[3 * m + 1], c.mode_k[3 * m + 2]}].push_back(m);
-    constexpr int kRow = 256 * 8;   // bytes per phase row
+    constexpr int kRow = kForcingThreads * 8;   // bytes per phase row (one float2 per thread)
     for (const auto& kv : byyz) {
       const int ky = kv.first.first, kz = kv.first.second;
       const int oy = (9 + std::abs(ky)) * kRow + (ky < 0 ? 1 : 0);

@@ -6,6 +6,10 @@
 namespace nbm {
 
 constexpr int kMaxDepth = 8;   // hidden layers supported
+// threads per block of the Fourier forcing kernel; one phase row of its LDS
+// table holds one float2 per thread, and the mode table's offsets are bytes
+// into that table
+constexpr int kForcingThreads = 128;
 constexpr int kTile = 16;      // collocation centres per tile (MFMA M = 16)
 constexpr int kBlock = 256;    // threads per work-group (4 wavefronts)
 

@@ -320,13 +320,15 @@ __global__ __launch_bounds__(256) void k_scatter(Problem P, const Meta* meta, co
 //   f = Re sum_groups e^{i pi (k_y y + k_z z)} sum_{k_x in group} c e^{i pi k_x x},
 // one complex multiply-add per mode and one complex product per group; the
 // mode records are read eight at a time.
+// 128-thread blocks: the phase rows take 27 KB of LDS per block, so five
+// blocks share a compute unit and hide the mode-record and LDS latencies.
 // ===========================================================================
 template <int D>
-__global__ __launch_bounds__(256) void k_forcing(Problem P, const float* pts, int64_t n,
-                                                 float* fout, const Meta* meta, const int* cls,
-                                                 const int* rank, float* fslot) {
-  __shared__ float2 ph[27][256];
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(kForcingThreads) void k_forcing(Problem P, const float* pts, int64_t n,
+                                                             float* fout, const Meta* meta, const int* cls,
+                                                             const int* rank, float* fslot) {
+  __shared__ float2 ph[27][kForcingThreads];
+  const int64_t i = (int64_t)blockIdx.x * kForcingThreads + threadIdx.x;
   const int t = threadIdx.x;
   float x[3] = {0.f, 0.f, 0.f};
   if (i < n)
@@ -1348,10 +1350,11 @@ hipError_t launch_reduce_loss(hipStream_t st, const double* lossp, int nparts, c
 hipError_t launch_forcing(hipStream_t st, const Problem& P, const float* pts, int64_t n, float* f,
                           const Meta* meta, const int* cls, const int* rank, float* fslot) {
   if (n == 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + kForcingThreads - 1) / kForcingThreads)), block(kForcingThreads);
   if (P.dim == 2)
-    hipLaunchKernelGGL(k_forcing<2>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, n, f, meta, cls, rank, fslot);
+    hipLaunchKernelGGL(k_forcing<2>, grid, block, 0, st, P, pts, n, f, meta, cls, rank, fslot);
   else
-    hipLaunchKernelGGL(k_forcing<3>, dim3((n + 255) / 256), dim3(256), 0, st, P, pts, n, f, meta, cls, rank, fslot);
+    hipLaunchKernelGGL(k_forcing<3>, grid, block, 0, st, P, pts, n, f, meta, cls, rank, fslot);
   return hipGetLastError();
 }
 
