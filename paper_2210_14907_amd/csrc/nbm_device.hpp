@@ -436,9 +436,16 @@ __device__ __forceinline__ void act_bwd_l1(float z, const L1Axes& f, float ab, c
 //     c_7 = q (u^3 - 5u^2/3 + 11u/15 - 17/315);
 //   sin (S = sin z, C = cos z): c_k = S or C with the sign of the k-th
 //     derivative, over k!.
-struct Taylor { float a, c[8]; };   // c[1..7]
+//
+// Micro tier (opt-in per call site, for the 128-wide kernels): when every
+// lane also has |p|, |p - e| <= 1/256, f runs to k = 4 and the derivative
+// series to k = 5; the first omitted terms are below 1.2e-13 and 4e-13
+// (|c_5| <= 0.134, 6|c_6| <= 0.44), i.e. at most ~1e-7 of the residual once
+// E is divided by h^2.
+constexpr float kMicroX = 0.00390625f;   // 1/256
+struct Taylor { float a, c[8]; };   // c[1..K]
 
-template <int ACT>
+template <int ACT, int K = 7>
 __device__ __forceinline__ Taylor taylor_at(float z) {
   Taylor T;
   T.c[0] = 0.f;
@@ -451,8 +458,10 @@ __device__ __forceinline__ Taylor taylor_at(float z) {
     T.c[3] = C * (-1.0f / 6.0f);
     T.c[4] = S * (1.0f / 24.0f);
     T.c[5] = C * (1.0f / 120.0f);
-    T.c[6] = S * (-1.0f / 720.0f);
-    T.c[7] = C * (-1.0f / 5040.0f);
+    if (K >= 7) {
+      T.c[6] = S * (-1.0f / 720.0f);
+      T.c[7] = C * (-1.0f / 5040.0f);
+    }
   } else {
     const TanhBase tb = tanh_base(z);
     const float t = tb.t, q = tb.q, u = t * t, tq = t * q;
@@ -462,37 +471,38 @@ __device__ __forceinline__ Taylor taylor_at(float z) {
     T.c[3] = q * (u - 1.0f / 3.0f);
     T.c[4] = tq * (2.0f / 3.0f - u);
     T.c[5] = q * fmaf(u, u - 1.0f, 2.0f / 15.0f);
-    T.c[6] = tq * fmaf(u, 4.0f / 3.0f - u, -17.0f / 45.0f);
-    T.c[7] = q * fmaf(u, fmaf(u, u - 5.0f / 3.0f, 11.0f / 15.0f), -17.0f / 315.0f);
+    if (K >= 7) {
+      T.c[6] = tq * fmaf(u, 4.0f / 3.0f - u, -17.0f / 45.0f);
+      T.c[7] = q * fmaf(u, fmaf(u, u - 5.0f / 3.0f, 11.0f / 15.0f), -17.0f / 315.0f);
+    }
   }
   return T;
 }
 
-// f(x) = sum_{k=2..7} c_k x^k
+// f(x) = sum_{k=2..KF} c_k x^k
+template <int KF = 7>
 __device__ __forceinline__ float taylor_f(const Taylor& T, float x) {
-  float r = fmaf(x, T.c[7], T.c[6]);
-  r = fmaf(x, r, T.c[5]);
-  r = fmaf(x, r, T.c[4]);
-  r = fmaf(x, r, T.c[3]);
-  r = fmaf(x, r, T.c[2]);
+  float r = T.c[KF];
+#pragma unroll
+  for (int k = KF - 1; k >= 2; --k) r = fmaf(x, r, T.c[k]);
   return (x * x) * r;
 }
-// g(x) = sum_{k=3..7} k c_k x^(k-1), from d[k] = k c_k: a'(z + x) = c_1 + d_2 x + g(x)
+// g(x) = sum_{k=3..KG} k c_k x^(k-1), from d[k] = k c_k: a'(z + x) = c_1 + d_2 x + g(x)
+template <int KG = 7>
 __device__ __forceinline__ float taylor_g(const float* d, float x) {
-  float r = fmaf(x, d[7], d[6]);
-  r = fmaf(x, r, d[5]);
-  r = fmaf(x, r, d[4]);
-  r = fmaf(x, r, d[3]);
+  float r = d[KG];
+#pragma unroll
+  for (int k = KG - 1; k >= 3; --k) r = fmaf(x, r, d[k]);
   return (x * x) * r;
 }
 
-template <int D>
+template <int D, int KF = 7>
 __device__ __forceinline__ void taylor_fwd(const Taylor& T, const float* p, const float* e, float* Dv,
                                            float* Ev) {
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     const float m = p[i] - e[i];
-    const float fp = taylor_f(T, p[i]), fm = taylor_f(T, -m);
+    const float fp = taylor_f<KF>(T, p[i]), fm = taylor_f<KF>(T, -m);
     Dv[i] = fmaf(T.c[1], p[i], fp);
     Ev[i] = fmaf(T.c[1], e[i], fp + fm);
   }
@@ -502,18 +512,18 @@ __device__ __forceinline__ void taylor_fwd(const Taylor& T, const float* p, cons
 //   dD/dz = a'(z+p) - a'(z) = d_2 p + g(p),        dD/dp = a'(z+p),
 //   dE/dz = a'(z+p) - 2a'(z) + a'(z-m) = d_2 e + g(p) + g(-m),
 //   dE/dp = a'(z+p) - a'(z-m) = d_2 (p + m) + g(p) - g(-m),   dE/de = a'(z-m)
-template <int D>
+template <int D, int KG = 7>
 __device__ __forceinline__ void taylor_bwd(const Taylor& T, const float* p, const float* e, float ab,
                                            const float* Db, const float* Eb, float& zb, float* pb,
                                            float* eb) {
   float d[8];
 #pragma unroll
-  for (int k = 2; k <= 7; ++k) d[k] = (float)k * T.c[k];
+  for (int k = 2; k <= KG; ++k) d[k] = (float)k * T.c[k];
   zb = ab * T.c[1];
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     const float m = p[i] - e[i];
-    const float gp = taylor_g(d, p[i]), gm = taylor_g(d, -m);
+    const float gp = taylor_g<KG>(d, p[i]), gm = taylor_g<KG>(d, -m);
     const float dDdz = fmaf(d[2], p[i], gp);
     const float dDdp = T.c[1] + dDdz;
     const float dEdz = fmaf(d[2], e[i], gp + gm);
@@ -556,10 +566,22 @@ __device__ __attribute__((noinline)) ActBwdOut act_bwd_general(float z, float p0
 
 // forward: base a, and per-axis D, E from (z, p, e).  One wave-uniform
 // branch takes the inline tiny-argument tier when every lane qualifies.
-template <int ACT, int D>
+template <int D>
+__device__ __forceinline__ bool micro_args(const float* p, const float* e) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < D; ++i) ok = ok && fabsf(p[i]) <= kMicroX && fabsf(p[i] - e[i]) <= kMicroX;
+  return ok;
+}
+
+template <int ACT, int D, bool MICRO = false>
 __device__ __forceinline__ void act_fwd(float z, const float* p, const float* e, float& a,
                                         float* Dv, float* Ev) {
-  if (__all(tiny_args<ACT, D>(p, e))) {
+  if (MICRO && __all(micro_args<D>(p, e))) {
+    const Taylor T = taylor_at<ACT, 5>(z);
+    a = T.a;
+    taylor_fwd<D, 4>(T, p, e, Dv, Ev);
+  } else if (__all(tiny_args<ACT, D>(p, e))) {
     const Taylor T = taylor_at<ACT>(z);
     a = T.a;
     taylor_fwd<D>(T, p, e, Dv, Ev);
@@ -572,11 +594,13 @@ __device__ __forceinline__ void act_fwd(float z, const float* p, const float* e,
 }
 
 // backward: given stream adjoints (ab, Db, Eb) return (zb, pb, eb)
-template <int ACT, int D>
+template <int ACT, int D, bool MICRO = false>
 __device__ __forceinline__ void act_bwd(float z, const float* p, const float* e, float ab,
                                         const float* Db, const float* Eb, float& zb, float* pb,
                                         float* eb) {
-  if (__all(tiny_args<ACT, D>(p, e))) {
+  if (MICRO && __all(micro_args<D>(p, e))) {
+    taylor_bwd<D, 5>(taylor_at<ACT, 5>(z), p, e, ab, Db, Eb, zb, pb, eb);
+  } else if (__all(tiny_args<ACT, D>(p, e))) {
     taylor_bwd<D>(taylor_at<ACT>(z), p, e, ab, Db, Eb, zb, pb, eb);
   } else {
     const ActBwdOut r = act_bwd_general<ACT, D>(
@@ -612,11 +636,16 @@ __device__ __attribute__((noinline)) ActFBOut act_fb_general(float z, float p0, 
   return r;
 }
 
-template <int ACT, int D>
+template <int ACT, int D, bool MICRO = false>
 __device__ __forceinline__ void act_fb(float z, const float* p, const float* e, float ab,
                                        const float* Db, const float* Eb, float& a, float* Dv,
                                        float* Ev, float& zb, float* pb, float* eb) {
-  if (__all(tiny_args<ACT, D>(p, e))) {
+  if (MICRO && __all(micro_args<D>(p, e))) {
+    const Taylor T = taylor_at<ACT, 5>(z);
+    a = T.a;
+    taylor_fwd<D, 4>(T, p, e, Dv, Ev);
+    taylor_bwd<D, 5>(T, p, e, ab, Db, Eb, zb, pb, eb);
+  } else if (__all(tiny_args<ACT, D>(p, e))) {
     const Taylor T = taylor_at<ACT>(z);
     a = T.a;
     taylor_fwd<D>(T, p, e, Dv, Ev);
