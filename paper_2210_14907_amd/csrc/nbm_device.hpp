@@ -670,6 +670,112 @@ __device__ __forceinline__ void act_fb_l1(float z, const L1Axes& f, float ab, co
   act_bwd_l1<ACT, D>(z, f, ab, Db, Eb, zb, pb);
 }
 
+// The first-layer forms above, out of line: taken only by wavefronts with a
+// first-layer argument beyond the micro bound, so the common path keeps its
+// registers.
+template <int ACT, int D>
+__device__ __attribute__((noinline)) ActFwdOut act_fwd_l1_general(float z, L1Axes f) {
+  ActFwdOut r;
+  act_fwd_l1<ACT, D>(z, f, r.a, r.D, r.E);
+  return r;
+}
+struct ActFBL1Out { float a, D[3], E[3], zb, pb[3]; };
+template <int ACT, int D>
+__device__ __attribute__((noinline)) ActFBL1Out act_fb_l1_general(float z, L1Axes f, float ab, float D0,
+                                                                   float D1, float D2, float E0, float E1,
+                                                                   float E2) {
+  const float Db[3] = {D0, D1, D2}, Eb[3] = {E0, E1, E2};
+  ActFBL1Out r;
+  act_fb_l1<ACT, D>(z, f, ab, Db, Eb, r.a, r.D, r.E, r.zb, r.pb);
+  return r;
+}
+
+// First layer with micro arguments (every |p| <= 1/256 in the wavefront):
+// e = 0 and m = p, so the Taylor forms (values to k = 4, derivatives to
+// k = 5, first omitted terms as in the micro tier) reduce to
+//   D = c1 p + c2 p^2 + c3 p^3 + c4 p^4,      E = 2 (c2 p^2 + c4 p^4),
+//   dD/dz = d2 p + d3 p^2 + d4 p^3 + d5 p^4,  dD/dp = c1 + dD/dz,
+//   dE/dz = 2 (d3 p^2 + d5 p^4),              dE/dp = 2 (d2 p + d4 p^3),
+// with d_k = k c_k.  The per-network axis factors are then u = p, v = p^2.
+template <int D>
+__device__ __forceinline__ bool l1_micro(const float* p) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < D; ++i) ok = ok && fabsf(p[i]) <= kMicroX;
+  return ok;
+}
+template <int D>
+__device__ inline L1Axes l1_axes_micro(const float* p) {
+  L1Axes r;
+  for (int i = 0; i < 3; ++i) { r.u[i] = 0.f; r.v[i] = 0.f; }
+  for (int i = 0; i < D; ++i) { r.u[i] = p[i]; r.v[i] = p[i] * p[i]; }
+  return r;
+}
+
+template <int ACT, int D>
+__device__ __forceinline__ void act_fwd_l1_micro(float z, const L1Axes& f, float& a, float* Dv, float* Ev) {
+  const Taylor T = taylor_at<ACT, 5>(z);
+  a = T.a;
+  const float e2 = 2.0f * T.c[2], e4 = 2.0f * T.c[4];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const float p = f.u[i], p2 = f.v[i];
+    Dv[i] = p * fmaf(p, fmaf(p, fmaf(p, T.c[4], T.c[3]), T.c[2]), T.c[1]);
+    Ev[i] = p2 * fmaf(p2, e4, e2);
+  }
+}
+
+template <int ACT, int D>
+__device__ __forceinline__ void act_fb_l1_micro(float z, const L1Axes& f, float ab, const float* Db,
+                                                const float* Eb, float& a, float* Dv, float* Ev,
+                                                float& zb, float* pb) {
+  const Taylor T = taylor_at<ACT, 5>(z);
+  a = T.a;
+  const float e2 = 2.0f * T.c[2], e4 = 2.0f * T.c[4];
+  const float d2 = 2.0f * T.c[2], d3 = 3.0f * T.c[3], d4 = 4.0f * T.c[4], d5 = 5.0f * T.c[5];
+  const float g2 = 2.0f * d2, g3 = 2.0f * d3, g4 = 2.0f * d4, g5 = 2.0f * d5;
+  zb = ab * T.c[1];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const float p = f.u[i], p2 = f.v[i];
+    Dv[i] = p * fmaf(p, fmaf(p, fmaf(p, T.c[4], T.c[3]), T.c[2]), T.c[1]);
+    Ev[i] = p2 * fmaf(p2, e4, e2);
+    const float dDdz = p * fmaf(p, fmaf(p, fmaf(p, d5, d4), d3), d2);
+    const float dDdp = T.c[1] + dDdz;
+    const float dEdz = p2 * fmaf(p2, g5, g3);
+    const float dEdp = p * fmaf(p2, g4, g2);
+    zb = fmaf(Db[i], dDdz, fmaf(Eb[i], dEdz, zb));
+    pb[i] = fmaf(Db[i], dDdp, Eb[i] * dEdp);
+  }
+}
+
+// first-layer dispatch: the micro forms inline, the others out of line
+template <int ACT, int D>
+__device__ __forceinline__ void act_fwd_l1_any(bool micro, float z, const L1Axes& f, float& a, float* Dv,
+                                               float* Ev) {
+  if (micro) {
+    act_fwd_l1_micro<ACT, D>(z, f, a, Dv, Ev);
+  } else {
+    const ActFwdOut r = act_fwd_l1_general<ACT, D>(z, f);
+    a = r.a;
+    for (int i = 0; i < D; ++i) { Dv[i] = r.D[i]; Ev[i] = r.E[i]; }
+  }
+}
+template <int ACT, int D>
+__device__ __forceinline__ void act_fb_l1_any(bool micro, float z, const L1Axes& f, float ab,
+                                              const float* Db, const float* Eb, float& a, float* Dv,
+                                              float* Ev, float& zb, float* pb) {
+  if (micro) {
+    act_fb_l1_micro<ACT, D>(z, f, ab, Db, Eb, a, Dv, Ev, zb, pb);
+  } else {
+    const ActFBL1Out r = act_fb_l1_general<ACT, D>(z, f, ab, Db[0], D > 1 ? Db[1] : 0.f, D > 2 ? Db[2] : 0.f,
+                                                   Eb[0], D > 1 ? Eb[1] : 0.f, D > 2 ? Eb[2] : 0.f);
+    a = r.a;
+    zb = r.zb;
+    for (int i = 0; i < D; ++i) { Dv[i] = r.D[i]; Ev[i] = r.E[i]; pb[i] = r.pb[i]; }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Level sets (FP64).  Omega^- = {phi < 0}; phi = 0 belongs to Omega^+.
 // ---------------------------------------------------------------------------

@@ -91,7 +91,9 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
     float W1n[3], p1[3];
     for (int a = 0; a < D; ++a) { W1n[a] = np.W1[n * D + a]; p1[a] = h * W1n[a]; }
     // first-layer axis factors, constant per net: kept in LDS, not registers
-    if (g == 0) l1ax[n] = l1_axes<ACT, D>(p1);
+    // micro first layer when every neuron of this wavefront has |h W1| <= 1/256
+    const bool l1m = __all(l1_micro<D>(p1));
+    if (g == 0) l1ax[n] = l1m ? l1_axes_micro<D>(p1) : l1_axes<ACT, D>(p1);
     __syncthreads();
     const float b1n = np.b1[n], won = np.wout[n];
     const float inv_hh = 1.0f / hh, inv_mu = 1.0f / (float)P.mu[net];
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
         for (int a = 0; a < D; ++a) z += W1n[a] * xs[X][c][a];
         z1[j] = z;
         float av, Dv[3], Ev[3];
-        act_fwd_l1<ACT, D>(z, l1ax[n], av, Dv, Ev);
+        act_fwd_l1_any<ACT, D>(l1m, z, l1ax[n], av, Dv, Ev);
         bufR[0][0][c][n] = from_f<T>(av);
         for (int a = 0; a < D; ++a) {
           bufR[0][1 + a][c][n] = from_f<T>(Dv[a]);
@@ -337,7 +339,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
             }
             act_fb<ACT, D>(zz, pp, ee, acc[0][j], Db, Eb, av[0], Dv, Ev, zb, pb, eb);
           } else {
-            act_fb_l1<ACT, D>(z1[j], l1ax[n], acc[0][j], Db, Eb, av[0], Dv, Ev, zb, pb);
+            act_fb_l1_any<ACT, D>(l1m, z1[j], l1ax[n], acc[0][j], Db, Eb, av[0], Dv, Ev, zb, pb);
           }
           for (int a = 0; a < D; ++a) { av[1 + a] = Dv[a]; av[1 + D + a] = Ev[a]; }
           if constexpr (PREC == 0) {
