@@ -30,7 +30,7 @@ static int fail(int code, const std::string& msg) {
 
 namespace {
 struct Layout {
-  size_t modes32, modes64, fmodes, meta, blockcnt, off, blockcnt_b, off_b, cls, rank, bcls, brank, cutidx,
+  size_t modes32, modes64, fmodes, meta, ctot, coff, blockcnt, off, blockcnt_b, off_b, cls, rank, bcls, brank, cutidx,
       centres, src, outputs, adj, Zst, Ast, ALst, dZ, dZw, shadow, partial, lossp, resid, lossbuf, fpre, fslot, total;
 };
 }  // namespace
@@ -57,6 +57,7 @@ struct nbm_ctx {
   int64_t per_net, Ptot;
   NetLayout lay;
   int64_t cap_n, cap_nb, cut_cap, cap_slots, cap_tiles, lstride;
+  int64_t nchunk;   // interior chunks of the two-level scan at capacity
   int G, Gf, Gfz;
   bool no_fused;
   Layout lo;
@@ -98,10 +99,15 @@ static void make_layout(nbm_ctx* c) {
   auto take_tr = [&](size_t bytes) { return take(ev ? 0 : bytes); };
   int64_t nblk = (c->cap_n + 255) / 256 + 1, nblkb = (c->cap_nb + 255) / 256 + 1;
   int64_t nblkc = (c->cut_cap + 255) / 256 + 1;
+  c->nchunk = scan_chunks(nblk);
   L.modes32 = take(sizeof(float) * 8 * (c->cfg.n_modes + 1));
   L.modes64 = take(sizeof(double) * 5 * (c->cfg.n_modes + 1));
   L.fmodes = take(sizeof(FMode) * (c->fmodes.size() + 1));
   L.meta = take(sizeof(Meta));
+  // chunk totals and offsets of the two-level scan: interior chunks, then
+  // boundary chunks at a fixed offset
+  L.ctot = take(sizeof(int) * 4 * (scan_chunks(nblk) + scan_chunks(nblkb)));
+  L.coff = take(sizeof(int) * 4 * (scan_chunks(nblk) + scan_chunks(nblkb)));
   L.blockcnt = take(sizeof(int) * 4 * nblk);
   L.off = take(sizeof(int) * 4 * nblk);
   L.blockcnt_b = take(sizeof(int) * 4 * nblkb);
@@ -414,6 +420,8 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   pc.bcls = at<int>(ws, Lo.bcls); pc.brank = at<int>(ws, Lo.brank);
   pc.blockcnt_b = at<int>(ws, Lo.blockcnt_b); pc.off_b = at<int>(ws, Lo.off_b);
   pc.meta = at<Meta>(ws, Lo.meta);
+  pc.ctot = at<int>(ws, Lo.ctot); pc.ctot_b = pc.ctot + 4 * ctx->nchunk;
+  pc.coff = at<int>(ws, Lo.coff); pc.coff_b = pc.coff + 4 * ctx->nchunk;
   pc.centres = at<float4>(ws, Lo.centres);
   pc.src = at<int>(ws, Lo.src);
   pc.cutidx = at<int>(ws, Lo.cutidx);
@@ -627,6 +635,8 @@ extern "C" int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const f
   pc.bcls = at<int>(ws, Lo.bcls); pc.brank = at<int>(ws, Lo.brank);
   pc.blockcnt_b = at<int>(ws, Lo.blockcnt_b); pc.off_b = at<int>(ws, Lo.off_b);
   pc.meta = at<Meta>(ws, Lo.meta);
+  pc.ctot = at<int>(ws, Lo.ctot); pc.ctot_b = pc.ctot + 4 * ctx->nchunk;
+  pc.coff = at<int>(ws, Lo.coff); pc.coff_b = pc.coff + 4 * ctx->nchunk;
   pc.centres = at<float4>(ws, Lo.centres);
   pc.src = at<int>(ws, Lo.src);
   pc.cutidx = at<int>(ws, Lo.cutidx);

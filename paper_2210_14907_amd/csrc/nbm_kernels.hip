@@ -129,48 +129,75 @@ __device__ inline void classify_block(const Problem& P, const float* pts, int64_
 }
 
 // exclusive scans of the block counts and the batch bookkeeping
-constexpr int kScanThreads = 1024;
+
+// one chunk of blockDim.x consecutive entries [base, base + blockDim.x) of a
+// block-count array (records of 4 ints, ncls classes used): exclusive prefix
+// sums, all classes at once, by lane shuffles within each wavefront and then
+// the wavefronts' totals; carry[k] enters as the offset of the chunk and
+// leaves advanced by its total.  Every thread of the block calls it.
+__device__ inline void scan_chunk(const int* bc, int nblk, int base, int ncls, int* off, int carry[3],
+                                  int (*wsum)[4]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nws = blockDim.x / 64;
+  const int idx = base + tid;
+  int v[3], x[3];
+  for (int k = 0; k < 3; ++k) v[k] = (idx < nblk && k < ncls) ? bc[idx * 4 + k] : 0;
+  for (int k = 0; k < 3; ++k) x[k] = v[k];
+  for (int d = 1; d < 64; d <<= 1)
+    for (int k = 0; k < 3; ++k) {
+      const int y = __shfl_up(x[k], d);
+      if (lane >= d) x[k] += y;
+    }
+  if (lane == 63)
+    for (int k = 0; k < 3; ++k) wsum[w][k] = x[k];
+  __syncthreads();
+  for (int k = 0; k < 3; ++k) {
+    int before = 0, tot = 0;
+    for (int q = 0; q < nws; ++q) {
+      if (q < w) before += wsum[q][k];
+      tot += wsum[q][k];
+    }
+    if (idx < nblk && k < ncls) off[idx * 4 + k] = carry[k] + before + x[k] - v[k];
+    carry[k] += tot;
+  }
+  __syncthreads();
+}
+
+// first level of the scan of large batches: block g scans the g-th chunk of
+// kScanThreads block counts (interior chunks, then boundary chunks) from zero
+// and writes the chunk's totals, which the second level (k_scan over the
+// chunk totals) turns into the chunk offsets that the scatter adds
+__global__ __launch_bounds__(kScanThreads) void k_scan_chunks(const int* bc_in, int nblk_in,
+                                                              const int* bc_bnd, int nblk_bnd,
+                                                              int* off_in, int* off_bnd, int* ctot_in,
+                                                              int* ctot_bnd, int nchunk_in) {
+  __shared__ int wsum[kScanThreads / 64][4];
+  const bool bnd = (int)blockIdx.x >= nchunk_in;
+  const int g = bnd ? (int)blockIdx.x - nchunk_in : (int)blockIdx.x;
+  int carry[3] = {0, 0, 0};
+  scan_chunk(bnd ? bc_bnd : bc_in, bnd ? nblk_bnd : nblk_in, g * kScanThreads, bnd ? 2 : 3,
+             bnd ? off_bnd : off_in, carry, wsum);
+  if (threadIdx.x == 0) {
+    int* ct = (bnd ? ctot_bnd : ctot_in) + g * 4;
+    for (int k = 0; k < 4; ++k) ct[k] = k < 3 ? carry[k] : 0;
+  }
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_scan(const int* bc_in, int nblk_in, const int* bc_bnd,
                                               int nblk_bnd, int* off_in, int* off_bnd, Meta* meta,
                                               int n, int nb, int cut_cap, int dim, int lo,
                                               int eval_mode) {
-  // exclusive prefix sums of the per-block class counts, all classes at once:
-  // wavefront prefix sums by lane shuffles, then the wavefronts' totals
-  // (256 threads for small batches, kScanThreads for large ones)
+  // exclusive prefix sums of the per-block class counts (or, for large
+  // batches, of the chunk totals), 256 or kScanThreads threads
   __shared__ int wsum[kScanThreads / 64][4];
-  const int nws = blockDim.x / 64;
   __shared__ int totals[8];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x;
   for (int arr = 0; arr < 2; ++arr) {
     const int* bc = arr == 0 ? bc_in : bc_bnd;
     int* off = arr == 0 ? off_in : off_bnd;
     const int nblk = arr == 0 ? nblk_in : nblk_bnd;
     const int ncls = arr == 0 ? 3 : 2;
     int carry[3] = {0, 0, 0};
-    for (int base = 0; base < nblk; base += (int)blockDim.x) {
-      const int idx = base + tid;
-      int v[3], x[3];
-      for (int k = 0; k < 3; ++k) v[k] = (idx < nblk && k < ncls) ? bc[idx * 4 + k] : 0;
-      for (int k = 0; k < 3; ++k) x[k] = v[k];
-      for (int d = 1; d < 64; d <<= 1)
-        for (int k = 0; k < 3; ++k) {
-          const int y = __shfl_up(x[k], d);
-          if (lane >= d) x[k] += y;
-        }
-      if (lane == 63)
-        for (int k = 0; k < 3; ++k) wsum[w][k] = x[k];
-      __syncthreads();
-      for (int k = 0; k < 3; ++k) {
-        int before = 0, tot = 0;
-        for (int q = 0; q < nws; ++q) {
-          if (q < w) before += wsum[q][k];
-          tot += wsum[q][k];
-        }
-        if (idx < nblk && k < ncls) off[idx * 4 + k] = carry[k] + before + x[k] - v[k];
-        carry[k] += tot;
-      }
-      __syncthreads();
-    }
+    for (int base = 0; base < nblk; base += (int)blockDim.x) scan_chunk(bc, nblk, base, ncls, off, carry, wsum);
     if (tid == 0)
       for (int k = 0; k < ncls; ++k) totals[arr * 4 + k] = carry[k];
   }
@@ -253,13 +280,14 @@ __global__ __launch_bounds__(256) void k_classify(Problem P, const float* pts, i
 
 template <int D>
 __device__ inline void scatter_block(const Problem& P, const Meta* meta, const float* pts, int64_t n,
-                                     const int* cls, int* rank, const int* off, int bnd,
-                                     int64_t tile_index, int grid_n, float4* centres, int* src,
+                                     const int* cls, int* rank, const int* off, const int* coff,
+                                     int bnd, int64_t tile_index, int grid_n, float4* centres, int* src,
                                      int* cutidx, int blk, float* fslot) {
   int64_t i = (int64_t)blk * 256 + threadIdx.x;
   if (i >= n) return;
   int c = cls[i];
-  int r = rank[i] + off[blk * 4 + c];
+  // block offsets within their chunk, plus the chunk's offset (large batches)
+  int r = rank[i] + off[blk * 4 + c] + (coff ? coff[(blk / kScanThreads) * 4 + c] : 0);
   rank[i] = r;
   float xf[3] = {0, 0, 0};
   if (pts) {
@@ -304,12 +332,13 @@ __global__ __launch_bounds__(256) void k_scatter(Problem P, const Meta* meta, co
                                                  int64_t tile_index, int grid_n, float4* centres,
                                                  int* src, int* cutidx, int nblk, const float* bpts,
                                                  int64_t nb, const int* bcls, int* brank,
-                                                 const int* off_b, float* fslot) {
+                                                 const int* off_b, float* fslot, const int* coff,
+                                                 const int* coff_b) {
   if ((int)blockIdx.x < nblk)
-    scatter_block<D>(P, meta, pts, n, cls, rank, off, 0, tile_index, grid_n, centres, src, cutidx,
-                     blockIdx.x, fslot);
+    scatter_block<D>(P, meta, pts, n, cls, rank, off, coff, 0, tile_index, grid_n, centres, src,
+                     cutidx, blockIdx.x, fslot);
   else
-    scatter_block<D>(P, meta, bpts, nb, bcls, brank, off_b, 1, 0, 0, centres, src, cutidx,
+    scatter_block<D>(P, meta, bpts, nb, bcls, brank, off_b, coff_b, 1, 0, 0, centres, src, cutidx,
                      blockIdx.x - nblk, nullptr);
 }
 
@@ -1301,14 +1330,26 @@ static void prep_impl(const PrepCall& c, int64_t nblk, int64_t nblkb) {
                        c.eval ? 1 : 0, c.tile_index, c.grid_n, c.cls, c.rank, c.blockcnt, (int)nblk,
                        c.bpts, c.nb, c.bcls, c.brank, c.blockcnt_b, (int)(nblk + nblkb), c.shadows,
                        c.prec, spm);
-  const int scan_threads = nblk + nblkb > 2048 ? kScanThreads : 256;
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(scan_threads), 0, st, c.blockcnt, (int)nblk, c.blockcnt_b,
-                     (int)nblkb, c.off, c.off_b, c.meta, (int)c.n, (int)c.nb, c.cut_cap, D, c.P.lo,
-                     c.eval ? 1 : 0);
+  // up to 2048 point blocks one work-group scans the block counts; larger
+  // batches (evaluation tiles, the largest training batches) scan chunks of
+  // kScanThreads counts in parallel, then the chunk totals
+  const bool chunked = nblk + nblkb > 2048;
+  const int64_t nci = (nblk + kScanThreads - 1) / kScanThreads, ncb = (nblkb + kScanThreads - 1) / kScanThreads;
+  if (chunked) {
+    hipLaunchKernelGGL(k_scan_chunks, dim3(nci + ncb), dim3(kScanThreads), 0, st, c.blockcnt, (int)nblk,
+                       c.blockcnt_b, (int)nblkb, c.off, c.off_b, c.ctot, c.ctot_b, (int)nci);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, st, c.ctot, (int)nci, c.ctot_b, (int)ncb, c.coff,
+                       c.coff_b, c.meta, (int)c.n, (int)c.nb, c.cut_cap, D, c.P.lo, c.eval ? 1 : 0);
+  } else {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, st, c.blockcnt, (int)nblk, c.blockcnt_b,
+                       (int)nblkb, c.off, c.off_b, c.meta, (int)c.n, (int)c.nb, c.cut_cap, D, c.P.lo,
+                       c.eval ? 1 : 0);
+  }
   if (c.n + c.nb)
     hipLaunchKernelGGL(k_scatter<D>, dim3(nblk + nblkb), dim3(256), 0, st, c.P, c.meta, c.pts, c.n,
                        c.cls, c.rank, c.off, c.tile_index, c.grid_n, c.centres, c.src, c.cutidx,
-                       (int)nblk, c.bpts, c.nb, c.bcls, c.brank, c.off_b, c.fslot);
+                       (int)nblk, c.bpts, c.nb, c.bcls, c.brank, c.off_b, c.fslot,
+                       chunked ? c.coff : nullptr, chunked ? c.coff_b : nullptr);
 }
 
 hipError_t launch_prep(const PrepCall& c) {

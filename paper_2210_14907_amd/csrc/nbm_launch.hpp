@@ -126,8 +126,15 @@ struct PrepCall {
   ShadowJobs shadows;   // operand copies made in the same launch (count 0: none)
   int prec;
   float* fslot;         // manufactured forcing of uncut points in slot order, or NULL
+  // chunk totals and chunk offsets of the two-level scan (more than 2048
+  // point blocks): kScanThreads block counts per chunk, records of 4 ints
+  int *ctot, *ctot_b, *coff, *coff_b;
 };
 hipError_t launch_prep(const PrepCall& c);
+
+// point blocks per chunk of the two-level offsets scan
+constexpr int kScanThreads = 1024;
+inline int64_t scan_chunks(int64_t nblk) { return (nblk + kScanThreads - 1) / kScanThreads; }
 
 // Cut cells are walked by at most this many blocks of the residual launch
 // (one loss partial each); the cell count itself is known only on the device.
