@@ -82,6 +82,47 @@ __device__ inline int classify_point(const Problem& P, const float* xf, double h
   return same ? (m0 ? 0 : 1) : 2;
 }
 
+// coordinates of point q of the grid_n^D lattice, x_a = -1 + 2 i_a / grid_n,
+// i_0 varying fastest; 32-bit division while the index fits in 32 bits (the
+// 64-bit division is a long instruction sequence)
+template <int D>
+__device__ inline void lattice_coords(int64_t q, int grid_n, float* xf) {
+  if ((uint64_t)q < (1ull << 32)) {
+    uint32_t u = (uint32_t)q;
+    const uint32_t gn = (uint32_t)grid_n;
+    for (int a = 0; a < D; ++a) {
+      const uint32_t t = u / gn;
+      xf[a] = -1.0f + 2.0f * (float)(u - t * gn) / (float)grid_n;
+      u = t;
+    }
+  } else {
+    const int64_t gn = grid_n;
+    for (int a = 0; a < D; ++a) { xf[a] = -1.0f + 2.0f * (float)(q % gn) / (float)gn; q /= gn; }
+  }
+}
+
+// side of an evaluation point: the decision of the FP64 level set, taken from
+// an FP32 evaluation of the star's phi where |phi| exceeds 1e-3 (its FP32
+// rounding error is below 1e-6 for coordinates in [-1, 1] away from the
+// polar axis), else from the FP64 evaluation
+template <int D>
+__device__ inline bool eval_minus(const Problem& P, const float* xf) {
+  if (P.iface == 1) {
+    const float X = xf[0], Y = xf[1], Z = D > 2 ? xf[2] : 0.0f;
+    const float rho2 = X * X + Y * Y, r2 = rho2 + Z * Z;
+    if (rho2 >= 1e-8f) {   // no underflow in rho^4 r^4
+      const float x2 = X * X, y2 = Y * Y;
+      const float im5 = Y * (5.0f * x2 * x2 - 10.0f * x2 * y2 + y2 * y2);
+      const float ang = 4.0f * Z * (Z * Z - rho2) * im5 / (rho2 * rho2 * r2 * r2);
+      const float ph = sqrtf(r2) - (float)P.R - (float)P.amp * ang;
+      if (fabsf(ph) > 1e-3f) return ph < 0.0f;
+    }
+  }
+  double x[3] = {0, 0, 0};
+  for (int a = 0; a < D; ++a) x[a] = xf[a];
+  return is_minus<D>(P, x);
+}
+
 // per-block class counts and block-local ranks (wave ballots)
 // mode 0: interior points (3 classes), 1: boundary / eval points (2 sides),
 // eval points are either given (pts) or generated from a grid tile.
@@ -96,15 +137,10 @@ __device__ inline void classify_block(const Problem& P, const float* pts, int64_
     if (pts) {
       for (int a = 0; a < D; ++a) xf[a] = pts[i * D + a];
     } else {
-      int64_t q = tile_index * n + i, gn = grid_n;
-      for (int a = 0; a < D; ++a) { xf[a] = -1.0f + 2.0f * (float)(q % gn) / (float)gn; q /= gn; }
+      lattice_coords<D>(tile_index * n + i, grid_n, xf);
     }
     if (mode == 0) c = classify_point<D>(P, xf, P.h);
-    else {
-      double x[3] = {0, 0, 0};
-      for (int a = 0; a < D; ++a) x[a] = xf[a];
-      c = is_minus<D>(P, x) ? 0 : 1;
-    }
+    else c = eval_minus<D>(P, xf) ? 0 : 1;
   }
   int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -293,8 +329,7 @@ __device__ inline void scatter_block(const Problem& P, const Meta* meta, const f
   if (pts) {
     for (int a = 0; a < D; ++a) xf[a] = pts[i * D + a];
   } else {
-    int64_t q = tile_index * n + i, gn = grid_n;
-    for (int a = 0; a < D; ++a) { xf[a] = -1.0f + 2.0f * (float)(q % gn) / (float)gn; q /= gn; }
+    lattice_coords<D>(tile_index * n + i, grid_n, xf);
   }
   float4 xc = make_float4(xf[0], xf[1], xf[2], 0.0f);
   if (bnd || c < 2) {
