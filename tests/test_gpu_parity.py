@@ -242,6 +242,34 @@ def test_eval_two_level_scan_every_output():
     assert np.all(np.minimum(np.abs(u[tie] - ref[tie]), np.abs(u[tie] - alt)) <= 1e-5 * scale)
 
 
+def test_eval_star_side_near_interface():
+    """Queries within 3e-3 of the star interface, where the evaluation decides
+    each side from FP32 level-set values outside a 1e-3 margin and from FP64
+    inside it: every output is compared with the oracle (FP32 operands, so a
+    query given the other network's value fails)."""
+    from paper_2210_14907_amd import NBM
+    from oracle import geometry as G
+    from oracle import mlp as M
+    wl = I.C4.replace(prec=I.PREC_FP32)
+    theta = I.xavier_params(wl, 5).astype(np.float32).astype(np.float64)
+    cand = I.lattice_points(4_000_000, 3, -1.0, 1.0, seed=11) * 0.7
+    cand = np.round(cand * 2.0 ** 22) / 2.0 ** 22
+    ph = G.phi(wl, cand)
+    q = cand[np.abs(ph) < 3e-3][:40_000]
+    ph = G.phi(wl, q)
+    print(f"[parity] star side: {q.shape[0]} queries, {int((np.abs(ph) <= 1e-3).sum())} inside the margin",
+          flush=True)
+    assert q.shape[0] > 20_000 and (np.abs(ph) <= 1e-3).sum() > 5_000
+    m = NBM(wl, max_points=q.shape[0], max_boundary=1, eval_only=True)
+    dev = torch.device("cuda:0")
+    p = torch.tensor(theta, dtype=torch.float32, device=dev)
+    u = m.eval(p, torch.tensor(q, dtype=torch.float32, device=dev)).cpu().numpy()
+    side = G.side_minus(wl, q)
+    ref = M.eval_two(wl, theta, q, side)
+    tie = np.abs(ph) < 1e-12
+    assert max_rel(u[~tie], ref[~tie]) <= 1e-5
+
+
 def test_edge_cases_small_and_ragged():
     wl = I.C2
     theta = I.xavier_params(wl, 2).astype(np.float32).astype(np.float64)
