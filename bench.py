@@ -267,6 +267,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--workload", default="c2", help="c2 (default, the headline line) or c1/c3/c4 for profiling")
+    ap.add_argument("--prec", choices=("fp32", "bf16"), default=None,
+                    help="operand precision of the workload, for profiling (default: the workload's own)")
     ap.add_argument("--only-eval", action="store_true",
                     help="print only the evaluation throughput of the 1024^3 grid workload (profiling)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -283,6 +285,10 @@ def main():
         print(json.dumps({"eval_c5": eval_rate()}), flush=True)
         return
     wl = I.WORKLOADS[args.workload]
+    if args.prec:
+        prec = I.PREC_BF16 if args.prec == "bf16" else I.PREC_FP32
+        if prec != wl.prec:
+            wl = wl.replace(prec=prec, name=wl.name.rsplit("_", 1)[0] + "_" + args.prec)
     if args.calib_copy_mb:
         nbytes = args.calib_copy_mb << 20
         a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
