@@ -443,6 +443,11 @@ __device__ __forceinline__ void act_bwd_l1(float z, const L1Axes& f, float ab, c
 // (|c_5| <= 0.134, 6|c_6| <= 0.44), i.e. at most ~1e-7 of the residual once
 // E is divided by h^2.
 constexpr float kMicroX = 0.00390625f;   // 1/256
+// Operands rounded to BF16 for the next product (micro tier 2): the same
+// forms up to |p|, |p - e| <= 1/32, where the omitted terms (<= 4.1e-9 and
+// 1.4e-8) stay two orders of magnitude below the BF16 rounding of values of
+// the size of E there (2^-9 x^2 ~ 1.9e-6 at x = 1/32).
+constexpr float kMicroXBf16 = 0.03125f;  // 1/32
 struct Taylor { float a, c[8]; };   // c[1..K]
 
 template <int ACT, int K = 7>
@@ -566,18 +571,21 @@ __device__ __attribute__((noinline)) ActBwdOut act_bwd_general(float z, float p0
 
 // forward: base a, and per-axis D, E from (z, p, e).  One wave-uniform
 // branch takes the inline tiny-argument tier when every lane qualifies.
-template <int D>
+// MICRO: 0 = no micro tier, 1 = up to kMicroX, 2 = up to kMicroXBf16 (BF16
+// operand paths only)
+template <int D, int MICRO>
 __device__ __forceinline__ bool micro_args(const float* p, const float* e) {
+  constexpr float X = MICRO == 2 ? kMicroXBf16 : kMicroX;
   bool ok = true;
 #pragma unroll
-  for (int i = 0; i < D; ++i) ok = ok && fabsf(p[i]) <= kMicroX && fabsf(p[i] - e[i]) <= kMicroX;
+  for (int i = 0; i < D; ++i) ok = ok && fabsf(p[i]) <= X && fabsf(p[i] - e[i]) <= X;
   return ok;
 }
 
-template <int ACT, int D, bool MICRO = false>
+template <int ACT, int D, int MICRO = 0>
 __device__ __forceinline__ void act_fwd(float z, const float* p, const float* e, float& a,
                                         float* Dv, float* Ev) {
-  if (MICRO && __all(micro_args<D>(p, e))) {
+  if (MICRO > 0 && __all(micro_args<D, MICRO>(p, e))) {
     const Taylor T = taylor_at<ACT, 5>(z);
     a = T.a;
     taylor_fwd<D, 4>(T, p, e, Dv, Ev);
@@ -594,11 +602,11 @@ __device__ __forceinline__ void act_fwd(float z, const float* p, const float* e,
 }
 
 // backward: given stream adjoints (ab, Db, Eb) return (zb, pb, eb)
-template <int ACT, int D, bool MICRO = false>
+template <int ACT, int D, int MICRO = 0>
 __device__ __forceinline__ void act_bwd(float z, const float* p, const float* e, float ab,
                                         const float* Db, const float* Eb, float& zb, float* pb,
                                         float* eb) {
-  if (MICRO && __all(micro_args<D>(p, e))) {
+  if (MICRO > 0 && __all(micro_args<D, MICRO>(p, e))) {
     taylor_bwd<D, 5>(taylor_at<ACT, 5>(z), p, e, ab, Db, Eb, zb, pb, eb);
   } else if (__all(tiny_args<ACT, D>(p, e))) {
     taylor_bwd<D>(taylor_at<ACT>(z), p, e, ab, Db, Eb, zb, pb, eb);
@@ -636,11 +644,11 @@ __device__ __attribute__((noinline)) ActFBOut act_fb_general(float z, float p0, 
   return r;
 }
 
-template <int ACT, int D, bool MICRO = false>
+template <int ACT, int D, int MICRO = 0>
 __device__ __forceinline__ void act_fb(float z, const float* p, const float* e, float ab,
                                        const float* Db, const float* Eb, float& a, float* Dv,
                                        float* Ev, float& zb, float* pb, float* eb) {
-  if (MICRO && __all(micro_args<D>(p, e))) {
+  if (MICRO > 0 && __all(micro_args<D, MICRO>(p, e))) {
     const Taylor T = taylor_at<ACT, 5>(z);
     a = T.a;
     taylor_fwd<D, 4>(T, p, e, Dv, Ev);

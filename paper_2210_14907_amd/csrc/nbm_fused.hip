@@ -44,6 +44,8 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
   constexpr int NOB = W / 16;       // 16-neuron blocks; wave w owns block w
   constexpr int KC = W / 4;         // K chunk per lane group
   static_assert(NOB == 4, "one 16-neuron block per wave");
+  // hidden layers with BF16 operands take the micro forms up to 1/32
+  constexpr int kMicroL = PREC == 1 ? 2 : 0;
   __shared__ __attribute__((aligned(16))) T bufR[2][S][kTile][LD];      // row layout [c][n]
   // BF16 only: dZ also as [neuron][centre][stream (7 + zero)], the dW operand
   // (8 K values per lane = the streams of one centre); the odd centre stride
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
           float pp[3], ee[3], av, Dv[3], Ev[3];
           for (int a = 0; a < D; ++a) { pp[a] = acc[1 + a][j]; ee[a] = acc[1 + D + a][j]; }
           if (!last) {
-            act_fwd<ACT, D>(z, pp, ee, av, Dv, Ev);
+            act_fwd<ACT, D, kMicroL>(z, pp, ee, av, Dv, Ev);
             Z[l - 2][0][j] = z;
             for (int s = 1; s < S; ++s) Z[l - 2][s][j] = acc[s][j];
             bufR[cur ^ 1][0][c][n] = from_f<T>(av);
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
               ab = won * adjs[c][0];
               for (int a = 0; a < D; ++a) { Db[a] = won * adjs[c][1 + a]; Eb[a] = won * adjs[c][1 + D + a]; }
             }
-            act_fb<ACT, D>(z, pp, ee, ab, Db, Eb, av, Dv, Ev, zb, pb, eb);
+            act_fb<ACT, D, kMicroL>(z, pp, ee, ab, Db, Eb, av, Dv, Ev, zb, pb, eb);
             dz[0][j] = zb;
             for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
             // output layer, u = sum_n w_out[n] a_L[n] (+ b_out) per stream: the
@@ -337,7 +339,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
               zz = Z[l - 3][0][j];
               for (int a = 0; a < D; ++a) { pp[a] = Z[l - 3][1 + a][j]; ee[a] = Z[l - 3][1 + D + a][j]; }
             }
-            act_fb<ACT, D>(zz, pp, ee, acc[0][j], Db, Eb, av[0], Dv, Ev, zb, pb, eb);
+            act_fb<ACT, D, kMicroL>(zz, pp, ee, acc[0][j], Db, Eb, av[0], Dv, Ev, zb, pb, eb);
           } else {
             act_fb_l1_any<ACT, D>(l1m, z1[j], l1ax[n], acc[0][j], Db, Eb, av[0], Dv, Ev, zb, pb);
           }
