@@ -34,6 +34,8 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
   constexpr int LD = W + (PREC == 0 ? 4 : 8);
   constexpr int NW = W / 16;     // wavefronts; wave w owns neurons 16w .. 16w+15
   constexpr int KC = W / 4;
+  // micro forms of the hidden layers: up to 1/256, or 1/32 with BF16 operands
+  constexpr int kMicroW = PREC == 1 ? 2 : 1;
   __shared__ __attribute__((aligned(16))) T bufR[2][S][kTile][LD];
   // BF16 operands leave room in LDS for the first hidden layer's
   // pre-activations [stream][neuron][centre] (each lane reads back only what
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
             float z = acc[0][j] + bias;
             float pp[3], ee[3], av, Dv[3], Ev[3];
             for (int a = 0; a < D; ++a) { pp[a] = acc[1 + a][j]; ee[a] = acc[1 + D + a][j]; }
-            act_fwd<ACT, D, 1>(z, pp, ee, av, Dv, Ev);
+            act_fwd<ACT, D, kMicroW>(z, pp, ee, av, Dv, Ev);
             Z[l - 2][0][j] = z;
             for (int s = 1; s < S; ++s) Z[l - 2][s][j] = acc[s][j];
             vals[0][j] = av;
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
               ab = won * adjs[c][0];
               for (int a = 0; a < D; ++a) { Db[a] = won * adjs[c][1 + a]; Eb[a] = won * adjs[c][1 + D + a]; }
             }
-            act_fb<ACT, D, 1>(z, pp, ee, ab, Db, Eb, av, Dv, Ev, zb, pb, eb);
+            act_fb<ACT, D, kMicroW>(z, pp, ee, ab, Db, Eb, av, Dv, Ev, zb, pb, eb);
             dz[0][j] = zb;
             for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
             // output layer, u = sum_n w_out[n] a_L[n] (+ b_out) per stream: the
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           for (int a = 0; a < D; ++a) { Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j]; }
           if (l > 2) {
             for (int a = 0; a < D; ++a) { pp[a] = Z[l - 3][1 + a][j]; ee[a] = Z[l - 3][1 + D + a][j]; }
-            act_bwd<ACT, D, 1>(Z[l - 3][0][j], pp, ee, acc[0][j], Db, Eb, zb, pb, eb);
+            act_bwd<ACT, D, kMicroW>(Z[l - 3][0][j], pp, ee, acc[0][j], Db, Eb, zb, pb, eb);
             dz[0][j] = zb;
             for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
           } else {
