@@ -21,6 +21,7 @@ from __future__ import annotations
 import ctypes
 import hashlib
 import os
+import tempfile
 from pathlib import Path
 
 import numpy as np
@@ -340,7 +341,9 @@ class GridSystem:
 
 
 def cache_dir() -> Path:
-    p = Path(os.environ.get("NBM_ORACLE_CACHE", str(_HERE.parent / "_work" / "oracle_cache")))
+    """Directory of cached grid solutions: $NBM_ORACLE_CACHE, else a folder in
+    the system's temporary directory."""
+    p = Path(os.environ.get("NBM_ORACLE_CACHE", str(Path(tempfile.gettempdir()) / "nbm_oracle_cache")))
     p.mkdir(parents=True, exist_ok=True)
     return p
 
