@@ -2,18 +2,23 @@
 
 A step is one pass of the whole hot path over one batch of synthetic input:
 device sampling of the collocation points, classification, the difference-
-stream MLP forward on MFMA, the cut-cell residual and FP64 loss, the fused
-backward with FP64 gradient reduction, and Adam.  The batch is the 3-D sphere
-workload (65,536 interior + 1,536 boundary points, two 3->64x3->1 tanh nets,
-FP32 MFMA operands, h = 1/128, mu 1:10).  Inputs are resident in HBM before
-the timed region.  Prints one JSON line.
+stream MLP forward on MFMA, the cut-cell residual and FP64 loss, the
+backward with FP64 gradient reduction, and Adam.  The headline workload is
+the 3-D sphere problem with two 3->128x4->1 sine networks in BF16 MFMA
+operands (262,144 interior + 3,072 boundary points, h = 1/256, mu 1:10),
+measured next to its FP32-operand twin on the same points and parameters;
+both are trained for the configured 2,000 Adam steps and judged against the
+FP64 grid solution at 256^3.  Inputs are resident in HBM before the timed
+region.  Prints one JSON line on stdout (progress goes to stderr).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -22,176 +27,264 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp32": 157.3e12, "bf16": 2.5e15}
+HBM_PEAK = 8.0e12
 
-# sources the fused W=64 kernel is built from: the HBM traffic recorded in the
-# counter summary applies only while they are unchanged
-FUSED_SOURCES = ["nbm_fused.hip", "nbm_device.hpp", "nbm_internal.hpp", "nbm_launch.hpp"]
-COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "c2_k_fused_counters.md")
+# counter summaries (rocprofv3 FETCH_SIZE / WRITE_SIZE) per dominant kernel,
+# valid while the sources they were taken from are unchanged
+COUNTERS = {
+    "k_fused": ("c2_k_fused_counters.md", ["nbm_fused.hip", "nbm_device.hpp", "nbm_internal.hpp", "nbm_launch.hpp"]),
+    "k_wide_fb": ("c3_k_wide_fb_counters.md", ["nbm_wide.hip", "nbm_device.hpp", "nbm_internal.hpp", "nbm_launch.hpp"]),
+}
 
 
-def kernel_source_hash():
-    import hashlib
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash(files):
     hsh = hashlib.sha256()
-    for f in FUSED_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2210_14907_amd", "csrc", f), "rb") as fh:
             hsh.update(fh.read())
     return hsh.hexdigest()
 
 
-def recorded_traffic():
-    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+def recorded_traffic(kernel, prec_tag):
+    """HBM bytes per launch of a kernel from its committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources changed
     since those counters were taken (or no summary exists)."""
+    if kernel not in COUNTERS:
+        return None
+    summary, files = COUNTERS[kernel]
     try:
-        with open(COUNTER_SUMMARY) as fh:
+        with open(os.path.join(ROOT, "profiles", summary)) as fh:
             text = fh.read()
     except OSError:
         return None
     vals = {}
     for ln in text.splitlines():
         ln = ln.strip().lstrip("-").strip()
-        if ln.startswith(("sources_sha256:", "traffic_bytes_per_launch:")):
+        if ":" in ln:
             k, v = ln.split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("sources_sha256") != kernel_source_hash():
+    if vals.get("sources_sha256") != kernel_source_hash(files):
         return None
     try:
-        return int(vals["traffic_bytes_per_launch"])
+        return int(vals[f"traffic_bytes_per_launch_{prec_tag}"])
     except (KeyError, ValueError):
         return None
 
 
-def flops_per_centre(wl):
-    """Algorithmic FLOPs of evaluating one network on the 2d+1 stencil nodes
-    (forward) and of the backward, per the dense layer shapes."""
+def flops_per_point(wl):
+    """Algorithmic FLOPs per collocation point of evaluating one network on
+    the 2d+1 stencil nodes (forward) and of its backward, from the dense
+    layer shapes: forward 2S[(L-1)W^2 + dW + W], backward
+    2S[2(L-1)W^2 + dW + 2W], of which 2S(L-1)W^2 are the hidden weight
+    gradients."""
     S, W, L, d = wl.n_streams, wl.width, wl.depth, wl.dim
     fwd = 2 * S * ((L - 1) * W * W + d * W + W)
     bwd = 2 * S * (2 * (L - 1) * W * W + d * W + 2 * W)
-    return fwd, bwd, 2 * S * 2 * W * W   # last: one backward hidden-layer launch
+    dw = 2 * S * (L - 1) * W * W
+    return fwd, bwd, dw
 
 
-def run_workload(wl, steps, warmup, seed=1, timing=True, train_to=0):
+class Run:
+    """One workload on the device: parameters, optimiser state, a step
+    function, and the step counter."""
+
+    def __init__(self, wl, seed=1):
+        import torch
+        from paper_2210_14907_amd import NBM
+        from paper_2210_14907_amd.train import init_params
+        self.wl, self.seed = wl, seed
+        self.nbm = NBM(wl)
+        dev = self.nbm.device
+        self.params = init_params(wl, 0, dev)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.empty_like(self.params)
+        self.losses = torch.empty(wl.steps + 4096, dtype=torch.float64, device=dev)
+        self.step = 0
+
+    def one(self):
+        self.step += 1
+        k = self.step
+        pts, bpts = self.nbm.sample_points(self.seed, k)
+        self.nbm.forward_residual(self.params, pts, bpts, want_grad=True,
+                                  loss=self.losses[k:k + 1], grad=self.grad)
+        self.nbm.adam_step(self.params, self.m, self.v, self.grad, k, lr=self.wl.lr)
+
+    def train_to(self, steps):
+        import torch
+        while self.step < steps:
+            self.one()
+        torch.cuda.synchronize()
+        return float(self.losses[self.step].item())
+
+
+def measure(run, steps, warmup, timing=True):
+    """Timed steps: the whole step (sample + forward/residual/backward +
+    Adam), the fused forward/residual/backward call alone on one resident
+    batch, a per-step distribution, and per-kernel-group event times."""
     import torch
-    from paper_2210_14907_amd import NBM
-    from paper_2210_14907_amd.train import init_params
-
-    dev = torch.device("cuda:0")
-    nbm = NBM(wl)
-    params = init_params(wl, 0, dev)
-    m = torch.zeros_like(params)
-    v = torch.zeros_like(params)
-    grad = torch.empty_like(params)
-    losses = torch.empty(max(2 * steps + warmup + 64, train_to + 1) + 1, dtype=torch.float64, device=dev)
-    step = 0
-
-    def one(k):
-        pts, bpts = nbm.sample_points(seed, k)
-        nbm.forward_residual(params, pts, bpts, want_grad=True, loss=losses[k:k + 1], grad=grad)
-        nbm.adam_step(params, m, v, grad, k, lr=wl.lr)
-
+    nbm = run.nbm
     for _ in range(warmup):
-        step += 1
-        one(step)
+        run.one()
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     for _ in range(steps):
-        step += 1
-        one(step)
+        run.one()
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
-    # fwd + residual + bwd only, on one resident batch
-    pts, bpts = nbm.sample_points(seed, 10 ** 6)
+    pts, bpts = nbm.sample_points(run.seed, 10 ** 6)
+    lbuf = torch.empty(1, dtype=torch.float64, device=nbm.device)
+    gbuf = torch.empty_like(run.params)
     torch.cuda.synchronize()
     ev0.record()
     for _ in range(steps):
-        nbm.forward_residual(params, pts, bpts, want_grad=True, loss=losses[0:1], grad=grad)
+        nbm.forward_residual(run.params, pts, bpts, want_grad=True, loss=lbuf, grad=gbuf)
     ev1.record()
     torch.cuda.synchronize()
     ms_fb = ev0.elapsed_time(ev1) / steps
-    # per-step distribution: each step bracketed by its own events
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
     for k in range(steps):
-        step += 1
         evs[2 * k].record()
-        one(step)
+        run.one()
         evs[2 * k + 1].record()
     torch.cuda.synchronize()
     per = np.array([evs[2 * k].elapsed_time(evs[2 * k + 1]) for k in range(steps)])
     out = {"ms_per_step": ms, "ms_fwd_res_bwd": ms_fb,
            "step_ms_p10_p50_p90": [round(float(np.percentile(per, q)), 4) for q in (10, 50, 90)]}
     if timing:
-        counts = nbm.batch_counts().cpu().numpy()
         nbm.set_timing(True)
-        for _ in range(max(3, min(steps, 20))):
-            step += 1
-            one(step)
+        nt = max(3, min(steps, 20))
+        for _ in range(nt):
+            run.one()
         tm = nbm.read_timing()
         nbm.set_timing(False)
-        counts = nbm.batch_counts().cpu().numpy()
         out["timing"] = tm
-        out["counts"] = counts
-    if train_to > step:
-        while step < train_to:
-            step += 1
-            one(step)
-        torch.cuda.synchronize()
-    out["steps_trained"] = step
-    out["final_loss"] = float(losses[step].item())
-    out["params"] = params
-    out["nbm"] = nbm
+        out["timed_steps"] = nt
+        out["counts"] = nbm.batch_counts().cpu().numpy()
     return out
 
 
-def accuracy(wl, res, judge_n, judge=None):
-    """L-inf / L2 of the trained surrogate at the interior nodes of a judge
-    grid, against the closed-form solution and the FP64 grid CG oracle.
-    `judge` = (GridSystem, solution, seconds) reuses an earlier solve."""
-    import torch
-    from oracle import grid as OG
-
-    nbm, params = res["nbm"], res["params"]
-    if judge is None:
-        gs = OG.GridSystem(wl, judge_n)
-        t0 = time.time()
-        U = gs.solve()
-        t_judge = time.time() - t0
+def roofline(wl, meas):
+    """Dominant kernel of the step against its roofline.  Algorithmic FLOPs
+    per launch = FLOPs per point x (interior + boundary points) of the batch;
+    average launch time from HIP events on the library's stream."""
+    import nbm_inputs as I
+    fwd, bwd, dw = flops_per_point(wl)
+    tm, nt = meas["timing"], meas["timed_steps"]
+    pts = wl.n_points + wl.n_boundary
+    dtype = "fp32" if wl.prec == I.PREC_FP32 else "bf16"
+    b_ms, b_n = tm["backward"]
+    if wl.width == 128:
+        name = "k_wide_fb (forward, residual and the dA/dZ chain of every tile)"
+        kern, flop = "k_wide_fb", fwd + bwd - dw
+    elif wl.width == 64:
+        name = "k_fused (forward + residual + backward, all layers)"
+        kern, flop = "k_fused", fwd + bwd
     else:
-        gs, U, t_judge = judge
-    res["judge"] = (gs, U, t_judge)
+        name = "k_backward (layered)"
+        kern, flop = None, bwd
+    avg = b_ms / b_n
+    per_launch = flop * pts
+    achieved = per_launch / (avg * 1e-3)
+    out = {"bound": "mfma", "kernel": name, "achieved": achieved / 1e12, "peak": PEAK[dtype] / 1e12,
+           "unit": "TFLOP/s", "frac": achieved / PEAK[dtype],
+           "traffic": recorded_traffic(kern, dtype) if kern else None,
+           "flop_per_launch": per_launch, "flop_per_point": flop, "points_per_launch": pts,
+           "avg_launch_ms": avg, "launches_timed": b_n, "steps_timed": nt}
+    w_ms, w_n = tm.get("weight_grad", (0.0, 0))
+    if w_n:
+        # the weight-gradient pass of the 128-wide path: dW_l = dZ_l^T A_{l-1}
+        # per hidden layer, from the tile layout (BF16/FP32 A and dZ)
+        c = meas["counts"]
+        nbr = 2 * wl.dim if wl.mu_minus != wl.mu_plus else 0
+        centres = int(c[0] + c[1] + (2 + nbr) * c[2] + c[3] + c[4])
+        opb = 2 if wl.prec == I.PREC_BF16 else 4
+        moved = 2 * centres * wl.n_streams * wl.width * opb   # A and dZ of one layer
+        avg_w = w_ms / w_n
+        out["weight_grad_pass"] = {
+            "kernel": "k_wide_dw (one launch per hidden layer)", "avg_launch_ms": avg_w,
+            "launches_per_step": w_n / nt,
+            "mfma_tflops": dw / (wl.depth - 1) * pts / (avg_w * 1e-3) / 1e12,
+            "operand_bytes_per_launch": moved, "operand_gbps": moved / (avg_w * 1e-3) / 1e9,
+            "hbm_frac": moved / (avg_w * 1e-3) / HBM_PEAK}
+    return out
+
+
+def summary(wl, meas):
+    n = wl.n_points
+    tm, nt = meas["timing"], meas["timed_steps"]
+    return {"pts_per_s": round(n / (meas["ms_per_step"] * 1e-3), 1),
+            "ms_per_step": round(meas["ms_per_step"], 4),
+            "fwd_res_bwd_pts_per_s": round(n / (meas["ms_fwd_res_bwd"] * 1e-3), 1),
+            "ms_fwd_res_bwd": round(meas["ms_fwd_res_bwd"], 4),
+            "step_ms_p10_p50_p90": meas["step_ms_p10_p50_p90"],
+            "kernel_ms_per_step": {k: round(v[0] / nt, 4) for k, v in tm.items() if v[1]}}
+
+
+def judge_accuracy(run, gs, U):
+    """L-inf / L2 of the trained surrogate at the interior nodes of the judge
+    grid, against the FP64 grid solution and (manufactured problems) the
+    closed form."""
+    import torch
+    nbm, params = run.nbm, run.params
     xin = gs.x[gs.interior]
-    q = torch.tensor(xin, dtype=torch.float32, device=nbm.device)
-    u = np.concatenate([nbm.eval(params, q[i:i + 60000]).cpu().numpy() for i in range(0, len(q), 60000)])
-    out = {"judge_n": judge_n, "judge_seconds": round(t_judge, 2)}
+    cap = int(nbm.cfg.max_points)
+    u = np.empty(xin.shape[0])
+    for i in range(0, xin.shape[0], cap):
+        q = torch.tensor(xin[i:i + cap], dtype=torch.float32, device=nbm.device)
+        u[i:i + cap] = nbm.eval(params, q).cpu().numpy()
     e = u - U[gs.interior]
-    out["linf_vs_grid"] = float(np.abs(e).max())
-    out["l2_vs_grid"] = float(np.sqrt(np.mean(e * e)))
+    out = {"linf_vs_grid": float(np.abs(e).max()), "l2_vs_grid": float(np.sqrt(np.mean(e * e)))}
     if gs.prob.has_exact():
         ex = gs.prob.u_exact(xin)
         out["linf_vs_exact"] = float(np.abs(u - ex).max())
         out["l2_vs_exact"] = float(np.sqrt(np.mean((u - ex) ** 2)))
-        out["grid_linf_vs_exact"] = float(np.abs(U[gs.interior] - ex).max())
     return out
+
+
+class Judge(threading.Thread):
+    """FP64 grid solution of a workload (oracle), solved on the host while the
+    device trains (nothing timed runs meanwhile)."""
+
+    def __init__(self, wl, n):
+        super().__init__(daemon=True)
+        self.wl, self.n = wl, n
+        self.result, self.error = None, None
+
+    def run(self):
+        try:
+            from oracle import grid as OG
+            t0 = time.time()
+            gs = OG.GridSystem(self.wl, self.n)
+            U = gs.solve()
+            self.result = (gs, U, time.time() - t0)
+        except Exception as e:   # reported in the line, never swallowed silently
+            self.error = repr(e)
 
 
 def cpu_baseline(wl, target_s=12.0):
     """The FP64 oracle's step (point evaluation + reverse mode) on a bounded
     sample of the same workload, timed on the host cores: batches of up to
     the workload's size, repeated until about target_s seconds of work."""
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     import nbm_inputs as I
     from oracle import nbm as ON
 
     theta = I.xavier_params(wl, 0)
-    n0 = 2048
+    n0 = 1024
     pts, bpts = I.collocation_batch(wl, n0, max(1, int(round(n0 * wl.dim * wl.h))), seed=11)
     t = time.time()
     ON.loss_and_grad(wl, theta, pts, bpts)
     rate0 = n0 / (time.time() - t)
     n = int(min(wl.n_points, max(n0, rate0 * target_s)))
-    nb = int(round(n * wl.dim * wl.h))
+    nb = max(1, int(round(n * wl.dim * wl.h)))
     reps = max(1, min(64, int(target_s * rate0 / n)))
     dt, done = 0.0, 0
     for k in range(reps):
@@ -203,10 +296,8 @@ def cpu_baseline(wl, target_s=12.0):
         if dt >= target_s:
             break
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    # one thread, on a smaller batch
-    from threadpoolctl import threadpool_limits
-    n1 = 4096
-    pts1, bpts1 = I.collocation_batch(wl, n1, int(round(n1 * wl.dim * wl.h)), seed=40)
+    n1 = 2048
+    pts1, bpts1 = I.collocation_batch(wl, n1, max(1, int(round(n1 * wl.dim * wl.h))), seed=40)
     with threadpool_limits(limits=1):
         t = time.time()
         ON.loss_and_grad(wl, theta, pts1, bpts1)
@@ -266,17 +357,18 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--workload", default="c2", help="c2 (default, the headline line) or c1/c3/c4 for profiling")
+    ap.add_argument("--workload", default="c3", help="c3 (default, the headline line), or c1/c2/c4 for profiling")
     ap.add_argument("--prec", choices=("fp32", "bf16"), default=None,
                     help="operand precision of the workload, for profiling (default: the workload's own)")
+    ap.add_argument("--judge-n", type=int, default=0, help="grid judge intervals per axis (default: the workload's)")
     ap.add_argument("--only-eval", action="store_true",
                     help="print only the evaluation throughput of the 1024^3 grid workload (profiling)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU (data-parallel) path.",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: every box this library runs on here has one GPU, "
+              "and the library has no multi-GPU (data-parallel) path.", file=sys.stderr)
         sys.exit(2)
     import torch
     import nbm_inputs as I
@@ -297,27 +389,21 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    res = run_workload(wl, args.steps, args.warmup, train_to=0 if args.no_accuracy else wl.steps)
-    n_step = wl.n_points
-    value = n_step / (res["ms_per_step"] * 1e-3)
-    fwd_f, bwd_f, bl_f = flops_per_centre(wl)
-    tm = res["timing"]
-    c = res["counts"]
-    nbr = 2 * wl.dim if wl.mu_minus != wl.mu_plus else 0
-    centres = int(c[0] + c[1] + (2 + nbr) * c[2] + c[3] + c[4])
-    f_ms, f_n = tm["forward"]
-    b_ms, b_n = tm["backward"]
-    if wl.width == 64:
-        # one launch per step runs the forward, residual and backward of every
-        # tile on chip; it is the dominant kernel
-        name, per_launch, avg = ("k_fused (forward + residual + backward, all layers)",
-                                 (fwd_f + bwd_f) * centres, b_ms / b_n)
-    elif b_ms >= f_ms:
-        name, per_launch, avg = "backward group", bwd_f * centres, b_ms / b_n
-    else:
-        name, per_launch, avg = "k_forward (all layers)", fwd_f * centres, f_ms / f_n
-    dtype = "fp32" if wl.prec == I.PREC_FP32 else "bf16"
-    achieved = per_launch / (avg * 1e-3)
+    twin_prec = I.PREC_FP32 if wl.prec == I.PREC_BF16 else I.PREC_BF16
+    twin_tag = "fp32" if twin_prec == I.PREC_FP32 else "bf16"
+    wl_twin = wl.replace(prec=twin_prec, name=wl.name.rsplit("_", 1)[0] + "_" + twin_tag)
+
+    log(f"timing {wl.name}")
+    main_run = Run(wl)
+    meas = measure(main_run, args.steps, args.warmup)
+    twin_run, twin_meas = None, None
+    if not args.no_extra or not args.no_accuracy:
+        log(f"timing {wl_twin.name}")
+        twin_run = Run(wl_twin)
+        twin_meas = measure(twin_run, max(10, args.steps // 2), 3)
+    value = wl.n_points / (meas["ms_per_step"] * 1e-3)
+    dtype = "f32" if wl.prec == I.PREC_FP32 else "bf16"
+    net = f"2 x {wl.dim}->{wl.width}x{wl.depth}->1 {'tanh' if wl.act == I.ACT_TANH else 'sin'}"
     line = {
         "metric": "colloc pts/s (fwd+FV residual+bwd), BF16 vs FP32, at stated Linf vs FP64 oracle",
         "value": round(value, 1),
@@ -325,52 +411,72 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(res["ms_per_step"], 4),
-        "step_ms_p10_p50_p90": res["step_ms_p10_p50_p90"],
+        "ms_per_step": round(meas["ms_per_step"], 4),
+        "step_ms_p10_p50_p90": meas["step_ms_p10_p50_p90"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if wl.prec == I.PREC_FP32 else "bf16",
-        "data": "synthetic (Philox lattice points, manufactured sphere solution, Xavier init seed 0)",
+        "dtype": dtype,
+        "data": "synthetic (Philox lattice points, seeded problem data, Xavier init seed 0)",
         "config": {"workload": wl.name, "n_points": wl.n_points, "n_boundary": wl.n_boundary,
-                   "h": wl.h, "net": f"2 x {wl.dim}->{wl.width}x{wl.depth}->1 {'tanh' if wl.act == I.ACT_TANH else 'sin'}",
-                   "mu": [wl.mu_minus, wl.mu_plus]},
-        "fwd_res_bwd_pts_per_s": round(n_step / (res["ms_fwd_res_bwd"] * 1e-3), 1),
-        "kernel_ms_per_step": {k: round(v[0] / max(1, tm["forward"][1]), 4) for k, v in tm.items() if v[1]},
-        "roofline": {"bound": "mfma", "kernel": name, "achieved": achieved / 1e12,
-                     "peak": PEAK[dtype] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[dtype],
-                     "traffic": recorded_traffic() if wl.width == 64 and wl.prec == I.PREC_FP32 else None,
-                     "flop_per_launch": per_launch, "avg_launch_ms": avg},
+                   "h": wl.h, "net": net, "mu": [wl.mu_minus, wl.mu_plus],
+                   "operands": "BF16 MFMA, FP32 accumulate" if wl.prec == I.PREC_BF16 else "FP32 MFMA"},
+        "value_is": "interior collocation points per second of the whole training step (sampling, "
+                    "classification, forward streams, residual, FP64 loss, backward, FP64 gradient "
+                    "reduction, Adam); fwd_res_bwd_pts_per_s is the forward+residual+backward call alone",
+        "fwd_res_bwd_pts_per_s": round(wl.n_points / (meas["ms_fwd_res_bwd"] * 1e-3), 1),
+        "kernel_ms_per_step": summary(wl, meas)["kernel_ms_per_step"],
+        "roofline": roofline(wl, meas),
     }
-    if not args.no_accuracy and wl.problem != I.PROB_FOURIER:
-        acc = accuracy(wl, res, 64)
-        acc["steps_trained"] = res["steps_trained"]
-        acc["final_loss"] = res["final_loss"]
-        line["accuracy"] = acc
-        if wl.prec == I.PREC_FP32:
-            # the same training in BF16 operands, judged on the same grid solution
-            wb = wl.replace(prec=I.PREC_BF16)
-            rb = run_workload(wb, 10, 3, timing=False, train_to=wb.steps)
-            ab = accuracy(wb, rb, 64, judge=res["judge"])
-            ab["steps_trained"] = rb["steps_trained"]
-            ab["final_loss"] = rb["final_loss"]
-            ab["linf_ratio_bf16_over_fp32"] = ab["linf_vs_grid"] / acc["linf_vs_grid"]
-            line["accuracy_bf16"] = ab
-            del rb
-            torch.cuda.empty_cache()
+    if twin_meas is not None:
+        tw = summary(wl_twin, twin_meas)
+        tw["roofline"] = roofline(wl_twin, twin_meas)
+        line[f"twin_{twin_tag}"] = {"workload": wl_twin.name, **tw}
+        bf, fp = (meas, twin_meas) if wl.prec == I.PREC_BF16 else (twin_meas, meas)
+        line["speedup_bf16_over_fp32"] = round(fp["ms_per_step"] / bf["ms_per_step"], 3)
     if not args.no_extra:
         extra = {}
-        for tag, w in (("c2_bf16", wl.replace(prec=I.PREC_BF16)), ("c3_bf16", I.C3),
-                       ("c3_fp32", I.C3.replace(prec=I.PREC_FP32)), ("c4_bf16", I.C4)):
-            r = run_workload(w, max(10, args.steps // 2), 3, timing=False)
-            extra[tag] = {"pts_per_s": round(w.n_points / (r["ms_per_step"] * 1e-3), 1),
-                          "fwd_res_bwd_pts_per_s": round(w.n_points / (r["ms_fwd_res_bwd"] * 1e-3), 1),
-                          "ms_per_step": round(r["ms_per_step"], 4)}
+        for tag, w in (("c2_fp32", I.C2), ("c2_bf16", I.C2.replace(prec=I.PREC_BF16)), ("c4_bf16", I.C4)):
+            if w.name == wl.name:
+                continue
+            log(f"timing {tag}")
+            r = Run(w)
+            mm = measure(r, max(10, args.steps // 2), 3)
+            extra[tag] = summary(w, mm)
+            extra[tag]["roofline"] = roofline(w, mm)
             del r
             torch.cuda.empty_cache()
-        line["same_step_other_precisions"] = extra
+        line["other_workloads"] = extra
+        log("timing the 1024^3 evaluation")
         line["eval_c5"] = eval_rate()
+    if not args.no_accuracy and wl.problem != I.PROB_FOURIER:
+        judge_n = args.judge_n or wl.judge_n
+        log(f"FP64 grid judge at {judge_n}^{wl.dim} on the host while both forms train {wl.steps} steps")
+        judge = Judge(wl, judge_n)
+        judge.start()
+        acc = {"judge_n": judge_n, "steps_trained": wl.steps}
+        for tag, r in ((dtype if dtype == "bf16" else "fp32", main_run), (twin_tag, twin_run)):
+            acc[f"final_loss_{tag}"] = r.train_to(wl.steps)
+            log(f"trained {r.wl.name} to step {r.step}")
+        judge.join()
+        if judge.error:
+            acc["judge_error"] = judge.error
+        else:
+            gs, U, t_judge = judge.result
+            acc["judge_seconds"] = round(t_judge, 1)
+            acc["judge_picard_iterations"] = gs.picard_iters
+            if gs.prob.has_exact():
+                ex = gs.prob.u_exact(gs.x[gs.interior])
+                acc["grid_linf_vs_exact"] = float(np.abs(U[gs.interior] - ex).max())
+            for tag, r in ((dtype if dtype == "bf16" else "fp32", main_run), (twin_tag, twin_run)):
+                acc[tag] = judge_accuracy(r, gs, U)
+            if "bf16" in acc and "fp32" in acc:
+                acc["linf_ratio_bf16_over_fp32"] = acc["bf16"]["linf_vs_grid"] / acc["fp32"]["linf_vs_grid"]
+                acc["target_ratio_max"] = 1.5
+            del gs, U
+        line["accuracy"] = acc
     if not args.no_cpu:
+        log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)
 

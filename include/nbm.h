@@ -100,11 +100,15 @@ void nbm_destroy(nbm_ctx* ctx);
 /* Number of FP32 parameters (both networks). */
 int64_t nbm_param_count(const nbm_ctx* ctx);
 
-/* Device workspace bytes needed for batches up to (max_points, max_boundary)
- * and for nbm_eval tiles up to max_points queries. */
-size_t nbm_workspace_bytes(const nbm_ctx* ctx);
+/* Device workspace bytes a call needs for a batch of n interior and nb
+ * boundary points (nbm_forward_residual, nbm_backward), or for n queries
+ * (nbm_eval, nb = 0).  A workspace sized for (n, nb) serves every smaller
+ * batch.  Returns 0 if n > max_points, nb > max_boundary or either is
+ * negative.  The caller allocates it (256-byte aligned) and owns it. */
+size_t nbm_workspace_bytes(const nbm_ctx* ctx, int64_t n, int64_t nb);
 
-/* Copy the problem tables (Fourier modes) into the workspace.  Must be called
+/* Copy the problem tables (Fourier modes) into the front of the workspace
+ * (the part whose offsets do not depend on the batch size).  Must be called
  * once for each workspace before the other workspace-using calls; blocks the
  * host until the copy is done. */
 int nbm_prepare(nbm_ctx* ctx, void* stream, void* ws, size_t ws_bytes);
@@ -157,13 +161,18 @@ int nbm_batch_counts(nbm_ctx* ctx, void* stream, int32_t* counts, void* ws, size
 /* Measurement support.  With timing enabled, every later call records a
  * pair of HIP events on its stream around each kernel group:
  * 0 shadow+classify+compact, 1 forward streams, 2 residual+loss,
- * 3 backward (one pair per hidden-layer launch), 4 gradient reduction,
- * 5 Adam, 6 sampling, 7 evaluation.  Costs a little host time per call. */
+ * 3 backward (the fused forward/residual/backward launch, or one pair per
+ * hidden-layer launch of the layered path), 4 gradient reduction, 5 Adam,
+ * 6 sampling, 7 evaluation, 8 weight-gradient launches of the 128-wide
+ * two-pass backward (one pair per hidden layer), 9 Fourier forcing.
+ * Costs a little host time per call. */
+#define NBM_TIMING_GROUPS 10
 int nbm_set_timing(nbm_ctx* ctx, int enable);
 
 /* Wait for the recorded events, write per group the summed milliseconds
- * ms[8] and the number of timed launches launches[8] (host arrays), then
- * forget the records.  Blocks the host. */
+ * ms[NBM_TIMING_GROUPS] and the number of timed launches
+ * launches[NBM_TIMING_GROUPS] (host arrays), then forget the records.
+ * Blocks the host. */
 int nbm_read_timing(nbm_ctx* ctx, double* ms, int64_t* launches);
 
 /* Thread-local description of the last error. */

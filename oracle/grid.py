@@ -80,6 +80,10 @@ def apply_A(d, n, cface, u):
     return y
 
 
+class PicardNotConverged(RuntimeError):
+    """The lagged low-mu gradient iteration missed its tolerance."""
+
+
 class GridSystem:
     """Assembled grid rows for one workload at n intervals per axis.
 
@@ -271,10 +275,14 @@ class GridSystem:
         return gr
 
     def solve(self, tol=1e-12, picard_tol=1e-10, max_picard=60, precond="mg", verbose=False,
-              glo_fn=None):
+              glo_fn=None, require_converged=True):
         """Solve the grid system.  With a contrast, the lagged low-mu gradients
         are found by the Picard iteration, unless glo_fn(y[..., d]) supplies
-        them directly (used by the patch test with the exact low-side field)."""
+        them directly (used by the patch test with the exact low-side field).
+        self.converged records whether the iteration met picard_tol within
+        max_picard iterations; if it did not, PicardNotConverged is raised
+        unless require_converged is False (an unconverged solution must never
+        stand in for the judge)."""
         d, n = self.d, self.n
         contrast = S.lo_side(self.wl) >= 0
         ncut_nodes = (self.cut.size, 2 * d + 1, d)
@@ -286,7 +294,10 @@ class GridSystem:
         U, it, rr = pcg(d, n, self.cface, b, tol=tol, precond=precond)
         self.pcg_iters = [it]
         self.picard_iters = 0
+        self.picard_dU = 0.0
+        self.converged = True
         if contrast and glo_fn is None:
+            self.converged = False
             # Anderson-accelerated fixed point on the lagged gradients
             hist_x, hist_f = [], []
             x = glo.ravel()
@@ -316,10 +327,16 @@ class GridSystem:
                 dU = np.abs(U - U_old).max()
                 if verbose:
                     print(f"picard {k}: max|dU| = {dU:.3e}, pcg {it}")
+                self.picard_dU = dU
                 if dU <= picard_tol * max(1.0, np.abs(U).max()):
+                    self.converged = True
                     break
         self.U = U
         self.relres = rr
+        if require_converged and not self.converged:
+            raise PicardNotConverged(
+                f"Picard iteration: max|dU| = {self.picard_dU:.3e} after {self.picard_iters} "
+                f"iterations (tolerance {picard_tol:.1e} relative)")
         return self.full_values(U)
 
     def row_residual(self, Ufull):
@@ -352,7 +369,8 @@ def solve_cached(wl: I.Workload, n: int, verbose=False):
     """Grid solution (full nodal array) for workload wl at n intervals, cached
     on disk by a hash of the problem-defining fields."""
     key = repr((wl.dim, wl.interface, wl.radius, wl.star_amp, wl.mu_minus, wl.mu_plus, wl.problem,
-                wl.alpha_const, wl.beta_const, wl.fourier_seed, wl.fourier_kmax, n, "v1"))
+                wl.alpha_const, wl.beta_const, wl.fourier_seed, wl.fourier_kmax, tuple(wl.plane_n),
+                wl.plane_c, tuple(wl.lin_a), tuple(wl.lin_b), n, "v2"))
     hsh = hashlib.sha1(key.encode()).hexdigest()[:16]
     f = cache_dir() / f"grid_{hsh}.npy"
     if f.exists():

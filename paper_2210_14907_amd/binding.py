@@ -55,7 +55,7 @@ def lib():
         L.nbm_destroy.restype = None
         L.nbm_param_count.argtypes = [vp]
         L.nbm_param_count.restype = i64
-        L.nbm_workspace_bytes.argtypes = [vp]
+        L.nbm_workspace_bytes.argtypes = [vp, i64, i64]
         L.nbm_workspace_bytes.restype = ctypes.c_size_t
         L.nbm_prepare.argtypes = [vp, vp, vp, ctypes.c_size_t]
         L.nbm_sample_points.argtypes = [vp, vp, ctypes.c_uint64, i64, vp, i64, vp, i64]
@@ -122,7 +122,9 @@ class NBM:
         _check(lib().nbm_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.ctx = h
         self.P = lib().nbm_param_count(h)
-        self.ws_bytes = lib().nbm_workspace_bytes(h)
+        self.ws_bytes = lib().nbm_workspace_bytes(h, cfg.max_points, 0 if eval_only else cfg.max_boundary)
+        if self.ws_bytes == 0:
+            raise NbmError("nbm_workspace_bytes rejected the batch capacity")
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.ws.data_ptr()) % 256
         self.ws_view = self.ws[off:off + self.ws_bytes]
@@ -191,15 +193,17 @@ class NBM:
                                   _ptr(o), _ptr(self.ws_view), self.ws_bytes))
         return out
 
-    TIMING_GROUPS = ["prep", "forward", "residual", "backward", "reduce", "adam", "sample", "eval"]
+    TIMING_GROUPS = ["prep", "forward", "residual", "backward", "reduce", "adam", "sample", "eval",
+                     "weight_grad", "forcing"]
 
     def set_timing(self, enable: bool):
         _check(lib().nbm_set_timing(self.ctx, 1 if enable else 0))
 
     def read_timing(self):
         """{group: (total ms, launches)} since the last read (blocks the host)."""
-        ms = (ctypes.c_double * 8)()
-        n = (ctypes.c_int64 * 8)()
+        ng = len(self.TIMING_GROUPS)
+        ms = (ctypes.c_double * ng)()
+        n = (ctypes.c_int64 * ng)()
         _check(lib().nbm_read_timing(self.ctx, ms, n))
         return {g: (ms[i], n[i]) for i, g in enumerate(self.TIMING_GROUPS)}
 

@@ -29,9 +29,18 @@ static int fail(int code, const std::string& msg) {
   } while (0)
 
 namespace {
+// Byte offsets of one call's workspace regions, for a batch of up to n
+// interior and nb boundary points (or n queries).  The Fourier tables and the
+// batch bookkeeping come first, at offsets that do not depend on the batch
+// size (nbm_prepare fills the tables once; nbm_batch_counts reads the
+// bookkeeping of the last call).
 struct Layout {
-  size_t modes32, modes64, fmodes, meta, ctot, coff, blockcnt, off, blockcnt_b, off_b, cls, rank, bcls, brank, cutidx,
-      centres, src, outputs, adj, Zst, Ast, ALst, dZ, dZw, shadow, partial, lossp, resid, lossbuf, fpre, fslot, total;
+  size_t modes32, modes64, fmodes, meta, prefix, ctot, coff, blockcnt, off, blockcnt_b, off_b, cls, rank, bcls,
+      brank, cutidx, centres, src, outputs, adj, Zst, Ast, ALst, dZ, dZw, shadow, partial, lossp, resid, lossbuf,
+      fpre, fslot, total;
+  int64_t nchunk;    // interior chunks of the two-level scan
+  int64_t cut_cap;   // cut cells this call can hold
+  int64_t lstride;   // elements of one layer in the tile layout
 };
 }  // namespace
 
@@ -56,11 +65,10 @@ struct nbm_ctx {
   int D, W, L, S, opbytes;
   int64_t per_net, Ptot;
   NetLayout lay;
-  int64_t cap_n, cap_nb, cut_cap, cap_slots, cap_tiles, lstride;
-  int64_t nchunk;   // interior chunks of the two-level scan at capacity
+  int64_t cap_n, cap_nb, cut_cap;   // largest batch (max_points, max_boundary) and cut capacity
   int G, Gf, Gfz;
   bool no_fused;
-  Layout lo;
+  Layout lo;        // layout at the largest batch (its prefix is shared by every call)
   void* prepared_ws;
   bool eval_only;
 };
@@ -87,23 +95,38 @@ struct Timer {
   }
 };
 
+struct WideTimers {
+  nbm_ctx* c;
+  hipStream_t st;
+  Timer* fb;
+  Timer* dw;
+};
+
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static void make_layout(nbm_ctx* c) {
-  Layout& L = c->lo;
+static Layout layout_for(const nbm_ctx* c, int64_t n, int64_t nb) {
+  Layout L;
   size_t o = 0;
   const bool ev = c->eval_only;
+  if (n < 1) n = 1;
+  if (ev) nb = 0;
   // evaluation-only workspaces keep just the classification, centre lists,
   // outputs and operand shadows
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
   auto take_tr = [&](size_t bytes) { return take(ev ? 0 : bytes); };
-  int64_t nblk = (c->cap_n + 255) / 256 + 1, nblkb = (c->cap_nb + 255) / 256 + 1;
-  int64_t nblkc = (c->cut_cap + 255) / 256 + 1;
-  c->nchunk = scan_chunks(nblk);
+  const int64_t cut = ev ? 0 : std::min<int64_t>(c->cut_cap, n);
+  const int nbr = c->P.lo >= 0 ? 2 * c->D : 0;
+  const int64_t tiles = (n + (2 + nbr) * cut + nb + 2 * kTile + kTile - 1) / kTile + 2;
+  const int64_t slots = tiles * kTile;
+  L.cut_cap = cut;
+  L.lstride = tiles * (int64_t)c->S * c->W * kTile;
+  int64_t nblk = (n + 255) / 256 + 1, nblkb = (nb + 255) / 256 + 1;
+  L.nchunk = scan_chunks(nblk);
   L.modes32 = take(sizeof(float) * 8 * (c->cfg.n_modes + 1));
   L.modes64 = take(sizeof(double) * 5 * (c->cfg.n_modes + 1));
   L.fmodes = take(sizeof(FMode) * (c->fmodes.size() + 1));
   L.meta = take(sizeof(Meta));
+  L.prefix = o;
   // chunk totals and offsets of the two-level scan: interior chunks, then
   // boundary chunks at a fixed offset
   L.ctot = take(sizeof(int) * 4 * (scan_chunks(nblk) + scan_chunks(nblkb)));
@@ -112,34 +135,35 @@ static void make_layout(nbm_ctx* c) {
   L.off = take(sizeof(int) * 4 * nblk);
   L.blockcnt_b = take(sizeof(int) * 4 * nblkb);
   L.off_b = take(sizeof(int) * 4 * nblkb);
-  L.cls = take(sizeof(int) * c->cap_n);
-  L.rank = take(sizeof(int) * c->cap_n);
-  L.bcls = take(sizeof(int) * c->cap_nb);
-  L.brank = take(sizeof(int) * c->cap_nb);
-  L.cutidx = take(sizeof(int) * c->cut_cap);
-  L.centres = take(sizeof(float) * 4 * c->cap_slots);
-  L.src = take(sizeof(int) * c->cap_slots);
-  L.outputs = take(sizeof(float) * 8 * c->cap_slots);
-  L.adj = take_tr(sizeof(float) * 8 * c->cap_slots);
+  L.cls = take(sizeof(int) * n);
+  L.rank = take(sizeof(int) * n);
+  L.bcls = take(sizeof(int) * nb);
+  L.brank = take(sizeof(int) * nb);
+  L.cutidx = take(sizeof(int) * cut);
+  L.centres = take(sizeof(float) * 4 * slots);
+  L.src = take(sizeof(int) * slots);
+  L.outputs = take(sizeof(float) * 8 * slots);
+  L.adj = take_tr(sizeof(float) * 8 * slots);
   // stored pre-activations are needed only by the layered backward, used when
   // no fused path is compiled for the shape (or NBM_NO_FUSED is set)
   const bool layered = c->no_fused || (!c->fused && !c->wide);
-  L.Zst = take_tr(layered ? sizeof(float) * c->L * c->lstride : 0);
-  L.Ast = take_tr((size_t)c->opbytes * (c->L - 1) * c->lstride);
-  L.ALst = take_tr(layered ? sizeof(float) * c->lstride : 0);
-  L.dZ = take_tr(layered ? sizeof(float) * c->lstride : 0);
-  L.dZw = take_tr(c->wide && !c->no_fused ? (size_t)c->opbytes * (c->L - 1) * c->lstride : 0);
+  L.Zst = take_tr(layered ? sizeof(float) * c->L * L.lstride : 0);
+  L.Ast = take_tr((size_t)c->opbytes * (c->L - 1) * L.lstride);
+  L.ALst = take_tr(layered ? sizeof(float) * L.lstride : 0);
+  L.dZ = take_tr(layered ? sizeof(float) * L.lstride : 0);
+  L.dZw = take_tr(c->wide && !c->no_fused ? (size_t)c->opbytes * (c->L - 1) * L.lstride : 0);
   L.shadow = take((size_t)c->opbytes * 2 * (c->L - 1) * 2 * c->W * c->W);
   L.partial = take_tr(sizeof(float) * (size_t)c->G * c->Ptot);
-  L.lossp = take(sizeof(double) * (nblk + nblkb + c->cut_cap + 4 + 512));
-  L.resid = take_tr(sizeof(float) * (c->cap_n + c->cap_nb));
+  L.lossp = take(sizeof(double) * (nblk + nblkb + cut + 4 + 512));
+  L.resid = take_tr(sizeof(float) * (n + nb));
   L.lossbuf = take(sizeof(double) * 4);
-  L.fpre = take_tr(c->cfg.problem == NBM_PROB_FOURIER ? sizeof(float) * c->cap_n : 0);
+  L.fpre = take_tr(c->cfg.problem == NBM_PROB_FOURIER ? sizeof(float) * n : 0);
   // forcing of the uncut centres in centre-slot order, for the fused paths'
   // inline tiles
   const bool fused_path = !c->no_fused && (c->fused || c->wide) && !c->eval_only;
-  L.fslot = take_tr(fused_path ? sizeof(float) * c->cap_slots : 0);
+  L.fslot = take_tr(fused_path ? sizeof(float) * slots : 0);
   L.total = o;
+  return L;
 }
 
 extern "C" const char* nbm_last_error(void) { return g_err.c_str(); }
@@ -269,16 +293,11 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
   x->cut_cap = c.cut_capacity > 0 ? c.cut_capacity : c.max_points / 8 + 64;
   if (x->cut_cap > x->cap_n) x->cut_cap = x->cap_n;
   if (x->eval_only) { x->cut_cap = 0; x->cap_nb = 0; }
-  int nbr = P.lo >= 0 ? 2 * c.dim : 0;
-  x->cap_slots = x->cap_n + (2 + nbr) * x->cut_cap + x->cap_nb + 2 * kTile;
-  x->cap_tiles = (x->cap_slots + kTile - 1) / kTile + 2;
-  x->cap_slots = x->cap_tiles * kTile;
-  x->lstride = x->cap_tiles * (int64_t)x->S * x->W * kTile;
   x->G = 512;
   x->Gf = 256;
   x->Gfz = 512;   // two fused work-groups per compute unit
   x->prepared_ws = nullptr;
-  make_layout(x);
+  x->lo = layout_for(x, x->cap_n, x->cap_nb);
   *out = x;
   return NBM_OK;
 }
@@ -298,7 +317,7 @@ extern "C" int nbm_set_timing(nbm_ctx* ctx, int enable) {
 
 extern "C" int nbm_read_timing(nbm_ctx* ctx, double* ms, int64_t* launches) {
   if (!ctx || !ms || !launches) return fail(NBM_EINVAL, "null argument");
-  for (int g = 0; g < 8; ++g) { ms[g] = 0.0; launches[g] = 0; }
+  for (int g = 0; g < NBM_TIMING_GROUPS; ++g) { ms[g] = 0.0; launches[g] = 0; }
   for (auto& t : ctx->timed) {
     HIPCHK(hipEventSynchronize(t.b));
     float v = 0.f;
@@ -314,16 +333,19 @@ extern "C" int nbm_read_timing(nbm_ctx* ctx, double* ms, int64_t* launches) {
 
 extern "C" int64_t nbm_param_count(const nbm_ctx* ctx) { return ctx ? ctx->Ptot : -1; }
 
-extern "C" size_t nbm_workspace_bytes(const nbm_ctx* ctx) { return ctx ? ctx->lo.total : 0; }
+extern "C" size_t nbm_workspace_bytes(const nbm_ctx* ctx, int64_t n, int64_t nb) {
+  if (!ctx || n < 0 || nb < 0 || n > ctx->cap_n || nb > ctx->cap_nb) return 0;
+  return layout_for(ctx, n, nb).total;
+}
 
 template <class T>
 static T* at(void* ws, size_t off) {
   return (T*)((char*)ws + off);
 }
 
-static int check_ws(nbm_ctx* ctx, void* ws, size_t bytes) {
+static int check_ws(nbm_ctx* ctx, void* ws, size_t bytes, const Layout& need) {
   if (!ws) return fail(NBM_EWORKSPACE, "workspace is null");
-  if (bytes < ctx->lo.total) return fail(NBM_EWORKSPACE, "workspace too small: need " + std::to_string(ctx->lo.total));
+  if (bytes < need.total) return fail(NBM_EWORKSPACE, "workspace too small: need " + std::to_string(need.total));
   if (ctx->prepared_ws != ws) return fail(NBM_EWORKSPACE, "workspace not prepared (call nbm_prepare)");
   if (((uintptr_t)ws & 255) != 0) return fail(NBM_EWORKSPACE, "workspace must be 256-byte aligned");
   return NBM_OK;
@@ -331,7 +353,7 @@ static int check_ws(nbm_ctx* ctx, void* ws, size_t bytes) {
 
 extern "C" int nbm_prepare(nbm_ctx* ctx, void* stream, void* ws, size_t ws_bytes) {
   if (!ctx || !ws) return fail(NBM_EINVAL, "null argument");
-  if (ws_bytes < ctx->lo.total) return fail(NBM_EWORKSPACE, "workspace too small: need " + std::to_string(ctx->lo.total));
+  if (ws_bytes < ctx->lo.prefix) return fail(NBM_EWORKSPACE, "workspace too small: need " + std::to_string(ctx->lo.prefix));
   if (((uintptr_t)ws & 255) != 0) return fail(NBM_EWORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
   if (ctx->P.n_modes) {
@@ -352,11 +374,11 @@ static Problem problem_for(nbm_ctx* ctx, void* ws) {
   return P;
 }
 
-static Nets nets_for(nbm_ctx* ctx, const float* params, void* ws) {
+static Nets nets_for(nbm_ctx* ctx, const float* params, void* ws, const Layout& Lo) {
   Nets N;
   std::memset(&N, 0, sizeof(N));
   size_t wsz = (size_t)ctx->W * ctx->W * ctx->opbytes;
-  char* sh = at<char>(ws, ctx->lo.shadow);
+  char* sh = at<char>(ws, Lo.shadow);
   for (int net = 0; net < 2; ++net) {
     const float* p = params + net * ctx->per_net;
     NetPtrs& np = N.net[net];
@@ -403,25 +425,24 @@ static ShadowJobs shadow_jobs(const nbm_ctx* ctx, const float* params, const Net
 // forward (+ optional backward) of one batch
 static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const float* pts, int64_t n,
                     const float* bpts, int64_t nb, float* residual, double* loss, float* grad,
-                    double dL, void* ws) {
-  const Layout& Lo = ctx->lo;
+                    double dL, void* ws, const Layout& Lo) {
   Problem P = problem_for(ctx, ws);
   // operand shadows of the hidden matrices
-  Nets N = nets_for(ctx, params, ws);
+  Nets N = nets_for(ctx, params, ws, Lo);
   Timer* tprep = new Timer(ctx, st, 0);
 
   // classification and centre lists
   PrepCall pc;
   std::memset(&pc, 0, sizeof(pc));
   pc.stream = st; pc.P = P; pc.pts = pts; pc.n = n; pc.bpts = bpts; pc.nb = nb; pc.eval = false;
-  pc.cut_cap = (int)ctx->cut_cap;
+  pc.cut_cap = (int)Lo.cut_cap;
   pc.cls = at<int>(ws, Lo.cls); pc.rank = at<int>(ws, Lo.rank);
   pc.blockcnt = at<int>(ws, Lo.blockcnt); pc.off = at<int>(ws, Lo.off);
   pc.bcls = at<int>(ws, Lo.bcls); pc.brank = at<int>(ws, Lo.brank);
   pc.blockcnt_b = at<int>(ws, Lo.blockcnt_b); pc.off_b = at<int>(ws, Lo.off_b);
   pc.meta = at<Meta>(ws, Lo.meta);
-  pc.ctot = at<int>(ws, Lo.ctot); pc.ctot_b = pc.ctot + 4 * ctx->nchunk;
-  pc.coff = at<int>(ws, Lo.coff); pc.coff_b = pc.coff + 4 * ctx->nchunk;
+  pc.ctot = at<int>(ws, Lo.ctot); pc.ctot_b = pc.ctot + 4 * Lo.nchunk;
+  pc.coff = at<int>(ws, Lo.coff); pc.coff_b = pc.coff + 4 * Lo.nchunk;
   pc.centres = at<float4>(ws, Lo.centres);
   pc.src = at<int>(ws, Lo.src);
   pc.cutidx = at<int>(ws, Lo.cutidx);
@@ -435,16 +456,17 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   const bool fourier = ctx->cfg.problem == NBM_PROB_FOURIER;
   pc.fslot = fourier ? nullptr : f_inline;
   hipError_t e = launch_prep(pc);
+  delete tprep;
   const float* fpre = nullptr;
   if (fourier && n > 0) {
     fpre = at<float>(ws, Lo.fpre);
+    Timer tfo(ctx, st, 9);
     if (e == hipSuccess) e = launch_forcing(st, P, pts, n, (float*)fpre, pc.meta, pc.cls, pc.rank, f_inline);
   }
-  delete tprep;
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("prep: ") + hipGetErrorString(e));
   // network streams at every centre
   int nbr = P.lo >= 0 ? 2 * ctx->D : 0;
-  int64_t cut_here = std::min<int64_t>(ctx->cut_cap, n);
+  const int64_t cut_here = Lo.cut_cap;
   int64_t slots = n + (2 + nbr) * cut_here + nb + 2 * kTile;
   int grid = (int)((slots + kTile - 1) / kTile + 2);
   const bool fused = grad != nullptr && (ctx->fused != nullptr || ctx->wide != nullptr) && !ctx->no_fused;
@@ -454,7 +476,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   mc.centres = pc.centres; mc.nets = &N; mc.L = ctx->L; mc.h = (float)ctx->cfg.h;
   mc.outputs = at<float>(ws, Lo.outputs);
   mc.Zst = at<float>(ws, Lo.Zst); mc.Ast = at<void>(ws, Lo.Ast); mc.ALst = at<float>(ws, Lo.ALst);
-  mc.dZ = at<float>(ws, Lo.dZ); mc.lstride = ctx->lstride;
+  mc.dZ = at<float>(ws, Lo.dZ); mc.lstride = Lo.lstride;
   mc.store = grad != nullptr && !fused; mc.streams = true;
   if (fused) {
     // forward only over the tiles that are not 16 uncut centres
@@ -506,13 +528,18 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
     std::memset(&wc, 0, sizeof(wc));
     wc.stream = st; wc.grid = ctx->Gf; wc.meta = pc.meta; wc.centres = pc.centres; wc.src = pc.src;
     wc.nets = &N; wc.P = P; wc.h = (float)ctx->cfg.h; wc.adj = adj; wc.resid = rc.resid;
-    wc.A = at<void>(ws, Lo.Ast); wc.dZ = at<void>(ws, Lo.dZw); wc.lstride = ctx->lstride;
+    wc.A = at<void>(ws, Lo.Ast); wc.dZ = at<void>(ws, Lo.dZw); wc.lstride = Lo.lstride;
     wc.partial = partial; wc.Ptot = ctx->Ptot; wc.lay = &ctx->lay; wc.off1 = ctx->per_net;
     wc.lossp = rc.lossp + nres; wc.scale = rc.scale; wc.fslot = f_inline;
-    {
-      Timer tb(ctx, st, 3);
-      e = ctx->wide(wc);
-    }
+    // group 3 times the forward/backward launch, group 8 each weight-gradient launch
+    WideTimers wt{ctx, st, new Timer(ctx, st, 3), nullptr};
+    wc.timer_ctx = &wt;
+    wc.after_fb = [](void* p) { auto* t = (WideTimers*)p; delete t->fb; t->fb = nullptr; };
+    wc.timer_begin = [](void* p) { auto* t = (WideTimers*)p; t->dw = new Timer(t->c, t->st, 8); };
+    wc.timer_end = [](void* p) { auto* t = (WideTimers*)p; delete t->dw; t->dw = nullptr; };
+    e = ctx->wide(wc);
+    delete wt.fb;
+    delete wt.dw;
     if (e != hipSuccess) return fail(NBM_EHIP, std::string("wide: ") + hipGetErrorString(e));
     red_lossp = rc.lossp; red_nparts = nres + ctx->Gf; red_loss = loss_out;
     Grows = ctx->Gf;
@@ -561,22 +588,25 @@ extern "C" int nbm_forward_residual(nbm_ctx* ctx, void* stream, const float* par
                                     int64_t n, const float* bpts, int64_t nb, float* residual,
                                     double* loss, float* grad, void* ws, size_t ws_bytes) {
   if (!ctx || !params || !loss) return fail(NBM_EINVAL, "null argument");
-  int rc = check_ws(ctx, ws, ws_bytes);
+  int rc = check_points(ctx, pts, n, bpts, nb);
   if (rc) return rc;
-  rc = check_points(ctx, pts, n, bpts, nb);
+  const Layout Lo = layout_for(ctx, n, nb);
+  rc = check_ws(ctx, ws, ws_bytes, Lo);
   if (rc) return rc;
-  return run_step(ctx, (hipStream_t)stream, params, pts, n, bpts, nb, residual, loss, grad, 1.0, ws);
+  return run_step(ctx, (hipStream_t)stream, params, pts, n, bpts, nb, residual, loss, grad, 1.0, ws, Lo);
 }
 
 extern "C" int nbm_backward(nbm_ctx* ctx, void* stream, const float* params, const float* pts, int64_t n,
                             const float* bpts, int64_t nb, double dL, float* grad, void* ws,
                             size_t ws_bytes) {
   if (!ctx || !params || !grad) return fail(NBM_EINVAL, "null argument");
-  int rc = check_ws(ctx, ws, ws_bytes);
+  if (!std::isfinite(dL)) return fail(NBM_EINVAL, "dL must be finite");
+  int rc = check_points(ctx, pts, n, bpts, nb);
   if (rc) return rc;
-  rc = check_points(ctx, pts, n, bpts, nb);
+  const Layout Lo = layout_for(ctx, n, nb);
+  rc = check_ws(ctx, ws, ws_bytes, Lo);
   if (rc) return rc;
-  return run_step(ctx, (hipStream_t)stream, params, pts, n, bpts, nb, nullptr, nullptr, grad, dL, ws);
+  return run_step(ctx, (hipStream_t)stream, params, pts, n, bpts, nb, nullptr, nullptr, grad, dL, ws, Lo);
 }
 
 extern "C" int nbm_adam_step(nbm_ctx* ctx, void* stream, float* params, float* m, float* v,
@@ -609,9 +639,10 @@ extern "C" int nbm_sample_points(nbm_ctx* ctx, void* stream, uint64_t seed, int6
 extern "C" int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const float* query, int64_t m,
                         int64_t tile_index, int32_t grid_n, float* u_out, void* ws, size_t ws_bytes) {
   if (!ctx || !params || !u_out) return fail(NBM_EINVAL, "null argument");
-  int rc = check_ws(ctx, ws, ws_bytes);
-  if (rc) return rc;
   if (m < 1 || m > ctx->cap_n) return fail(NBM_EINVAL, "m must be in [1, max_points]");
+  const Layout Lo = layout_for(ctx, m, 0);
+  int rc = check_ws(ctx, ws, ws_bytes, Lo);
+  if (rc) return rc;
   if (!query) {
     if (grid_n < 2 || (grid_n & (grid_n - 1)) != 0 || grid_n > (1 << 14))
       return fail(NBM_EINVAL, "grid_n must be a power of two in [2, 2^14]");
@@ -620,9 +651,8 @@ extern "C" int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const f
       return fail(NBM_EINVAL, "tile outside the grid");
   }
   hipStream_t st = (hipStream_t)stream;
-  const Layout& Lo = ctx->lo;
   Problem P = problem_for(ctx, ws);
-  Nets N = nets_for(ctx, params, ws);
+  Nets N = nets_for(ctx, params, ws, Lo);
   Timer tev(ctx, st, 7);
 
   PrepCall pc;
@@ -635,8 +665,8 @@ extern "C" int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const f
   pc.bcls = at<int>(ws, Lo.bcls); pc.brank = at<int>(ws, Lo.brank);
   pc.blockcnt_b = at<int>(ws, Lo.blockcnt_b); pc.off_b = at<int>(ws, Lo.off_b);
   pc.meta = at<Meta>(ws, Lo.meta);
-  pc.ctot = at<int>(ws, Lo.ctot); pc.ctot_b = pc.ctot + 4 * ctx->nchunk;
-  pc.coff = at<int>(ws, Lo.coff); pc.coff_b = pc.coff + 4 * ctx->nchunk;
+  pc.ctot = at<int>(ws, Lo.ctot); pc.ctot_b = pc.ctot + 4 * Lo.nchunk;
+  pc.coff = at<int>(ws, Lo.coff); pc.coff_b = pc.coff + 4 * Lo.nchunk;
   pc.centres = at<float4>(ws, Lo.centres);
   pc.src = at<int>(ws, Lo.src);
   pc.cutidx = at<int>(ws, Lo.cutidx);
@@ -661,7 +691,7 @@ extern "C" int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const f
   mc.op = MlpCall::FORWARD; mc.stream = st; mc.grid = grid; mc.meta = pc.meta;
   mc.centres = pc.centres; mc.nets = &N; mc.L = ctx->L; mc.h = (float)ctx->cfg.h;
   mc.outputs = at<float>(ws, Lo.outputs);
-  mc.lstride = ctx->lstride;
+  mc.lstride = Lo.lstride;
   mc.store = false; mc.streams = false;
   e = ctx->mlp(mc);
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("eval: ") + hipGetErrorString(e));
@@ -672,7 +702,9 @@ extern "C" int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const f
 
 extern "C" int nbm_batch_counts(nbm_ctx* ctx, void* stream, int32_t* counts, void* ws, size_t ws_bytes) {
   if (!ctx || !counts) return fail(NBM_EINVAL, "null argument");
-  int rc = check_ws(ctx, ws, ws_bytes);
+  Layout pre = ctx->lo;
+  pre.total = pre.prefix;   // only the bookkeeping is read
+  int rc = check_ws(ctx, ws, ws_bytes, pre);
   if (rc) return rc;
   hipError_t e = launch_counts((hipStream_t)stream, at<Meta>(ws, ctx->lo.meta), counts);
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("counts: ") + hipGetErrorString(e));

@@ -452,7 +452,8 @@ __global__ void k_fill(float* p, int64_t n, float v) {
 // grad[j] = scale * sum_g partial[g][j] in FP64: 64 columns per block, the
 // G rows split over 16 groups (g = k, k+16, ...) with four running sums each;
 // group sums are added in a fixed order.  With `loss`, one extra block sums
-// the FP64 loss partials (fixed strided order, then a fixed tree).
+// the FP64 loss partials (fixed strided order, then a fixed tree).  Both
+// outputs are NaN when the batch overflowed the cut capacity.
 __global__ __launch_bounds__(1024) void k_reduce(const float* partial, int G, int64_t P, float* grad,
                                                  double scale, const double* lp, int nparts,
                                                  const Meta* meta, double* loss) {
@@ -500,7 +501,9 @@ __global__ __launch_bounds__(1024) void k_reduce(const float* partial, int G, in
   if (k == 0 && j < P) {
     double t = 0.0;
     for (int q = 0; q < 16; ++q) t += sh[q][c];
-    grad[j] = (float)(t * scale);
+    // a batch whose cut cells overflowed the capacity dropped some of them:
+    // its gradient is marked NaN like its loss, never returned partial
+    grad[j] = meta->overflow ? __builtin_nanf("") : (float)(t * scale);
   }
 }
 

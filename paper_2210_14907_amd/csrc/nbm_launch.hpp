@@ -88,7 +88,8 @@ struct WideCall {
   int64_t off1;
   double* lossp;
   double scale;
-  void (*timer_begin)(void*);
+  void (*after_fb)(void*);      // called after the forward/backward launch (or null)
+  void (*timer_begin)(void*);   // called around each weight-gradient launch (or null)
   void (*timer_end)(void*);
   void* timer_ctx;
 };

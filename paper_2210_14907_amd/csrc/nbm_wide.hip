@@ -471,6 +471,7 @@ hipError_t wide_impl(const WideCall& c) {
                      c.centres, c.src, *c.nets, c.P, c.h, c.adj, c.resid, c.A, c.dZ, c.lstride,
                      c.partial, c.Ptot, *c.lay, c.off1, c.lossp, c.scale, c.fslot);
   hipError_t e = hipGetLastError();
+  if (c.after_fb) c.after_fb(c.timer_ctx);
   if (e != hipSuccess) return e;
   for (int l = 2; l <= L; ++l) {
     if (c.timer_begin) c.timer_begin(c.timer_ctx);

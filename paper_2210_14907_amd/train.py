@@ -16,20 +16,38 @@ from .binding import NBM
 
 
 class NBMResidual(torch.autograd.Function):
+    """loss = NBMResidual.apply(params, pts, bpts, nbm, fused=True).
+
+    fused=True: the forward call also writes dL/dtheta (one fused pass), the
+    backward returns it times the upstream gradient.  fused=False: the
+    forward computes only the loss, the backward calls nbm_backward with the
+    upstream gradient as its factor (the step is recomputed; nothing is
+    stored between the two calls)."""
+
     @staticmethod
-    def forward(ctx, params, pts, bpts, nbm: NBM):
-        loss, _, grad = nbm.forward_residual(params.detach(), pts, bpts, want_grad=True)
-        ctx.save_for_backward(grad)
+    def forward(ctx, params, pts, bpts, nbm: NBM, fused: bool = True):
+        p = params.detach()
+        if fused:
+            loss, _, grad = nbm.forward_residual(p, pts, bpts, want_grad=True)
+            ctx.save_for_backward(grad)
+        else:
+            loss, _, _ = nbm.forward_residual(p, pts, bpts)
+            ctx.save_for_backward(p, pts, bpts)
+        ctx.nbm, ctx.fused = nbm, fused
         return loss.reshape(())
 
     @staticmethod
     def backward(ctx, gout):
-        (grad,) = ctx.saved_tensors
-        return grad * gout.to(grad.dtype), None, None, None
+        if ctx.fused:
+            (grad,) = ctx.saved_tensors
+            return grad * gout.to(grad.dtype), None, None, None, None
+        p, pts, bpts = ctx.saved_tensors
+        grad = ctx.nbm.backward(p, pts, bpts, dL=float(gout.item()))
+        return grad, None, None, None, None
 
 
-def nbm_loss(params, pts, bpts, nbm: NBM):
-    return NBMResidual.apply(params, pts, bpts, nbm)
+def nbm_loss(params, pts, bpts, nbm: NBM, fused: bool = True):
+    return NBMResidual.apply(params, pts, bpts, nbm, fused)
 
 
 def init_params(wl: I.Workload, seed: int = 0, device="cuda:0"):
@@ -37,7 +55,8 @@ def init_params(wl: I.Workload, seed: int = 0, device="cuda:0"):
 
 
 def train(wl: I.Workload, steps: int = None, lr: float = None, seed: int = 1, params=None,
-          nbm: NBM = None, start_step: int = 1, state=None, log_every: int = 0):
+          nbm: NBM = None, start_step: int = 1, state=None, log_every: int = 0,
+          check_finite: bool = True):
     """Adam training loop; returns (params, nbm, state, losses[cpu float64])."""
     steps = wl.steps if steps is None else steps
     lr = wl.lr if lr is None else lr
@@ -55,4 +74,9 @@ def train(wl: I.Workload, steps: int = None, lr: float = None, seed: int = 1, pa
         nbm.adam_step(params, state["m"], state["v"], grad, step, lr=lr)
         if log_every and (k + 1) % log_every == 0:
             print(f"step {step}: loss {losses[k].item():.6e}", flush=True)
-    return params, nbm, state, losses.cpu()
+    losses = losses.cpu()
+    if check_finite and not torch.isfinite(losses).all():
+        bad = int((~torch.isfinite(losses)).nonzero()[0, 0]) + start_step
+        raise RuntimeError(f"non-finite loss at step {bad} (a batch over the cut capacity "
+                           "reports NaN loss and gradient)")
+    return params, nbm, state, losses

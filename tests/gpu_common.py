@@ -47,3 +47,34 @@ def max_rel(a, b):
     b = np.asarray(b, dtype=np.float64)
     den = np.abs(b).max()
     return np.abs(a - b).max() / (den if den > 0 else 1.0)
+
+
+def param_blocks(wl):
+    """(name, slice) of every parameter block of both nets, in packing order:
+    W1, b1, (W_l, b_l) for l = 2..L, w_out, b_out per net."""
+    W, d, L = wl.width, wl.dim, wl.depth
+    out, off = [], 0
+    for net in ("minus", "plus"):
+        shapes = [("W1", W * d), ("b1", W)]
+        for l in range(2, L + 1):
+            shapes += [(f"W{l}", W * W), (f"b{l}", W)]
+        shapes += [("wout", W), ("bout", 1)]
+        for name, size in shapes:
+            out.append((f"{net}.{name}", slice(off, off + size)))
+            off += size
+    assert off == wl.n_params
+    return out
+
+
+def grad_block_ratios(wl, g, g_o, tol, floor=1e-3):
+    """Per parameter block, the largest |g - g_o| / (tol (|g_o| + floor max|g_o|_block)):
+    every entry of every block must be within tol of the oracle relative to its
+    own size, entries far below the block's largest one relative to that."""
+    g = np.asarray(g, dtype=np.float64)
+    g_o = np.asarray(g_o, dtype=np.float64)
+    out = {}
+    for name, sl in param_blocks(wl):
+        a, b = g[sl], g_o[sl]
+        bound = tol * (np.abs(b) + floor * np.abs(b).max())
+        out[name] = float(np.max(np.abs(a - b) / np.where(bound > 0, bound, 1.0)))
+    return out

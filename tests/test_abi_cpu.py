@@ -52,8 +52,13 @@ def test_create_counts_and_workspace(wl):
     rc, h = _create(_cfg(wl))
     assert rc == 0
     assert B.lib().nbm_param_count(h) == wl.n_params
-    ws = B.lib().nbm_workspace_bytes(h)
+    ws = B.lib().nbm_workspace_bytes(h, wl.n_points, wl.n_boundary)
     assert ws > 0
+    # smaller batches need no more; past the capacity the query is rejected
+    assert 0 < B.lib().nbm_workspace_bytes(h, wl.n_points // 4, 0) < ws
+    assert B.lib().nbm_workspace_bytes(h, wl.n_points + 1, 0) == 0
+    assert B.lib().nbm_workspace_bytes(h, 1, wl.n_boundary + 1) == 0
+    assert B.lib().nbm_workspace_bytes(h, -1, 0) == 0
     B.lib().nbm_destroy(h)
 
 

@@ -1,0 +1,192 @@
+"""Gradient parity, element by element and per parameter block, where the
+W = 128 path really runs (paper Sec. 3: automatic differentiation across the
+NBM kernels, then Adam).
+
+- The sphere workload's full training batch (262,144 + 3,072 points, two
+  3->128x4->1 sine nets, h = 1/256) in BF16 and FP32 operands: over 1,000
+  tiles per net against 256 persistent work-groups, so the two-pass backward
+  walks several tiles per work-group and its weight-gradient pass runs its
+  double-buffered staging loop more than once.
+- The star workload (h = 1/1024, mu 1:100, Fourier forcing) on a batch with
+  more than 512 tiles in each net.
+- nbm_backward with an upstream factor, and the torch.autograd.Function
+  wrapper, against the oracle and central finite differences.
+
+Every gradient entry must satisfy |g - g_o| <= tol (|g_o| + 1e-3 max|g_o|)
+with max over its parameter block (tol 1e-5 FP32, 2e-2 BF16 operands)."""
+import numpy as np
+import pytest
+
+import nbm_inputs as I
+from oracle import nbm as N
+from oracle import scheme as S
+from tests.gpu_common import grad_block_ratios, max_rel, parity_batch, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {I.PREC_FP32: 1e-5, I.PREC_BF16: 2e-2}
+DEV = "cuda:0"
+
+
+def _gpu_step(wl, theta, pts, bpts, nbm=None):
+    from paper_2210_14907_amd import NBM
+    m = nbm or NBM(wl, max_points=max(pts.shape[0], 16), max_boundary=max(bpts.shape[0], 1))
+    p = torch.tensor(theta, dtype=torch.float32, device=DEV)
+    tp = torch.tensor(pts, dtype=torch.float32, device=DEV)
+    tb = torch.tensor(bpts, dtype=torch.float32, device=DEV).reshape(-1, wl.dim)
+    loss, res, grad = m.forward_residual(p, tp, tb, want_residual=True, want_grad=True)
+    counts = m.batch_counts().cpu().numpy()
+    torch.cuda.synchronize()
+    return loss.item(), res.cpu().numpy(), grad.cpu().numpy().astype(np.float64), counts
+
+
+def _report(tag, ratios):
+    worst = max(ratios, key=ratios.get)
+    print(f"[grad] {tag}: worst block {worst} ratio {ratios[worst]:.3f}; "
+          + " ".join(f"{k}={v:.2f}" for k, v in ratios.items()), flush=True)
+    return ratios[worst]
+
+
+_C3_ORACLE = {}
+
+
+def _c3_full_batch():
+    """Sampled full C3 batch (device Philox, seed 1, step 1) and the oracle's
+    loss and gradient on the same points (computed once)."""
+    if "ref" not in _C3_ORACLE:
+        from paper_2210_14907_amd import NBM
+        wl = I.C3
+        m = NBM(wl)
+        pts, bpts = m.sample_points(seed=1, step=1)
+        P = pts.cpu().numpy().astype(np.float64)
+        B = bpts.cpu().numpy().astype(np.float64)
+        theta = I.xavier_params(wl, 0).astype(np.float32).astype(np.float64)
+        print(f"[grad] c3 full batch: oracle on {P.shape[0]} + {B.shape[0]} points", flush=True)
+        L_o, g_o, res_o = N.loss_and_grad(wl, theta, P, B)
+        _C3_ORACLE["ref"] = (P, B, theta, L_o, g_o, res_o)
+    return _C3_ORACLE["ref"]
+
+
+@pytest.mark.parametrize("prec", [I.PREC_BF16, I.PREC_FP32], ids=["bf16", "fp32"])
+def test_c3_full_batch_gradient_elementwise(prec):
+    wl = I.C3.replace(prec=prec)
+    P, B, theta, L_o, g_o, res_o = _c3_full_batch()
+    L_g, r_g, g_g, counts = _gpu_step(wl, theta, P, B)
+    cls = res_o["cls"]
+    assert counts[0] == (cls == 0).sum() and counts[1] == (cls == 1).sum()
+    assert counts[2] == (cls == S.CLASS_CUT).sum() and counts[5] == 0
+    # both nets hold more than two tiles per persistent work-group
+    assert counts[0] // 16 > 512 and counts[1] // 16 > 512
+    tol = TOL[prec]
+    r_o = np.concatenate([res_o["r"], res_o["rb"]])
+    e_loss, e_res = abs(L_g - L_o) / abs(L_o), max_rel(r_g, r_o)
+    worst = _report(f"c3_full_{'bf16' if prec else 'fp32'} loss {e_loss:.1e} res {e_res:.1e}",
+                    grad_block_ratios(wl, g_g, g_o, tol))
+    assert e_loss <= tol and e_res <= tol
+    assert worst <= 1.0
+
+
+def test_c4_many_tiles_per_net_gradient_elementwise():
+    """Star workload, BF16 operands: 100,000 uniform points plus 16,000 points
+    inside the star, so each network has well over 512 tiles."""
+    wl = I.C4
+    rng = np.random.default_rng(12)
+    pts, bpts = parity_batch(wl, 100_000, 384, 2_000, 0.003, seed=31)
+    v = rng.normal(size=(16_000, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    inner = v * rng.uniform(0.0, 0.3, size=(16_000, 1))
+    inner = np.round(inner * 2.0 ** 22) / 2.0 ** 22
+    pts = np.concatenate([pts, inner]).astype(np.float32).astype(np.float64)
+    bpts = bpts.astype(np.float32).astype(np.float64)
+    theta = I.xavier_params(wl, 3).astype(np.float32).astype(np.float64)
+    print(f"[grad] c4 batch {pts.shape[0]} + {bpts.shape[0]}: oracle", flush=True)
+    L_o, g_o, res_o = N.loss_and_grad(wl, theta, pts, bpts)
+    L_g, r_g, g_g, counts = _gpu_step(wl, theta, pts, bpts)
+    cls = res_o["cls"]
+    assert counts[2] == (cls == S.CLASS_CUT).sum() and counts[5] == 0
+    assert counts[0] // 16 > 512 and counts[1] // 16 > 512
+    tol = TOL[wl.prec]
+    r_o = np.concatenate([res_o["r"], res_o["rb"]])
+    e_loss, e_res = abs(L_g - L_o) / abs(L_o), max_rel(r_g, r_o)
+    worst = _report(f"c4_many_tiles loss {e_loss:.1e} res {e_res:.1e}",
+                    grad_block_ratios(wl, g_g, g_o, tol))
+    assert e_loss <= tol and e_res <= tol
+    assert worst <= 1.0
+
+
+CASES = [
+    ("c1", I.C1, 4096, 256, 256, 0.05),
+    ("c2", I.C2, 4096, 96, 512, 0.02),
+    ("c2_bf16", I.C2.replace(prec=I.PREC_BF16), 4096, 96, 512, 0.02),
+    ("c3_fp32", I.C3.replace(prec=I.PREC_FP32), 2048, 48, 256, 0.01),
+]
+
+
+@pytest.mark.parametrize("name,wl,n,nb,n_near,band", CASES, ids=[c[0] for c in CASES])
+def test_small_batch_gradient_elementwise(name, wl, n, nb, n_near, band):
+    theta = I.xavier_params(wl, 0).astype(np.float32).astype(np.float64)
+    pts, bpts = parity_batch(wl, n, nb, n_near, band)
+    pts = pts.astype(np.float32).astype(np.float64)
+    bpts = bpts.astype(np.float32).astype(np.float64)
+    _, g_o, _ = N.loss_and_grad(wl, theta, pts, bpts)
+    _, _, g_g, _ = _gpu_step(wl, theta, pts, bpts)
+    assert _report(name, grad_block_ratios(wl, g_g, g_o, TOL[wl.prec])) <= 1.0
+
+
+@pytest.mark.parametrize("wl", [I.C2, I.C3], ids=["c2_fused", "c3_two_pass"])
+def test_backward_entry_point_scales_by_upstream_factor(wl):
+    """nbm_backward(dL) recomputes the step and returns dL times the fused
+    gradient of nbm_forward_residual (same kernels, the factor enters the
+    residual adjoints)."""
+    from paper_2210_14907_amd import NBM
+    theta = I.xavier_params(wl, 4).astype(np.float32)
+    pts, bpts = parity_batch(wl, 3000, 64, 256, 0.01, seed=5)
+    m = NBM(wl, max_points=pts.shape[0], max_boundary=bpts.shape[0])
+    p = torch.tensor(theta, device=DEV)
+    tp = torch.tensor(pts, dtype=torch.float32, device=DEV)
+    tb = torch.tensor(bpts, dtype=torch.float32, device=DEV)
+    _, _, g1 = m.forward_residual(p, tp, tb, want_grad=True)
+    g1 = g1.clone()
+    g2 = m.backward(p, tp, tb, dL=0.37)
+    torch.cuda.synchronize()
+    a, b = g2.cpu().numpy().astype(np.float64), 0.37 * g1.cpu().numpy().astype(np.float64)
+    assert _report(f"backward_dL {wl.name}", grad_block_ratios(wl, a, b, 1e-6)) <= 1.0
+
+
+def test_autograd_function_matches_oracle_and_finite_differences():
+    """loss = 3 NBMResidual(params) - 0.5: params.grad is 3 dL/dtheta, equal to
+    the oracle's gradient, and its entries match central differences of the
+    GPU loss on a tiny 2-D net (both the fused path and the one that calls
+    nbm_backward from the autograd backward)."""
+    from paper_2210_14907_amd import NBM
+    from paper_2210_14907_amd.train import NBMResidual
+    wl = I.C1.replace(width=16, depth=2)
+    theta = I.xavier_params(wl, 7).astype(np.float32).astype(np.float64)
+    pts, bpts = parity_batch(wl, 300, 24, 40, 0.05, seed=17)
+    pts = pts.astype(np.float32).astype(np.float64)
+    bpts = bpts.astype(np.float32).astype(np.float64)
+    _, g_o, _ = N.loss_and_grad(wl, theta, pts, bpts)
+    m = NBM(wl, max_points=pts.shape[0], max_boundary=bpts.shape[0])
+    tp = torch.tensor(pts, dtype=torch.float32, device=DEV)
+    tb = torch.tensor(bpts, dtype=torch.float32, device=DEV)
+    for fused in (True, False):
+        p = torch.tensor(theta, dtype=torch.float32, device=DEV, requires_grad=True)
+        loss = 3.0 * NBMResidual.apply(p, tp, tb, m, fused) - 0.5
+        loss.backward()
+        g = p.grad.cpu().numpy().astype(np.float64)
+        assert _report(f"autograd fused={fused}", grad_block_ratios(wl, g, 3.0 * g_o, 1e-5)) <= 1.0
+    # central differences of the GPU loss (FP64 accumulation of FP32
+    # residuals) on the largest entries of each block
+    pd = torch.tensor(theta, dtype=torch.float32, device=DEV)
+    rng = np.random.default_rng(0)
+    idx = np.concatenate([np.argsort(-np.abs(g_o))[:6], rng.choice(wl.n_params, 6, replace=False)])
+    eps = 2e-3
+    for i in idx:
+        up, dn = pd.clone(), pd.clone()
+        up[i] += eps
+        dn[i] -= eps
+        Lu = m.forward_residual(up, tp, tb)[0].item()
+        Ld = m.forward_residual(dn, tp, tb)[0].item()
+        fd = (Lu - Ld) / (float(up[i].item()) - float(dn[i].item()))
+        assert abs(fd - g_o[i]) <= 2e-2 * abs(g_o[i]) + 1e-3 * np.abs(g_o).max(), (i, fd, g_o[i])

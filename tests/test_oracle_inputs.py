@@ -1,0 +1,163 @@
+"""Pins of the seeded problem tables and of the oracle's network forward.
+
+The Fourier mode table (star workload: f^- = f^+ = a random smooth series of
+integer wave numbers with 1 <= |k| <= 8, one term per +-k pair, amplitudes
+~ N(0, 1/|k|^2)) is shared by the oracle and the HIP path, so it is pinned
+here against brute-force enumeration of the lattice ball, and the oracle's
+forcing against a term-by-term scalar sum, its value at the origin, its
+periodicity and its parity split.  The network forward (paper Sec. 3: two
+fully connected networks; Sec. 4.1: sine activation) is pinned on tiny nets
+whose weights are chosen so that every activation takes a value known in
+closed form (tanh(atanh q) = q, sin(pi/6) = 1/2, ...)."""
+import math
+
+import numpy as np
+
+import nbm_inputs as I
+from oracle import mlp as M
+from oracle.problems import Problem
+
+
+def _lattice_ball(kmax):
+    r = np.arange(-kmax, kmax + 1)
+    g = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
+    n2 = (g * g).sum(axis=1)
+    return g[(n2 >= 1) & (n2 <= kmax * kmax)]
+
+
+def test_fourier_mode_count_and_half_space():
+    k, a, b = I.fourier_modes(I.C4)
+    ball = _lattice_ball(8)
+    # the integer points of the radius-8 ball without the origin: 2,108 of them
+    assert ball.shape[0] == 2108
+    assert k.shape == (1054, 3) and a.shape == (1054,) and b.shape == (1054,)
+    ks = {tuple(v) for v in k.tolist()}
+    assert len(ks) == 1054                                  # no repeats
+    assert not any((-v[0], -v[1], -v[2]) in ks for v in ks)  # never both k and -k
+    both = ks | {(-v[0], -v[1], -v[2]) for v in ks}
+    assert both == {tuple(v) for v in ball.tolist()}        # every pair represented
+    # representative: first non-zero component positive
+    for v in k.tolist():
+        first = next(c for c in v if c != 0)
+        assert first > 0
+    # enumeration order: lexicographic in (k0, k1, k2)
+    keys = [tuple(v) for v in k.tolist()]
+    assert keys == sorted(keys)
+    n = np.sqrt((k.astype(np.float64) ** 2).sum(axis=1))
+    assert n.min() == 1.0 and n.max() == 8.0
+
+
+def test_fourier_amplitudes_scale_with_one_over_k():
+    """a_k |k| and b_k |k| are 2,108 standard normal draws: their mean square
+    is 1 within 4 standard errors (sqrt(2/2108) = 0.031) and their mean is 0
+    within 4/sqrt(2108)."""
+    k, a, b = I.fourier_modes(I.C4)
+    n = np.sqrt((k.astype(np.float64) ** 2).sum(axis=1))
+    z = np.concatenate([a * n, b * n])
+    assert abs(np.mean(z * z) - 1.0) < 4 * math.sqrt(2.0 / z.size)
+    assert abs(np.mean(z)) < 4.0 / math.sqrt(z.size)
+    # a different seed gives a different table, the same seed the same one
+    k2, a2, _ = I.fourier_modes(I.C4.replace(fourier_seed=3))
+    assert np.array_equal(k, k2) and not np.allclose(a, a2)
+    _, a3, _ = I.fourier_modes(I.C4)
+    assert np.array_equal(a, a3)
+
+
+def test_fourier_forcing_termwise_and_closed_forms():
+    wl = I.C4
+    prob = Problem(wl)
+    k, a, b = I.fourier_modes(wl)
+    rng = np.random.default_rng(0)
+    x = rng.uniform(-1, 1, size=(6, 3))
+    f = prob.f_side(0, x)
+    for i in range(x.shape[0]):
+        s = 0.0
+        for m in range(k.shape[0]):
+            ph = math.pi * (int(k[m, 0]) * x[i, 0] + int(k[m, 1]) * x[i, 1] + int(k[m, 2]) * x[i, 2])
+            s += float(a[m]) * math.cos(ph) + float(b[m]) * math.sin(ph)
+        assert abs(f[i] - s) <= 1e-12 * max(1.0, abs(s))
+    # both sides carry the same forcing
+    assert np.array_equal(prob.f_side(1, x), f)
+    # f(0) = sum of cosine amplitudes
+    assert abs(prob.f_side(0, np.zeros((1, 3)))[0] - a.sum()) <= 1e-12 * np.abs(a).sum()
+    # integer wave numbers times pi: period 2 along every axis
+    for ax in range(3):
+        sh = x.copy()
+        sh[:, ax] += 2.0
+        assert np.allclose(prob.f_side(0, sh), f, rtol=0, atol=1e-11)
+    # even part is the cosine series, odd part the sine series
+    fm = prob.f_side(0, -x)
+    ph = math.pi * (x @ k.T.astype(np.float64))
+    assert np.allclose(0.5 * (f + fm), np.cos(ph) @ a, rtol=0, atol=1e-11)
+    assert np.allclose(0.5 * (f - fm), np.sin(ph) @ b, rtol=0, atol=1e-11)
+
+
+def test_fourier_forcing_is_smooth_spectrum():
+    """-Laplacian of each mode is pi^2 |k|^2 times the mode: a seven-point
+    finite-difference Laplacian of the oracle's f matches the spectral one
+    to O(h^2)."""
+    wl = I.C4
+    prob = Problem(wl)
+    k, a, b = I.fourier_modes(wl)
+    x = np.array([[0.1, -0.3, 0.45], [-0.7, 0.2, 0.05]])
+    kk = (k.astype(np.float64) ** 2).sum(axis=1)
+    ph = math.pi * (x @ k.T.astype(np.float64))
+    lap_spec = -(math.pi ** 2) * ((np.cos(ph) * kk) @ a + (np.sin(ph) * kk) @ b)
+    errs = []
+    for h in (1e-3, 5e-4):
+        lap = -6.0 * prob.f_side(0, x)
+        for ax in range(3):
+            e = np.zeros(3)
+            e[ax] = h
+            lap = lap + prob.f_side(0, x + e) + prob.f_side(0, x - e)
+        errs.append(np.abs(lap / h ** 2 - lap_spec).max())
+    scale = np.abs(lap_spec).max()
+    assert errs[0] < 1e-4 * scale and errs[1] < 0.4 * errs[0] + 1e-6 * scale
+
+
+def _pack(wl, nets):
+    out = []
+    for layers in nets:
+        for Wm, bv in layers:
+            out += [np.asarray(Wm, dtype=np.float64).ravel(), np.asarray(bv, dtype=np.float64)]
+    th = np.concatenate(out)
+    assert th.size == wl.n_params
+    return th
+
+
+def test_mlp_forward_tanh_hand_values():
+    """2 -> 2 -> 1 tanh nets.  At x = (1, 2): net^-'s pre-activations are
+    atanh(1/2) and atanh(-1/4) (the weight matrix is not symmetric, so a
+    transposed one changes them), the output is 2(1/2) + 4(-1/4) + 0.3 = 0.3;
+    net^+ has a non-zero bias and gives -3(0.6) + 0.25 = -1.55."""
+    wl = I.C1.replace(width=2, depth=1)
+    p, q = math.atanh(0.5), math.atanh(-0.25)
+    c = 0.1
+    net_m = [([[p - 2.0 * c, c], [0.0, q / 2.0]], [0.0, 0.0]), ([[2.0, 4.0]], [0.3])]
+    r = math.atanh(0.6)
+    net_p = [([[0.0, 0.0], [r - 1.0, 0.0]], [0.0, 1.0]), ([[5.0, -3.0]], [0.25])]
+    th = _pack(wl, [net_m, net_p])
+    nets = M.unpack(wl, th)
+    x = np.array([[1.0, 2.0]])
+    assert abs(M.forward(wl, nets[0], x)[0] - 0.3) < 1e-14
+    assert abs(M.forward(wl, nets[1], x)[0] - (-1.55)) < 1e-14
+    # eval_two picks the net of each point's side
+    u = M.eval_two(wl, th, np.array([[1.0, 2.0], [1.0, 2.0]]), np.array([True, False]))
+    assert np.allclose(u, [0.3, -1.55], rtol=0, atol=1e-14)
+
+
+def test_mlp_forward_sin_two_hidden_layers_hand_values():
+    """3 -> 2 -> 2 -> 1 sine nets (no frequency scaling).  x = (0.5, -1, 2):
+    layer 1 gives sin(pi/6) = 1/2 and sin(pi/2) = 1; layer 2 gives
+    sin(pi/3 * 1/2) = 1/2 and sin(pi * 1/2 - pi/2 * 1 + pi/4) = sin(pi/4);
+    output 6(1/2) - 2 sin(pi/4) - 1 = 2 - sqrt(2)."""
+    wl = I.C2.replace(width=2, depth=2, act=I.ACT_SIN)
+    W1 = [[math.pi / 3.0, 0.0, 0.0], [0.0, 0.0, math.pi / 4.0]]
+    W2 = [[math.pi / 3.0, 0.0], [math.pi, -math.pi / 2.0]]
+    net = [(W1, [0.0, 0.0]), (W2, [0.0, math.pi / 4.0]), ([[6.0, -2.0]], [-1.0])]
+    zero = [(np.zeros((2, 3)), np.zeros(2)), (np.zeros((2, 2)), np.zeros(2)), (np.zeros((1, 2)), [0.7])]
+    th = _pack(wl, [net, zero])
+    nets = M.unpack(wl, th)
+    x = np.array([[0.5, -1.0, 2.0]])
+    assert abs(M.forward(wl, nets[0], x)[0] - (2.0 - math.sqrt(2.0))) < 1e-14
+    assert abs(M.forward(wl, nets[1], x)[0] - 0.7) < 1e-15
