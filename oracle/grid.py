@@ -180,20 +180,29 @@ class GridSystem:
         d, h, wl, prob = self.d, self.h, self.wl, self.prob
         b = np.zeros(self.N)
         if not hasattr(self, "_f_uncut"):
-            # the forcing does not change across Picard iterations
-            xu = self.x[self.uncut]
-            su = self.side[self.uncut]
+            # everything but the lagged gradients is the same in every Picard
+            # iteration: forcing, cut-cell geometry, interface data at the nodes
             if wl.problem == I.PROB_FOURIER:
-                self._f_uncut = prob.f_side(0, xu)   # f^- = f^+
+                fn = prob.f_grid(self.n)               # f^- = f^+ at every node
+                fcut = (fn[self.cut], fn[self.cut])
+                self._f_uncut = fn[self.uncut]
+                del fn
             else:
+                xu = self.x[self.uncut]
+                su = self.side[self.uncut]
                 self._f_uncut = np.where(su, prob.f_side(0, xu), prob.f_side(1, xu))
+                xc = self.x[self.cut]
+                fcut = (prob.f_side(0, xc), prob.f_side(1, xc))
+            if self.cut.size:
+                nodes = self.cut[:, None] + self.node_offsets()[None, :]
+                self._cut_static = S.cut_static(wl, prob, self.x[self.cut], h, fvals=fcut)
+                self._jump_data = S.jump_data(wl, prob, self.x[nodes])
         b[self.uncut] = h * h * self._f_uncut
         if self.cut.size:
             nodes = self.cut[:, None] + self.node_offsets()[None, :]
-            y = self.x[nodes]
             sides = self.side[nodes]
-            J = S.jump_extension(wl, prob, y, grad_lo_cut)
-            terms = S.cut_terms(wl, prob, self.x[self.cut], h, sides, J)
+            J = S.jump_extension(wl, prob, None, grad_lo_cut, data=self._jump_data)
+            terms = S.cut_terms(wl, prob, self.x[self.cut], h, sides, J, static=self._cut_static)
             self._cut_terms = terms
             b[self.cut] = -h * h * terms["K"]
         # Dirichlet neighbours
@@ -217,43 +226,59 @@ class GridSystem:
         return out
 
     # ----------------------------------------------------------------- contrast
-    def extend_lo(self, Ufull, sweeps=None):
-        """Extend the low-mu side field across Gamma: constant normal
-        derivative (upwind extrapolation of q = n.grad u), then linear
-        extension of u with n.grad u = q.  Returns nodal array."""
+    def _extension_setup(self):
+        """Everything of the low-side extension that depends only on the
+        geometry (computed once, reused by every Picard iteration): the band
+        |phi| < 6h of interior nodes two cells inside the box, the unit
+        normals there (pointing away from the low side), the nodes whose q is
+        known (low side) and the targets with their upwind neighbours."""
+        if hasattr(self, "_ext"):
+            return self._ext
         d, h, n = self.d, self.h, self.n
         lo = S.lo_side(self.wl)
         lo_mask = self.side if lo == 0 else ~self.side
-        nrm = G.grad_phi(self.wl, self.x)
+        inner = self.interior.copy()
+        for a in range(d):
+            inner &= (self.idx[:, a] > 1) & (self.idx[:, a] < n - 1)
+        cand = np.nonzero(inner)[0]
+        band = np.abs(G.phi(self.wl, self.x[cand])) < 6.0 * h
+        cand = cand[band]
+        nrm = G.grad_phi(self.wl, self.x[cand])
         nn = np.sqrt((nrm * nrm).sum(axis=1, keepdims=True))
         nrm = nrm / np.where(nn > 0, nn, 1.0)
         if lo == 1:
             nrm = -nrm  # march from the low side outwards
-        ph = np.abs(G.phi(self.wl, self.x))
-        band = ph < 6.0 * h
-        inner = band & self.interior
-        for a in range(d):
-            inner &= (self.idx[:, a] > 1) & (self.idx[:, a] < n - 1)
+        known = lo_mask[cand]
+        ip, nrm_ip = cand[known], nrm[known]
+        tgt, nrm_t = cand[~known], nrm[~known]
+        # upwind neighbours: z - sign(n_a) e_a
+        up_nb = np.stack([tgt - np.sign(nrm_t[:, a]).astype(np.int64) * self.stride[a]
+                          for a in range(d)], axis=1)
+        wts = np.abs(nrm_t)
+        self._ext = {"lo_mask": lo_mask, "ip": ip, "nrm_ip": nrm_ip, "tgt": tgt, "up_nb": up_nb,
+                     "wts": wts, "wsum": wts.sum(axis=1)}
+        return self._ext
+
+    def extend_lo(self, Ufull, sweeps=None):
+        """Extend the low-mu side field across Gamma: constant normal
+        derivative (upwind extrapolation of q = n.grad u), then linear
+        extension of u with n.grad u = q.  Returns nodal array."""
+        d, h = self.d, self.h
+        ex = self._extension_setup()
+        lo_mask, ip, nrm_ip = ex["lo_mask"], ex["ip"], ex["nrm_ip"]
+        tgt, up_nb, wts, wsum = ex["tgt"], ex["up_nb"], ex["wts"], ex["wsum"]
         if sweeps is None:
             sweeps = 12
         # q = n . grad u on the low side (central differences if both
         # neighbours are on the low side, otherwise one-sided)
         q = np.zeros(self.N)
-        known_q = lo_mask & inner
-        ip = np.nonzero(known_q)[0]
         for a in range(d):
             up, um = ip + self.stride[a], ip - self.stride[a]
             lu, lm = lo_mask[up], lo_mask[um]
             der = np.where(lu & lm, (Ufull[up] - Ufull[um]) / (2 * h),
                            np.where(lu, (Ufull[up] - Ufull[ip]) / h,
                                     np.where(lm, (Ufull[ip] - Ufull[um]) / h, 0.0)))
-            q[ip] += nrm[ip, a] * der
-        tgt = np.nonzero(inner & ~lo_mask)[0]
-        # upwind neighbours: z - sign(n_a) e_a
-        up_nb = np.stack([tgt - np.sign(nrm[tgt, a]).astype(np.int64) * self.stride[a]
-                          for a in range(d)], axis=1)
-        wts = np.abs(nrm[tgt])
-        wsum = wts.sum(axis=1)
+            q[ip] += nrm_ip[:, a] * der
         for _ in range(sweeps):
             q[tgt] = (wts * q[up_nb]).sum(axis=1) / wsum
         u = Ufull.copy()

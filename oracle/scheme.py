@@ -64,7 +64,16 @@ def lo_side(wl: I.Workload) -> int:
     return 0 if wl.mu_minus < wl.mu_plus else 1
 
 
-def jump_extension(wl: I.Workload, prob: Problem, y: np.ndarray, grad_lo: np.ndarray = None):
+def jump_data(wl: I.Workload, prob: Problem, y: np.ndarray):
+    """Interface data the jump extension needs at nodes y[..., d]: the
+    projection pi(y) (one Newton step), the signed distance, the normal at
+    pi(y), alpha and beta there."""
+    pi, dist, n = G.project(wl, y)
+    return {"alpha": prob.alpha(pi, n), "beta": prob.beta(pi, n), "dist": dist, "n": n}
+
+
+def jump_extension(wl: I.Workload, prob: Problem, y: np.ndarray, grad_lo: np.ndarray = None,
+                   data=None):
     """J(y) = alpha(pi(y)) + dist(y) * j, an extension of [u] = u^+ - u^- off Gamma.
 
     j approximates [d_n u] from mu^+ d_n u^+ - mu^- d_n u^- = beta:
@@ -73,10 +82,11 @@ def jump_extension(wl: I.Workload, prob: Problem, y: np.ndarray, grad_lo: np.nda
       lo = plus:  j = beta/mu^- + (1 - mu^+/mu^-) g,
     with g = n(pi(y)) . grad_lo(y), the lagged normal derivative on the side
     with the smaller coefficient (|1 - mu_lo/mu_hi| < 1).  grad_lo[..., d]
-    is supplied by the caller (central differences of the lo-side field)."""
-    pi, dist, n = G.project(wl, y)
-    al = prob.alpha(pi, n)
-    be = prob.beta(pi, n)
+    is supplied by the caller (central differences of the lo-side field).
+    data = jump_data(wl, prob, y) may be passed instead of y."""
+    if data is None:
+        data = jump_data(wl, prob, y)
+    al, be, dist, n = data["alpha"], data["beta"], data["dist"], data["n"]
     mm, mp = wl.mu_minus, wl.mu_plus
     lo = lo_side(wl)
     if lo < 0:
@@ -87,14 +97,11 @@ def jump_extension(wl: I.Workload, prob: Problem, y: np.ndarray, grad_lo: np.nda
     return al + dist * j
 
 
-def cut_terms(wl: I.Workload, prob: Problem, xc: np.ndarray, h: float, sides: np.ndarray,
-              J: np.ndarray):
-    """Everything of the cut-cell residual that does not depend on U.
-
-    sides[n, 2d+1] node sides (True = minus), J[n, 2d+1] jump extension at the
-    nodes.  Returns dict with face coefficients c[n, 2d] (sum_s mu^s a^s_F),
-    mubar[n], the constant part K[n] of R_p (so that
-    R_p = -(1/h^2) sum_F c_F (U_F - U_0) + K) and the geometry."""
+def cut_static(wl: I.Workload, prob: Problem, xc: np.ndarray, h: float, fvals=None):
+    """The parts of the cut-cell residual that depend on neither U nor J:
+    geometry, face coefficients c[n, 2d] (sum_s mu^s a^s_F), mubar[n], the
+    source sum_s v^s f^s(x_p) and the interface term gamma_p beta(pi(c_p))/h.
+    fvals = (f^-(xc), f^+(xc)) may be passed in precomputed."""
     d = wl.dim
     geom = G.cell_geometry(wl, xc, h)
     mm, mp = wl.mu_minus, wl.mu_plus
@@ -102,6 +109,27 @@ def cut_terms(wl: I.Workload, prob: Problem, xc: np.ndarray, h: float, sides: np
     ap = 1.0 - an
     c = mm * an + mp * ap
     mubar = c.sum(axis=1) / (2 * d)
+    vneg = geom["vneg"]
+    fm, fp = (prob.f_side(0, xc), prob.f_side(1, xc)) if fvals is None else fvals
+    src = vneg * fm + (1.0 - vneg) * fp
+    pic, _, nc = G.project(wl, geom["cen"])
+    bterm = np.where(geom["gamma"] > 0, geom["gamma"] * prob.beta(pic, nc) / h, 0.0)
+    return {"c": c, "mubar": mubar, "an": an, "ap": ap, "src": src, "bterm": bterm, "geom": geom}
+
+
+def cut_terms(wl: I.Workload, prob: Problem, xc: np.ndarray, h: float, sides: np.ndarray,
+              J: np.ndarray, static=None):
+    """Everything of the cut-cell residual that does not depend on U.
+
+    sides[n, 2d+1] node sides (True = minus), J[n, 2d+1] jump extension at the
+    nodes.  Returns dict with face coefficients c[n, 2d] (sum_s mu^s a^s_F),
+    mubar[n], the constant part K[n] of R_p (so that
+    R_p = -(1/h^2) sum_F c_F (U_F - U_0) + K) and the geometry.  static =
+    cut_static(...) of the same cells may be passed in."""
+    d = wl.dim
+    st = cut_static(wl, prob, xc, h) if static is None else static
+    mm, mp = wl.mu_minus, wl.mu_plus
+    an, ap = st["an"], st["ap"]
     # corrections u~^s(y) - U(y)
     corr_m = np.where(sides, 0.0, -J)
     corr_p = np.where(sides, J, 0.0)
@@ -109,12 +137,8 @@ def cut_terms(wl: I.Workload, prob: Problem, xc: np.ndarray, h: float, sides: np
     for F in range(2 * d):
         flux_corr += mm * an[:, F] * (corr_m[:, 1 + F] - corr_m[:, 0])
         flux_corr += mp * ap[:, F] * (corr_p[:, 1 + F] - corr_p[:, 0])
-    vneg = geom["vneg"]
-    src = vneg * prob.f_side(0, xc) + (1.0 - vneg) * prob.f_side(1, xc)
-    pic, _, nc = G.project(wl, geom["cen"])
-    bterm = np.where(geom["gamma"] > 0, geom["gamma"] * prob.beta(pic, nc) / h, 0.0)
-    K = -flux_corr / (h * h) - src + bterm
-    return {"c": c, "mubar": mubar, "K": K, "geom": geom}
+    K = -flux_corr / (h * h) - st["src"] + st["bterm"]
+    return {"c": st["c"], "mubar": st["mubar"], "K": K, "geom": st["geom"]}
 
 
 def cut_residual(U: np.ndarray, terms, h: float) -> np.ndarray:

@@ -161,3 +161,17 @@ def test_mlp_forward_sin_two_hidden_layers_hand_values():
     x = np.array([[0.5, -1.0, 2.0]])
     assert abs(M.forward(wl, nets[0], x)[0] - (2.0 - math.sqrt(2.0))) < 1e-14
     assert abs(M.forward(wl, nets[1], x)[0] - 0.7) < 1e-15
+
+
+def test_fourier_forcing_on_grid_equals_series():
+    """The axis-by-axis evaluation of the forcing at grid nodes (used by the
+    grid judge) equals the series summed mode by mode at every node."""
+    prob = Problem(I.C4)
+    n = 12
+    ax = -1.0 + (2.0 / n) * np.arange(n + 1)
+    i0, i1, i2 = np.meshgrid(np.arange(n + 1), np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    flat = (i0 + (n + 1) * i1 + (n + 1) ** 2 * i2).ravel()
+    x = np.stack([ax[i0.ravel()], ax[i1.ravel()], ax[i2.ravel()]], axis=1)
+    fg = prob.f_grid(n)
+    assert fg.shape == ((n + 1) ** 3,)
+    assert np.allclose(fg[flat], prob.f_side(0, x), rtol=0, atol=1e-11)
