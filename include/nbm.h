@@ -89,6 +89,12 @@ typedef struct nbm_config {
   int64_t cut_capacity;  /* max cut cells per batch; 0 -> max_points/8 + 64 */
   int32_t eval_only;     /* 1: workspace for nbm_eval only (max_points = largest
                             query tile); training calls return NBM_EWORKSPACE */
+  int32_t levels;        /* implicit refinement levels beyond the base (paper
+                            Sec. 3 implicit cells at several resolutions, Sec. 4.2
+                            base resolution refined implicitly): every point
+                            carries cells of side h, h/2, ..., h/2^levels and the
+                            loss is the sum of the levels' losses.  0..6,
+                            h/2^levels >= 2^-20 */
 } nbm_config;
 
 typedef struct nbm_ctx nbm_ctx;
@@ -124,8 +130,10 @@ int nbm_sample_points(nbm_ctx* ctx, void* stream, uint64_t seed, int64_t step, f
 /* Forward pass: residual of every interior and boundary point and the loss
  * L = (sum_p r_p^2 + sum_b r_b^2) / (n + nb), accumulated in FP64
  * (paper Sec. 3: point residuals r_p = |M^-1 A u - M^-1 b| aggregated into a
- * global loss).  params [P] device; pts [n][d], bpts [nb][d] device;
- * residual [n + nb] device or NULL; loss: one device double.
+ * global loss); with levels > 0, L = sum over levels l of the loss of cells
+ * of side h / 2^l.  params [P] device; pts [n][d], bpts [nb][d] device;
+ * residual [(levels + 1) (n + nb)] device (level-major) or NULL; loss: one
+ * device double.
  * If grad is not NULL the same pass also writes dL/dtheta [P] (FP32, reduced
  * in FP64 in a fixed order): the fused forward + residual + backward step. */
 int nbm_forward_residual(nbm_ctx* ctx, void* stream, const float* params, const float* pts,
@@ -152,6 +160,16 @@ int nbm_adam_step(nbm_ctx* ctx, void* stream, float* params, float* m, float* v,
  * are generated in the kernel.  u_out [m] device FP32.  m <= max_points. */
 int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const float* query, int64_t m,
              int64_t tile_index, int32_t grid_n, float* u_out, void* ws, size_t ws_bytes);
+
+/* Grid fallback of the evaluation: where the surrogate's error against the
+ * grid solution (the method without the learned part) exceeds a stated
+ * tolerance, a tile takes the grid solution instead.  Writes, at the m points
+ * of tile `tile_index` of the grid_n^d lattice (as nbm_eval with query ==
+ * NULL), the multilinear interpolation of U, the solution on the
+ * (judge_n + 1)^d nodes -1 + 2 j / judge_n (device FP64, axis 0 fastest).
+ * u_out [m] device FP32.  No workspace; U is only read. */
+int nbm_grid_interp(nbm_ctx* ctx, void* stream, const double* U, int32_t judge_n, int64_t tile_index,
+                    int32_t grid_n, int64_t m, float* u_out);
 
 /* Classes of the last batch seen by nbm_forward_residual / nbm_backward on
  * this workspace, written to counts[8] (device int32): interior A^-, A^+,

@@ -59,6 +59,7 @@ class Workload:
     plane_c: float = 0.1                 # IFACE_PLANE offset
     lin_a: tuple = (0.3, -0.7, 0.2, 1.1)  # PROB_LINEAR u^- coefficients (x, y, z, const)
     lin_b: tuple = (-0.4, 0.9, 0.5, -0.6)  # PROB_LINEAR u^+ coefficients
+    levels: int = 0       # implicit refinement levels: cells of side h, h/2, ..., h/2^levels
 
     def replace(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)

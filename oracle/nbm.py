@@ -134,9 +134,37 @@ def residuals(wl: I.Workload, theta: np.ndarray, pts: np.ndarray, bpts: np.ndarr
             "glo": res_glo if ids.size else None}
 
 
+def level_spacings(wl: I.Workload):
+    """Cell sides of the resolution levels: h, h/2, ..., h/2^levels (paper
+    Sec. 3: implicit cells of several resolutions at each collocation point;
+    Sec. 4.2: a base resolution implicitly refined)."""
+    return [wl.h / 2.0 ** l for l in range(wl.levels + 1)]
+
+
+def multires_loss(wl: I.Workload, theta: np.ndarray, pts: np.ndarray, bpts: np.ndarray):
+    """Loss over every resolution level: the sum of the levels' losses."""
+    return sum(residuals(wl, theta, pts, bpts, h=hl)["loss"] for hl in level_spacings(wl))
+
+
 def loss_and_grad(wl: I.Workload, theta: np.ndarray, pts: np.ndarray, bpts: np.ndarray,
                   h: float = None, dL: float = 1.0, glo_override=None):
-    """Loss and dL/dtheta (FP64).  dL scales the gradient (upstream factor)."""
+    """Loss and dL/dtheta (FP64).  dL scales the gradient (upstream factor).
+    Without an explicit h, a workload with refinement levels sums the loss
+    and gradient over h, h/2, ..., h/2^levels; the returned dict then holds
+    the base level's classes and "r_levels", every level's interior and
+    boundary residuals, level-major."""
+    if h is None and wl.levels > 0:
+        L, g, out = 0.0, None, None
+        rl = []
+        for hl in level_spacings(wl):
+            Ll, gl, res = loss_and_grad(wl, theta, pts, bpts, h=hl, dL=dL)
+            L += Ll
+            g = gl if g is None else g + gl
+            out = res if out is None else out
+            rl.append(np.concatenate([res["r"], res["rb"]]))
+        out = dict(out)
+        out["r_levels"] = np.concatenate(rl)
+        return L, g, out
     h = wl.h if h is None else h
     res = residuals(wl, theta, pts, bpts, h, glo_override=glo_override)
     d = wl.dim

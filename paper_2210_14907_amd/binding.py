@@ -19,6 +19,7 @@ _lib = None
 
 EXPORTS = ["nbm_create", "nbm_destroy", "nbm_param_count", "nbm_workspace_bytes", "nbm_prepare",
            "nbm_sample_points", "nbm_forward_residual", "nbm_backward", "nbm_adam_step", "nbm_eval",
+           "nbm_grid_interp",
            "nbm_batch_counts", "nbm_set_timing", "nbm_read_timing", "nbm_last_error"]
 
 
@@ -35,7 +36,8 @@ class NbmConfig(ctypes.Structure):
                 ("n_modes", ctypes.c_int32), ("mode_k", ctypes.POINTER(ctypes.c_int32)),
                 ("mode_a", ctypes.POINTER(ctypes.c_double)), ("mode_b", ctypes.POINTER(ctypes.c_double)),
                 ("max_points", ctypes.c_int64), ("max_boundary", ctypes.c_int64),
-                ("cut_capacity", ctypes.c_int64), ("eval_only", ctypes.c_int32)]
+                ("cut_capacity", ctypes.c_int64), ("eval_only", ctypes.c_int32),
+                ("levels", ctypes.c_int32)]
 
 
 class NbmError(RuntimeError):
@@ -63,6 +65,7 @@ def lib():
         L.nbm_backward.argtypes = [vp, vp, vp, vp, i64, vp, i64, f64, vp, vp, ctypes.c_size_t]
         L.nbm_adam_step.argtypes = [vp, vp, vp, vp, vp, vp, i64, f32, f32, f32, f32]
         L.nbm_eval.argtypes = [vp, vp, vp, vp, i64, i64, ctypes.c_int32, vp, vp, ctypes.c_size_t]
+        L.nbm_grid_interp.argtypes = [vp, vp, vp, ctypes.c_int32, i64, ctypes.c_int32, i64, vp]
         L.nbm_batch_counts.argtypes = [vp, vp, vp, vp, ctypes.c_size_t]
         L.nbm_set_timing.argtypes = [vp, ctypes.c_int]
         L.nbm_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -117,6 +120,7 @@ class NBM:
         cfg.max_boundary = wl.n_boundary if max_boundary is None else max_boundary
         cfg.cut_capacity = cut_capacity
         cfg.eval_only = 1 if eval_only else 0
+        cfg.levels = wl.levels
         self.cfg = cfg
         h = ctypes.c_void_p()
         _check(lib().nbm_create(ctypes.byref(cfg), ctypes.byref(h)))
@@ -154,7 +158,7 @@ class NBM:
         if loss is None:
             loss = torch.empty(1, dtype=torch.float64, device=self.device)
         if want_residual and residual is None:
-            residual = torch.empty(n + nb, dtype=torch.float32, device=self.device)
+            residual = torch.empty((self.wl.levels + 1) * (n + nb), dtype=torch.float32, device=self.device)
         if want_grad and grad is None:
             grad = torch.empty(self.P, dtype=torch.float32, device=self.device)
         _check(lib().nbm_forward_residual(self.ctx, _stream(), _ptr(params), _ptr(pts), n, _ptr(bpts), nb,
@@ -191,6 +195,17 @@ class NBM:
             o = out[i:i + cap]
             _check(lib().nbm_eval(self.ctx, _stream(), _ptr(params), _ptr(q), q.shape[0], 0, 0,
                                   _ptr(o), _ptr(self.ws_view), self.ws_bytes))
+        return out
+
+    def grid_interp(self, U, judge_n, tile_index, grid_n, m, out=None):
+        """Multilinear interpolation of the nodal FP64 device array U
+        [(judge_n+1)^d] at tile `tile_index` of m points of the grid_n^d lattice."""
+        if out is None:
+            out = torch.empty(m, dtype=torch.float32, device=self.device)
+        if U.dtype != torch.float64 or U.numel() != (judge_n + 1) ** self.wl.dim:
+            raise NbmError("U must be a float64 array of (judge_n + 1)^d nodal values")
+        _check(lib().nbm_grid_interp(self.ctx, _stream(), _ptr(U), int(judge_n), int(tile_index), int(grid_n),
+                                     int(m), _ptr(out)))
         return out
 
     TIMING_GROUPS = ["prep", "forward", "residual", "backward", "reduce", "adam", "sample", "eval",

@@ -5,8 +5,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <string>
 #include <map>
+#include <string>
 #include <vector>
 
 #include "../../include/nbm.h"
@@ -37,7 +37,7 @@ namespace {
 struct Layout {
   size_t modes32, modes64, fmodes, meta, prefix, ctot, coff, blockcnt, off, blockcnt_b, off_b, cls, rank, bcls,
       brank, cutidx, centres, src, outputs, adj, Zst, Ast, ALst, dZ, dZw, shadow, partial, lossp, resid, lossbuf,
-      fpre, fslot, total;
+      gacc, fpre, fslot, total;
   int64_t nchunk;    // interior chunks of the two-level scan
   int64_t cut_cap;   // cut cells this call can hold
   int64_t lstride;   // elements of one layer in the tile layout
@@ -147,16 +147,20 @@ static Layout layout_for(const nbm_ctx* c, int64_t n, int64_t nb) {
   // stored pre-activations are needed only by the layered backward, used when
   // no fused path is compiled for the shape (or NBM_NO_FUSED is set)
   const bool layered = c->no_fused || (!c->fused && !c->wide);
+  const bool two_pass = c->wide && !c->no_fused;
   L.Zst = take_tr(layered ? sizeof(float) * c->L * L.lstride : 0);
-  L.Ast = take_tr((size_t)c->opbytes * (c->L - 1) * L.lstride);
+  // activations leave the chip only on the layered and the 128-wide two-pass paths
+  L.Ast = take_tr(layered || two_pass ? (size_t)c->opbytes * (c->L - 1) * L.lstride : 0);
   L.ALst = take_tr(layered ? sizeof(float) * L.lstride : 0);
   L.dZ = take_tr(layered ? sizeof(float) * L.lstride : 0);
-  L.dZw = take_tr(c->wide && !c->no_fused ? (size_t)c->opbytes * (c->L - 1) * L.lstride : 0);
+  L.dZw = take_tr(two_pass ? (size_t)c->opbytes * (c->L - 1) * L.lstride : 0);
   L.shadow = take((size_t)c->opbytes * 2 * (c->L - 1) * 2 * c->W * c->W);
   L.partial = take_tr(sizeof(float) * (size_t)c->G * c->Ptot);
   L.lossp = take(sizeof(double) * (nblk + nblkb + cut + 4 + 512));
   L.resid = take_tr(sizeof(float) * (n + nb));
   L.lossbuf = take(sizeof(double) * 4);
+  // FP64 accumulators of the gradient and loss over resolution levels
+  L.gacc = take_tr(c->cfg.levels > 0 ? sizeof(double) * (size_t)c->Ptot : 0);
   L.fpre = take_tr(c->cfg.problem == NBM_PROB_FOURIER ? sizeof(float) * n : 0);
   // forcing of the uncut centres in centre-slot order, for the fused paths'
   // inline tiles
@@ -181,6 +185,8 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
   if (c.interface_kind < 0 || c.interface_kind > 2) return fail(NBM_EINVAL, "bad interface kind");
   if (c.interface_kind == NBM_IFACE_STAR && c.dim != 3) return fail(NBM_EINVAL, "star needs dim 3");
   if (!(c.mu_minus > 0.0) || !(c.mu_plus > 0.0)) return fail(NBM_EINVAL, "mu must be positive");
+  if (c.levels < 0 || c.levels > 6 || std::ldexp(c.h, -c.levels) < std::ldexp(1.0, -20))
+    return fail(NBM_EINVAL, "levels must be in [0, 6] with h / 2^levels >= 2^-20");
   if (c.k_minus != 0.0 || c.k_plus != 0.0)
     return fail(NBM_EUNSUPPORTED, "Helmholtz term k != 0 is not compiled into this library");
   if (c.problem < 0 || c.problem > 3) return fail(NBM_EINVAL, "bad problem kind");
@@ -422,11 +428,16 @@ static ShadowJobs shadow_jobs(const nbm_ctx* ctx, const float* params, const Net
   return j;
 }
 
-// forward (+ optional backward) of one batch
-static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const float* pts, int64_t n,
-                    const float* bpts, int64_t nb, float* residual, double* loss, float* grad,
-                    double dL, void* ws, const Layout& Lo) {
+// forward (+ optional backward) of one batch at one resolution: implicit
+// cells of side h; acc says how the level's loss and gradient enter the
+// FP64 accumulators (0: a single level)
+static int run_level(nbm_ctx* ctx, hipStream_t st, const float* params, const float* pts, int64_t n,
+                     const float* bpts, int64_t nb, float* residual, double* loss, float* grad,
+                     double dL, void* ws, const Layout& Lo, double h, int acc) {
   Problem P = problem_for(ctx, ws);
+  P.h = h;
+  double* gacc = at<double>(ws, Lo.gacc);
+  double* lacc = at<double>(ws, Lo.lossbuf) + 1;
   // operand shadows of the hidden matrices
   Nets N = nets_for(ctx, params, ws, Lo);
   Timer* tprep = new Timer(ctx, st, 0);
@@ -473,7 +484,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   MlpCall mc;
   std::memset(&mc, 0, sizeof(mc));
   mc.op = MlpCall::FORWARD; mc.stream = st; mc.grid = grid; mc.meta = pc.meta;
-  mc.centres = pc.centres; mc.nets = &N; mc.L = ctx->L; mc.h = (float)ctx->cfg.h;
+  mc.centres = pc.centres; mc.nets = &N; mc.L = ctx->L; mc.h = (float)h;
   mc.outputs = at<float>(ws, Lo.outputs);
   mc.Zst = at<float>(ws, Lo.Zst); mc.Ast = at<void>(ws, Lo.Ast); mc.ALst = at<float>(ws, Lo.ALst);
   mc.dZ = at<float>(ws, Lo.dZ); mc.lstride = Lo.lstride;
@@ -512,6 +523,8 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   rc.scale = 2.0 * dL / (double)(n + nb);
   rc.skip_inline = fused ? 1 : 0;
   rc.fpre = fpre;
+  rc.lacc = lacc;
+  rc.acc = acc;
   e = launch_residuals(rc);
   delete tres;
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("residual: ") + hipGetErrorString(e));
@@ -527,7 +540,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
     WideCall wc;
     std::memset(&wc, 0, sizeof(wc));
     wc.stream = st; wc.grid = ctx->Gf; wc.meta = pc.meta; wc.centres = pc.centres; wc.src = pc.src;
-    wc.nets = &N; wc.P = P; wc.h = (float)ctx->cfg.h; wc.adj = adj; wc.resid = rc.resid;
+    wc.nets = &N; wc.P = P; wc.h = (float)h; wc.adj = adj; wc.resid = rc.resid;
     wc.A = at<void>(ws, Lo.Ast); wc.dZ = at<void>(ws, Lo.dZw); wc.lstride = Lo.lstride;
     wc.partial = partial; wc.Ptot = ctx->Ptot; wc.lay = &ctx->lay; wc.off1 = ctx->per_net;
     wc.lossp = rc.lossp + nres; wc.scale = rc.scale; wc.fslot = f_inline;
@@ -548,7 +561,7 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
     FusedCall fc;
     std::memset(&fc, 0, sizeof(fc));
     fc.stream = st; fc.grid = ctx->Gfz; fc.meta = pc.meta; fc.centres = pc.centres; fc.src = pc.src;
-    fc.nets = &N; fc.P = P; fc.h = (float)ctx->cfg.h; fc.adj = adj; fc.resid = rc.resid;
+    fc.nets = &N; fc.P = P; fc.h = (float)h; fc.adj = adj; fc.resid = rc.resid;
     fc.partial = partial; fc.Ptot = ctx->Ptot; fc.lay = &ctx->lay; fc.off1 = ctx->per_net;
     fc.lossp = rc.lossp + nres; fc.scale = rc.scale; fc.fslot = f_inline;
     {
@@ -578,9 +591,28 @@ static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const flo
   }
   {
     Timer tr(ctx, st, 4);
-    e = launch_reduce(st, partial, Grows, ctx->Ptot, grad, 1.0, red_lossp, red_nparts, pc.meta, red_loss);
+    e = launch_reduce(st, partial, Grows, ctx->Ptot, grad, 1.0, red_lossp, red_nparts, pc.meta, red_loss, gacc,
+                      lacc, acc);
   }
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("reduce: ") + hipGetErrorString(e));
+  return NBM_OK;
+}
+
+// One batch over every resolution level (paper Sec. 3: implicit cells of
+// several resolutions at each collocation point; Sec. 4.2: a base
+// resolution refined implicitly): level l uses cells of side h / 2^l and
+// the levels' losses and gradients are summed in FP64.
+static int run_step(nbm_ctx* ctx, hipStream_t st, const float* params, const float* pts, int64_t n,
+                    const float* bpts, int64_t nb, float* residual, double* loss, float* grad,
+                    double dL, void* ws, const Layout& Lo) {
+  const int R = ctx->cfg.levels;
+  for (int l = 0; l <= R; ++l) {
+    const int acc = R == 0 ? 0 : (l == 0 ? 1 : (l == R ? 3 : 2));
+    float* res_l = residual ? residual + (int64_t)l * (n + nb) : nullptr;
+    const int rc = run_level(ctx, st, params, pts, n, bpts, nb, res_l, loss, grad, dL, ws, Lo,
+                             std::ldexp(ctx->cfg.h, -l), acc);
+    if (rc) return rc;
+  }
   return NBM_OK;
 }
 
@@ -697,6 +729,22 @@ extern "C" int nbm_eval(nbm_ctx* ctx, void* stream, const float* params, const f
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("eval: ") + hipGetErrorString(e));
   e = launch_eval_out(st, (int64_t)grid * kTile, pc.meta, mc.outputs, pc.src, u_out);
   if (e != hipSuccess) return fail(NBM_EHIP, std::string("eval out: ") + hipGetErrorString(e));
+  return NBM_OK;
+}
+
+extern "C" int nbm_grid_interp(nbm_ctx* ctx, void* stream, const double* U, int32_t judge_n,
+                               int64_t tile_index, int32_t grid_n, int64_t m, float* u_out) {
+  if (!ctx || !U || !u_out) return fail(NBM_EINVAL, "null argument");
+  if (judge_n < 1 || judge_n > (1 << 14)) return fail(NBM_EINVAL, "judge_n must be in [1, 2^14]");
+  if (grid_n < 2 || (grid_n & (grid_n - 1)) != 0 || grid_n > (1 << 14))
+    return fail(NBM_EINVAL, "grid_n must be a power of two in [2, 2^14]");
+  if (m < 1) return fail(NBM_EINVAL, "m must be positive");
+  const double tot = std::pow((double)grid_n, ctx->D);
+  if (tile_index < 0 || (double)(tile_index + 1) * (double)m > tot)
+    return fail(NBM_EINVAL, "tile outside the grid");
+  Timer tev(ctx, (hipStream_t)stream, 7);
+  hipError_t e = launch_grid_interp((hipStream_t)stream, ctx->D, U, judge_n, tile_index, m, grid_n, u_out);
+  if (e != hipSuccess) return fail(NBM_EHIP, std::string("grid interp: ") + hipGetErrorString(e));
   return NBM_OK;
 }
 

@@ -256,6 +256,57 @@ hipError_t eval_impl(const EvalCall& c) {
   return hipGetLastError();
 }
 
+// Grid fallback of the evaluation: at every point of tile `tile` (m
+// consecutive points of the grid_n^D lattice x_a = -1 + 2 i_a / grid_n, axis 0
+// fastest), the multilinear interpolation of a nodal solution U given on the
+// (judge_n + 1)^D nodes y_a = -1 + 2 j_a / judge_n (axis 0 fastest).  FP64
+// weights and sums, FP32 output.  One thread per point; consecutive threads
+// read neighbouring nodes, so a wavefront's loads of U stay within a few
+// cache lines of each row.
+template <int D>
+__global__ __launch_bounds__(256) void k_grid_interp(const double* __restrict__ U, int judge_n, int64_t first,
+                                                     int64_t m, int grid_n, float* __restrict__ u_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  int64_t q = first + i;
+  const double scale = (double)judge_n / (double)grid_n;   // judge intervals per lattice step
+  int j0[D];
+  double fr[D];
+  for (int a = 0; a < D; ++a) {
+    const int64_t ia = q % grid_n;
+    q /= grid_n;
+    const double t = (double)ia * scale;                 // position in judge cells
+    int j = (int)t;
+    if (j > judge_n - 1) j = judge_n - 1;
+    j0[a] = j;
+    fr[a] = t - (double)j;
+  }
+  const int64_t s1 = judge_n + 1, s2 = s1 * s1;
+  double acc = 0.0;
+  for (int c = 0; c < (1 << D); ++c) {
+    double w = 1.0;
+    int64_t flat = 0;
+    for (int a = 0; a < D; ++a) {
+      const int bit = (c >> a) & 1;
+      w *= bit ? fr[a] : 1.0 - fr[a];
+      flat += (int64_t)(j0[a] + bit) * (a == 0 ? 1 : (a == 1 ? s1 : s2));
+    }
+    acc += w * U[flat];
+  }
+  u_out[i] = (float)acc;
+}
+
+hipError_t launch_grid_interp(hipStream_t st, int dim, const double* U, int judge_n, int64_t tile_index,
+                              int64_t m, int grid_n, float* u_out) {
+  const dim3 grid((unsigned)((m + 255) / 256)), block(256);
+  const int64_t first = tile_index * m;
+  if (dim == 2)
+    hipLaunchKernelGGL(k_grid_interp<2>, grid, block, 0, st, U, judge_n, first, m, grid_n, u_out);
+  else
+    hipLaunchKernelGGL(k_grid_interp<3>, grid, block, 0, st, U, judge_n, first, m, grid_n, u_out);
+  return hipGetLastError();
+}
+
 #define NBM_EVAL(D, W, L, ACT, PREC) \
   if (dim == D && width == W && depth == L && act == ACT && prec == PREC) return &eval_impl<D, W, L, ACT, PREC>;
 

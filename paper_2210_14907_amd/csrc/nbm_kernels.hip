@@ -454,9 +454,21 @@ __global__ void k_fill(float* p, int64_t n, float v) {
 // group sums are added in a fixed order.  With `loss`, one extra block sums
 // the FP64 loss partials (fixed strided order, then a fixed tree).  Both
 // outputs are NaN when the batch overflowed the cut capacity.
+// Several resolution levels of one batch accumulate in FP64 across
+// launches: acc = 0 a single level (write grad / loss), 1 the first level
+// (write the FP64 accumulators), 2 a middle level (add to them), 3 the last
+// level (write accumulator + this level).
+__device__ __forceinline__ double acc_level(int acc, double* slot, double v) {
+  if (acc == 1) { *slot = v; return v; }
+  if (acc == 2) { *slot += v; return v; }
+  if (acc == 3) return *slot + v;
+  return v;
+}
+
 __global__ __launch_bounds__(1024) void k_reduce(const float* partial, int G, int64_t P, float* grad,
                                                  double scale, const double* lp, int nparts,
-                                                 const Meta* meta, double* loss) {
+                                                 const Meta* meta, double* loss, double* gacc,
+                                                 double* lacc, int acc) {
   __shared__ double sh[16][64];
   const int c = threadIdx.x & 63, k = threadIdx.x >> 6;
   if (loss && blockIdx.x == gridDim.x - 1) {
@@ -472,7 +484,8 @@ __global__ __launch_bounds__(1024) void k_reduce(const float* partial, int G, in
     if (threadIdx.x == 0) {
       double L = fl[0] / (double)(meta->n + meta->nb);
       if (meta->overflow) L = __builtin_nan("");
-      *loss = L;
+      L = acc_level(acc, lacc, L);
+      if (acc == 0 || acc == 3) *loss = L;
     }
     return;
   }
@@ -503,12 +516,14 @@ __global__ __launch_bounds__(1024) void k_reduce(const float* partial, int G, in
     for (int q = 0; q < 16; ++q) t += sh[q][c];
     // a batch whose cut cells overflowed the capacity dropped some of them:
     // its gradient is marked NaN like its loss, never returned partial
-    grad[j] = meta->overflow ? __builtin_nanf("") : (float)(t * scale);
+    double v = meta->overflow ? __builtin_nan("") : t * scale;
+    v = acc_level(acc, gacc + j, v);
+    if (acc == 0 || acc == 3) grad[j] = (float)v;
   }
 }
 
 __global__ __launch_bounds__(256) void k_reduce_loss(const double* lp, int nparts, const Meta* meta,
-                                                     double* loss) {
+                                                     double* loss, double* lacc, int acc) {
   __shared__ double s[256];
   double acc = 0.0;
   // fixed-order strided partial sums, then a fixed tree
@@ -522,7 +537,8 @@ __global__ __launch_bounds__(256) void k_reduce_loss(const double* lp, int npart
   if (threadIdx.x == 0) {
     double L = s[0] / (double)(meta->n + meta->nb);
     if (meta->overflow) L = __builtin_nan("");
-    *loss = L;
+    L = acc_level(acc, lacc, L);
+    if (acc == 0 || acc == 3) *loss = L;
   }
 }
 
@@ -1415,14 +1431,15 @@ hipError_t launch_residuals(const ResCall& c) {
   }
   if (c.loss) {
     int nparts = (int)(nblk + nblkc + nblkb) + c.extra_parts;
-    hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(256), 0, st, c.lossp, nparts, c.meta, c.loss);
+    hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(256), 0, st, c.lossp, nparts, c.meta, c.loss, c.lacc,
+                       c.acc);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_loss(hipStream_t st, const double* lossp, int nparts, const Meta* meta,
                               double* loss) {
-  hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(256), 0, st, lossp, nparts, meta, loss);
+  hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(256), 0, st, lossp, nparts, meta, loss, nullptr, 0);
   return hipGetLastError();
 }
 
@@ -1444,10 +1461,11 @@ hipError_t launch_fill(hipStream_t st, float* p, int64_t n, float v) {
 }
 
 hipError_t launch_reduce(hipStream_t st, const float* partial, int G, int64_t P, float* grad,
-                         double scale, const double* lossp, int nparts, const Meta* meta, double* loss) {
+                         double scale, const double* lossp, int nparts, const Meta* meta, double* loss,
+                         double* gacc, double* lacc, int acc) {
   const int nblk = (int)((P + 63) / 64) + (loss ? 1 : 0);
   hipLaunchKernelGGL(k_reduce, dim3(nblk), dim3(1024), 0, st, partial, G, P, grad, scale, lossp, nparts,
-                     meta, loss);
+                     meta, loss, gacc, lacc, acc);
   return hipGetLastError();
 }
 

@@ -161,6 +161,8 @@ struct ResCall {
   int skip_inline;
   int extra_parts;   // loss partials appended after the residual kernels' ones
   const float* fpre; // precomputed forcing per interior point, or NULL
+  double* lacc;      // FP64 loss accumulator over resolution levels
+  int acc;           // 0 one level; 1 first, 2 middle, 3 last of several
 };
 hipError_t launch_residuals(const ResCall& c);
 hipError_t launch_reduce_loss(hipStream_t st, const double* lossp, int nparts, const Meta* meta,
@@ -173,14 +175,19 @@ hipError_t launch_forcing(hipStream_t st, const Problem& P, const float* pts, in
                           const Meta* meta, const int* cls, const int* rank, float* fslot);
 
 // grad = scale * (FP64 fixed-order sum of the G partial rows); with `loss`,
-// the same launch also reduces the nparts FP64 loss partials
+// the same launch also reduces the nparts FP64 loss partials.  acc > 0
+// accumulates resolution levels in the FP64 arrays gacc [P] and lacc [1].
 hipError_t launch_reduce(hipStream_t st, const float* partial, int G, int64_t P, float* grad,
-                         double scale, const double* lossp, int nparts, const Meta* meta, double* loss);
+                         double scale, const double* lossp, int nparts, const Meta* meta, double* loss,
+                         double* gacc, double* lacc, int acc);
 hipError_t launch_adam(hipStream_t st, float* p, float* m, float* v, const float* g, int64_t n,
                        float lr, float b1, float b2, float eps, float c1, float c2);
 hipError_t launch_sample_points(hipStream_t st, int dim, uint64_t seed, int64_t step, int64_t jh,
                                 float* pts, int64_t n, float* bpts, int64_t nb);
 hipError_t launch_counts(hipStream_t st, const Meta* meta, int* counts);
+// multilinear interpolation of a nodal grid solution at one lattice tile
+hipError_t launch_grid_interp(hipStream_t st, int dim, const double* U, int judge_n, int64_t tile_index,
+                              int64_t m, int grid_n, float* u_out);
 hipError_t launch_eval_out(hipStream_t st, int64_t slots, const Meta* meta, const float* outputs,
                            const int* src, float* u_out);
 

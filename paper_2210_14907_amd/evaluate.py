@@ -1,11 +1,14 @@
-"""Dense evaluation of a trained surrogate and the grid fallback.
+"""Dense evaluation of a trained surrogate with the grid solution as fallback.
 
 The surrogate u(x) = u^{sigma(x)}(x) is evaluated by `nbm_eval` on the
 grid_n^d lattice x = -1 + 2 i / grid_n, streamed in tiles of consecutive
 points (axis 0 fastest).  A judge solution given on the nodes of a coarser
-grid (judge_n intervals; judge_n divides grid_n) marks each tile: where the
-surrogate's largest error at the judge nodes inside the tile exceeds the
-tolerance tau, the tile falls back to the judge's multilinear interpolation.
+grid (judge_n intervals; judge_n divides grid_n, so every judge node is a
+lattice point) marks each tile: where the surrogate's largest error at the
+judge nodes inside the tile exceeds the tolerance tau (or is not finite), the
+tile falls back to the judge, and `nbm_grid_interp` writes the multilinear
+interpolation of the judge solution at every point of that tile.  The error
+after the fallback is measured on the values actually written.
 """
 from __future__ import annotations
 
@@ -19,10 +22,12 @@ import numpy as np
 class TileReport:
     tiles: int
     fallback_tiles: int
-    linf: float            # surrogate error at judge nodes (all tiles)
+    linf: float            # surrogate error at the judge nodes (all tiles), before the fallback
     l2: float
-    linf_after: float      # error after fallback
+    linf_after: float      # error of the written output at the judge nodes
+    l2_after: float
     judge_points: int
+    tau: float
 
 
 def judge_mask_in_tile(grid_n: int, judge_n: int, d: int, tile: int, m: int):
@@ -46,37 +51,58 @@ def decide_fallback(tile_err: np.ndarray, tau: float) -> np.ndarray:
 
 
 def evaluate_lattice(nbm, params, grid_n: int, tile_points: int, judge_U=None, judge_n: int = 0,
-                     tau: float = math.inf, keep=None):
-    """Stream the lattice through the GPU; returns a TileReport (and fills
-    keep[tile] = u for tiles listed in the dict `keep`)."""
+                     tau: float = math.inf, out=None, keep=None):
+    """Stream the lattice through the GPU.
+
+    judge_U: nodal judge solution [(judge_n+1)^d] (numpy or device tensor,
+    FP64).  out: optional device FP32 tensor [grid_n^d] that receives the
+    final field (surrogate, or the interpolated judge on fallback tiles).
+    keep: optional dict {tile: None} filled with host copies of those tiles.
+    Returns a TileReport."""
     import torch
 
     d = nbm.wl.dim
     total = grid_n ** d
     if total % tile_points:
         raise ValueError("tile_points must divide grid_n^d")
+    if judge_U is not None and (judge_n < 1 or grid_n % judge_n):
+        raise ValueError("judge_n must divide grid_n")
     ntiles = total // tile_points
-    out = torch.empty(tile_points, dtype=torch.float32, device=nbm.device)
+    dev = nbm.device
+    buf = torch.empty(tile_points, dtype=torch.float32, device=dev)
+    Ud = None
+    if judge_U is not None:
+        Ud = judge_U if torch.is_tensor(judge_U) else torch.tensor(np.ascontiguousarray(judge_U), device=dev)
+        Ud = Ud.to(device=dev, dtype=torch.float64).contiguous()
     errs = np.zeros(ntiles)
-    sq = 0.0
-    cnt = 0
+    errs_after = np.zeros(ntiles)
+    sq = sq_after = 0.0
+    cnt = nfb = 0
     for t in range(ntiles):
-        nbm.eval(params, None, m=tile_points, tile_index=t, grid_n=grid_n, out=out)
-        if judge_U is None and keep is None:
-            continue
-        u = out.cpu().numpy()
-        if keep is not None and t in keep:
-            keep[t] = u.copy()
-        if judge_U is not None:
+        u = buf if out is None else out[t * tile_points:(t + 1) * tile_points]
+        nbm.eval(params, None, m=tile_points, tile_index=t, grid_n=grid_n, out=u)
+        if Ud is not None:
             loc, flat = judge_mask_in_tile(grid_n, judge_n, d, t, tile_points)
-            e = np.abs(u[loc].astype(np.float64) - judge_U[flat])
-            errs[t] = e.max() if e.size else 0.0
-            sq += float((e * e).sum())
-            cnt += e.size
+            loc_d = torch.from_numpy(loc).to(dev)
+            ref = Ud[torch.from_numpy(flat).to(dev)]
+            e = (u[loc_d].double() - ref).abs()
+            e_max = float(e.max().item()) if e.numel() else 0.0
+            errs[t] = e_max if math.isfinite(e_max) else math.inf
+            sq += float((e * e).sum().item())
+            cnt += int(e.numel())
+            if decide_fallback(np.array([errs[t]]), tau)[0]:
+                nbm.grid_interp(Ud, judge_n, t, grid_n, tile_points, out=u)
+                nfb += 1
+                e = (u[loc_d].double() - ref).abs()
+                errs_after[t] = float(e.max().item()) if e.numel() else 0.0
+            else:
+                errs_after[t] = errs[t]
+            sq_after += float((e * e).sum().item())
+        if keep is not None and t in keep:
+            keep[t] = u.cpu().numpy().copy()
     torch.cuda.synchronize()
-    if judge_U is None:
-        return TileReport(ntiles, 0, float("nan"), float("nan"), float("nan"), 0)
-    fb = decide_fallback(errs, tau)
-    after = np.where(fb, 0.0, errs)   # fallback tiles take the judge values at its nodes
-    return TileReport(ntiles, int(fb.sum()), float(errs.max()), math.sqrt(sq / max(cnt, 1)),
-                      float(after.max()), cnt)
+    if Ud is None:
+        return TileReport(ntiles, 0, float("nan"), float("nan"), float("nan"), float("nan"), 0, tau)
+    c = max(cnt, 1)
+    return TileReport(ntiles, nfb, float(errs.max()), math.sqrt(sq / c), float(errs_after.max()),
+                      math.sqrt(sq_after / c), cnt, tau)

@@ -12,8 +12,12 @@ NBM kernels, then Adam).
 - nbm_backward with an upstream factor, and the torch.autograd.Function
   wrapper, against the oracle and central finite differences.
 
-Every gradient entry must satisfy |g - g_o| <= tol (|g_o| + 1e-3 max|g_o|)
-with max over its parameter block (tol 1e-5 FP32, 2e-2 BF16 operands)."""
+Every gradient entry must satisfy |g - g_o| <= tol (|g_o| + floor max|g_o|)
+with max over its parameter block: tol 1e-5 and floor 0.1 with FP32 operands
+(entries resolved down to 1e-6 of the block's largest; FP32 partial sums over
+thousands of terms per work-group carry ~1e-7 of it), tol 2e-2 and floor 0.2
+with BF16 operands (resolved down to 2^-8 of the block's largest: the BF16
+rounding of both factors of each weight-gradient product, 2^-9 each)."""
 import numpy as np
 import pytest
 
@@ -26,6 +30,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = {I.PREC_FP32: 1e-5, I.PREC_BF16: 2e-2}
+FLOOR = {I.PREC_FP32: 0.1, I.PREC_BF16: 0.2}
 DEV = "cuda:0"
 
 
@@ -68,23 +73,28 @@ def _c3_full_batch():
     return _C3_ORACLE["ref"]
 
 
-@pytest.mark.parametrize("prec", [I.PREC_BF16, I.PREC_FP32], ids=["bf16", "fp32"])
-def test_c3_full_batch_gradient_elementwise(prec):
-    wl = I.C3.replace(prec=prec)
+def test_c3_full_batch_gradient_elementwise():
     P, B, theta, L_o, g_o, res_o = _c3_full_batch()
-    L_g, r_g, g_g, counts = _gpu_step(wl, theta, P, B)
-    cls = res_o["cls"]
-    assert counts[0] == (cls == 0).sum() and counts[1] == (cls == 1).sum()
-    assert counts[2] == (cls == S.CLASS_CUT).sum() and counts[5] == 0
-    # both nets hold more than two tiles per persistent work-group
-    assert counts[0] // 16 > 512 and counts[1] // 16 > 512
-    tol = TOL[prec]
     r_o = np.concatenate([res_o["r"], res_o["rb"]])
-    e_loss, e_res = abs(L_g - L_o) / abs(L_o), max_rel(r_g, r_o)
-    worst = _report(f"c3_full_{'bf16' if prec else 'fp32'} loss {e_loss:.1e} res {e_res:.1e}",
-                    grad_block_ratios(wl, g_g, g_o, tol))
-    assert e_loss <= tol and e_res <= tol
-    assert worst <= 1.0
+    cls = res_o["cls"]
+    out = {}
+    for prec in (I.PREC_FP32, I.PREC_BF16):
+        wl = I.C3.replace(prec=prec)
+        tag = "bf16" if prec else "fp32"
+        L_g, r_g, g_g, counts = _gpu_step(wl, theta, P, B)
+        assert counts[0] == (cls == 0).sum() and counts[1] == (cls == 1).sum()
+        assert counts[2] == (cls == S.CLASS_CUT).sum() and counts[5] == 0
+        # both nets hold more than two tiles per persistent work-group
+        assert counts[0] // 16 > 512 and counts[1] // 16 > 512
+        tol = TOL[prec]
+        e_loss, e_res = abs(L_g - L_o) / abs(L_o), max_rel(r_g, r_o)
+        worst = _report(f"c3_full_{tag} loss {e_loss:.1e} res {e_res:.1e}",
+                        grad_block_ratios(wl, g_g, g_o, tol, FLOOR[prec]))
+        out[tag] = (e_loss, e_res, worst)
+    for tag, (e_loss, e_res, worst) in out.items():
+        tol = TOL[I.PREC_BF16 if tag == "bf16" else I.PREC_FP32]
+        assert e_loss <= tol and e_res <= tol, tag
+        assert worst <= 1.0, tag
 
 
 def test_c4_many_tiles_per_net_gradient_elementwise():
@@ -110,7 +120,7 @@ def test_c4_many_tiles_per_net_gradient_elementwise():
     r_o = np.concatenate([res_o["r"], res_o["rb"]])
     e_loss, e_res = abs(L_g - L_o) / abs(L_o), max_rel(r_g, r_o)
     worst = _report(f"c4_many_tiles loss {e_loss:.1e} res {e_res:.1e}",
-                    grad_block_ratios(wl, g_g, g_o, tol))
+                    grad_block_ratios(wl, g_g, g_o, tol, FLOOR[wl.prec]))
     assert e_loss <= tol and e_res <= tol
     assert worst <= 1.0
 
@@ -131,27 +141,32 @@ def test_small_batch_gradient_elementwise(name, wl, n, nb, n_near, band):
     bpts = bpts.astype(np.float32).astype(np.float64)
     _, g_o, _ = N.loss_and_grad(wl, theta, pts, bpts)
     _, _, g_g, _ = _gpu_step(wl, theta, pts, bpts)
-    assert _report(name, grad_block_ratios(wl, g_g, g_o, TOL[wl.prec])) <= 1.0
+    assert _report(name, grad_block_ratios(wl, g_g, g_o, TOL[wl.prec], FLOOR[wl.prec])) <= 1.0
 
 
-@pytest.mark.parametrize("wl", [I.C2, I.C3], ids=["c2_fused", "c3_two_pass"])
+@pytest.mark.parametrize("wl", [I.C2, I.C3, I.C1], ids=["c2_fused", "c3_two_pass", "c1_layered"])
 def test_backward_entry_point_scales_by_upstream_factor(wl):
     """nbm_backward(dL) recomputes the step and returns dL times the fused
     gradient of nbm_forward_residual (same kernels, the factor enters the
-    residual adjoints)."""
+    residual adjoints).  A power of two scales every rounded quantity
+    exactly, so dL = 0.25 must give 0.25 g bit for bit; dL = 0.37 within the
+    operand precision's bar."""
     from paper_2210_14907_amd import NBM
     theta = I.xavier_params(wl, 4).astype(np.float32)
     pts, bpts = parity_batch(wl, 3000, 64, 256, 0.01, seed=5)
-    m = NBM(wl, max_points=pts.shape[0], max_boundary=bpts.shape[0])
+    m = NBM(wl, max_points=pts.shape[0], max_boundary=bpts.shape[0], cut_capacity=pts.shape[0])
     p = torch.tensor(theta, device=DEV)
     tp = torch.tensor(pts, dtype=torch.float32, device=DEV)
     tb = torch.tensor(bpts, dtype=torch.float32, device=DEV)
-    _, _, g1 = m.forward_residual(p, tp, tb, want_grad=True)
+    L1, _, g1 = m.forward_residual(p, tp, tb, want_grad=True)
     g1 = g1.clone()
-    g2 = m.backward(p, tp, tb, dL=0.37)
+    assert np.isfinite(L1.item())
+    g_q = m.backward(p, tp, tb, dL=0.25).clone()
+    g_r = m.backward(p, tp, tb, dL=0.37)
     torch.cuda.synchronize()
-    a, b = g2.cpu().numpy().astype(np.float64), 0.37 * g1.cpu().numpy().astype(np.float64)
-    assert _report(f"backward_dL {wl.name}", grad_block_ratios(wl, a, b, 1e-6)) <= 1.0
+    assert torch.equal(g_q, 0.25 * g1)
+    a, b = g_r.cpu().numpy().astype(np.float64), 0.37 * g1.cpu().numpy().astype(np.float64)
+    assert _report(f"backward_dL {wl.name}", grad_block_ratios(wl, a, b, TOL[wl.prec], FLOOR[wl.prec])) <= 1.0
 
 
 def test_autograd_function_matches_oracle_and_finite_differences():
@@ -175,7 +190,8 @@ def test_autograd_function_matches_oracle_and_finite_differences():
         loss = 3.0 * NBMResidual.apply(p, tp, tb, m, fused) - 0.5
         loss.backward()
         g = p.grad.cpu().numpy().astype(np.float64)
-        assert _report(f"autograd fused={fused}", grad_block_ratios(wl, g, 3.0 * g_o, 1e-5)) <= 1.0
+        assert _report(f"autograd fused={fused}",
+                       grad_block_ratios(wl, g, 3.0 * g_o, TOL[wl.prec], FLOOR[wl.prec])) <= 1.0
     # central differences of the GPU loss (FP64 accumulation of FP32
     # residuals) on the largest entries of each block
     pd = torch.tensor(theta, dtype=torch.float32, device=DEV)

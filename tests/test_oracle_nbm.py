@@ -113,3 +113,25 @@ def test_loss_is_mean_square():
     pts, bpts = I.collocation_batch(wl, 64, 8)
     res = N.residuals(wl, th, pts, bpts)
     assert res["loss"] == pytest.approx((np.sum(res["r"] ** 2) + np.sum(res["rb"] ** 2)) / 72, rel=1e-15)
+
+
+def test_multiresolution_gradient_finite_differences():
+    """Three refinement levels (cells of side h, h/2, h/4, h/8 at every point,
+    losses summed): the gradient matches central differences of the summed
+    loss, and each level sees its own cut cells."""
+    wl = I.C1.replace(width=6, depth=2, act=I.ACT_SIN, h=1.0 / 8, levels=3)
+    th = I.xavier_params(wl, 1) * 1.5
+    pts, bpts = I.collocation_batch(wl, 80, 10, seed=7)
+    pts = np.concatenate([pts, I.near_interface_points(wl, 40, 0.1, seed=8)])
+    L, g, res = N.loss_and_grad(wl, th, pts, bpts)
+    assert res["r_levels"].shape == (4 * (pts.shape[0] + bpts.shape[0]),)
+    cuts = [(N.residuals(wl, th, pts, bpts, h=hl)["cls"] == S.CLASS_CUT).sum() for hl in N.level_spacings(wl)]
+    assert cuts[0] > cuts[-1] > 0
+    assert abs(L - N.multires_loss(wl, th, pts, bpts)) <= 1e-12 * L
+    rng = np.random.default_rng(1)
+    for j in rng.choice(th.size, 10, replace=False):
+        e = np.zeros_like(th)
+        step = 1e-6 * max(1.0, abs(th[j]))
+        e[j] = step
+        fd = (N.multires_loss(wl, th + e, pts, bpts) - N.multires_loss(wl, th - e, pts, bpts)) / (2 * step)
+        assert abs(g[j] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max()), (j, g[j], fd)
