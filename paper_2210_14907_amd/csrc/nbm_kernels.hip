@@ -523,7 +523,7 @@ __global__ __launch_bounds__(1024) void k_reduce(const float* partial, int G, in
 }
 
 __global__ __launch_bounds__(256) void k_reduce_loss(const double* lp, int nparts, const Meta* meta,
-                                                     double* loss, double* lacc, int acc) {
+                                                     double* loss, double* lacc, int mode) {
   __shared__ double s[256];
   double acc = 0.0;
   // fixed-order strided partial sums, then a fixed tree
@@ -537,8 +537,8 @@ __global__ __launch_bounds__(256) void k_reduce_loss(const double* lp, int npart
   if (threadIdx.x == 0) {
     double L = s[0] / (double)(meta->n + meta->nb);
     if (meta->overflow) L = __builtin_nan("");
-    L = acc_level(acc, lacc, L);
-    if (acc == 0 || acc == 3) *loss = L;
+    L = acc_level(mode, lacc, L);
+    if (mode == 0 || mode == 3) *loss = L;
   }
 }
 

@@ -342,3 +342,36 @@ def test_forward_residual_replays_in_a_graph():
         # eager work of the program between replays
         m.forward_residual(p * 1.01, tp, tb, want_grad=True)
         torch.cuda.synchronize()
+
+
+MULTIRES_CASES = [
+    # name, workload, n, nb, n_near, band
+    ("c2_levels3", I.C2.replace(levels=3), 2048, 64, 256, 0.02),
+    ("c3_levels2_bf16", I.C3.replace(levels=2), 1536, 48, 256, 0.01),
+    ("c1_levels3", I.C1.replace(levels=3), 2048, 128, 256, 0.05),
+]
+
+
+@pytest.mark.parametrize("name,wl,n,nb,n_near,band", MULTIRES_CASES, ids=[c[0] for c in MULTIRES_CASES])
+def test_multiresolution_step_parity(name, wl, n, nb, n_near, band):
+    """Implicit refinement: every point carries cells of side h, h/2, ...,
+    h/2^levels; the GPU's summed loss, every level's residual vector and the
+    summed gradient match the oracle's."""
+    from tests.gpu_common import grad_block_ratios
+    theta = I.xavier_params(wl, 0).astype(np.float32).astype(np.float64)
+    pts, bpts = parity_batch(wl, n, nb, n_near, band, seed=13)
+    pts = pts.astype(np.float32).astype(np.float64)
+    bpts = bpts.astype(np.float32).astype(np.float64)
+    L_o, g_o, res_o = N.loss_and_grad(wl, theta, pts, bpts)
+    L_g, r_g, g_g, counts, _ = _run(wl, pts, bpts, theta, cut_capacity=pts.shape[0])
+    assert counts[5] == 0 and r_g.shape == res_o["r_levels"].shape
+    tol = TOL[wl.prec]
+    e_loss = abs(L_g - L_o) / abs(L_o)
+    per_level = (n + n_near + nb)
+    e_res = max(max_rel(r_g[k * per_level:(k + 1) * per_level], res_o["r_levels"][k * per_level:(k + 1) * per_level])
+                for k in range(wl.levels + 1))
+    ratios = grad_block_ratios(wl, g_g, g_o, tol, 0.1 if wl.prec == I.PREC_FP32 else 0.2)
+    worst = max(ratios.values())
+    print(f"[parity] {name}: loss {e_loss:.2e} res (worst level) {e_res:.2e} grad block ratio {worst:.3f}",
+          flush=True)
+    assert e_loss <= tol and e_res <= tol and worst <= 1.0
