@@ -56,10 +56,13 @@ extern "C" {
 #define NBM_IFACE_SPHERE 0  /* |x| - radius (circle in 2-D) */
 #define NBM_IFACE_STAR 1    /* |x| - radius - amp sin(5 theta) sin(4 psi) */
 #define NBM_IFACE_PLANE 2   /* plane_n . x - plane_c */
+#define NBM_IFACE_MESH 3    /* level set stored on a coarse mesh (paper Sec. 3), multilinear */
 #define NBM_PROB_MMS_2D 0   /* u^- = exp(x+y), u^+ = sin(pi x) cos(pi y) */
 #define NBM_PROB_MMS_SPHERE 1 /* u^- = exp(z), u^+ = cos x sin y (paper Sec. 4.1) */
 #define NBM_PROB_FOURIER 2  /* f^- = f^+ = sum_k a_k cos(pi k.x) + b_k sin(pi k.x) */
 #define NBM_PROB_LINEAR 3   /* u^- = a.x + a0, u^+ = b.x + b0 */
+#define NBM_MU_CONST 0      /* mu^-+ = mu_minus, mu_plus */
+#define NBM_MU_PAPER 1      /* mu^- = y^2 ln(x+2) + 4, mu^+ = exp(-z) (paper Sec. 4.1) */
 
 /* Problem and network description (paper Sec. 2 problem statement; Sec. 3
  * two networks; Sec. 4.1 workload).  Host memory, copied by nbm_create. */
@@ -75,8 +78,11 @@ typedef struct nbm_config {
   double star_amp;    /* star amplitude */
   double plane_n[3];  /* plane normal (unit) */
   double plane_c;     /* plane offset */
-  double mu_minus, mu_plus; /* piecewise-constant diffusion coefficients > 0 */
-  double k_minus, k_plus;   /* Helmholtz coefficients: must be 0 (not compiled) */
+  double mu_minus, mu_plus; /* piecewise-constant diffusion coefficients > 0; with
+                               NBM_MU_PAPER they only tell which side is smaller */
+  int32_t mu_kind;    /* NBM_MU_*: with NBM_MU_PAPER every face takes mu at its centre
+                         (the step then runs the layered kernels) */
+  double k_minus, k_plus;   /* Helmholtz coefficients k^-+ >= 0 of the term k u */
   int32_t problem;    /* NBM_PROB_* */
   double alpha_const, beta_const; /* jump data of NBM_PROB_FOURIER */
   double lin_a[4], lin_b[4];      /* NBM_PROB_LINEAR coefficients */
@@ -89,6 +95,11 @@ typedef struct nbm_config {
   int64_t cut_capacity;  /* max cut cells per batch; 0 -> max_points/8 + 64 */
   int32_t eval_only;     /* 1: workspace for nbm_eval only (max_points = largest
                             query tile); training calls return NBM_EWORKSPACE */
+  int32_t phi_n;         /* NBM_IFACE_MESH: intervals per axis of the level-set mesh
+                            over [-1,1]^dim, 2..1024 */
+  const double* phi_table; /* NBM_IFACE_MESH: host [(phi_n+1)^dim] nodal values at
+                            -1 + 2 j / phi_n, axis 0 fastest; copied by nbm_create,
+                            placed in the workspace by nbm_prepare */
   int32_t levels;        /* implicit refinement levels beyond the base (paper
                             Sec. 3 implicit cells at several resolutions, Sec. 4.2
                             base resolution refined implicitly): every point
@@ -113,7 +124,7 @@ int64_t nbm_param_count(const nbm_ctx* ctx);
  * negative.  The caller allocates it (256-byte aligned) and owns it. */
 size_t nbm_workspace_bytes(const nbm_ctx* ctx, int64_t n, int64_t nb);
 
-/* Copy the problem tables (Fourier modes) into the front of the workspace
+/* Copy the problem tables (Fourier modes, level-set mesh) into the front of the workspace
  * (the part whose offsets do not depend on the batch size).  Must be called
  * once for each workspace before the other workspace-using calls; blocks the
  * host until the copy is done. */

@@ -25,10 +25,13 @@ PREC_BF16 = 1
 IFACE_SPHERE = 0   # circle in 2-D, sphere in 3-D, radius R
 IFACE_STAR = 1     # |x| - 0.5 - amp * sin(5 theta) sin(4 psi)
 IFACE_PLANE = 2    # n . x - c (test problems only)
+IFACE_GRID = 3     # level set stored on a coarse mesh, interpolated (multi)linearly
 PROB_MMS_2D = 0    # u^- = exp(x+y), u^+ = sin(pi x) cos(pi y)
 PROB_MMS_SPHERE = 1  # u^- = exp(z), u^+ = cos(x) sin(y)
 PROB_FOURIER = 2   # f^- = f^+ = seeded Fourier series, alpha, beta constants, g = 0
 PROB_LINEAR = 3    # u^- = a.x + a0, u^+ = b.x + b0 (patch tests only)
+MU_CONST = 0       # mu^-+ constants
+MU_PAPER = 1       # mu^- = y^2 ln(x + 2) + 4, mu^+ = exp(-z) (Sec. 4.1)
 
 
 @dataclasses.dataclass(frozen=True)
@@ -60,6 +63,11 @@ class Workload:
     lin_a: tuple = (0.3, -0.7, 0.2, 1.1)  # PROB_LINEAR u^- coefficients (x, y, z, const)
     lin_b: tuple = (-0.4, 0.9, 0.5, -0.6)  # PROB_LINEAR u^+ coefficients
     levels: int = 0       # implicit refinement levels: cells of side h, h/2, ..., h/2^levels
+    k_minus: float = 0.0  # Helmholtz coefficients k^-+ of the term k u (>= 0)
+    k_plus: float = 0.0
+    mu_kind: int = 0      # 0: constant mu_minus / mu_plus; MU_PAPER: the variable coefficients of Sec. 4.1
+    phi_n: int = 0        # IFACE_GRID: intervals per axis of the level-set mesh
+    phi_shape: int = IFACE_STAR   # IFACE_GRID: the shape whose level set the mesh samples
 
     def replace(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)
@@ -99,7 +107,14 @@ C4 = Workload("c4_star3d_sin128x4_bf16", 3, 128, 4, ACT_SIN, PREC_BF16, 1.0 / 10
               _nb(1048576, 3, 1.0 / 1024), IFACE_STAR, 0.5, 0.1, 1.0, 100.0, PROB_FOURIER,
               alpha_const=1.0, beta_const=0.0, steps=1000, judge_n=256)
 
-WORKLOADS = {"c1": C1, "c2": C2, "c3": C3, "c4": C4}
+# The paper's convergence workload (Sec. 4.1): sphere r = 0.5, u^- = e^z,
+# u^+ = cos x sin y, mu^- = y^2 ln(x+2) + 4, mu^+ = e^-z, two sine networks of
+# 5 hidden layers x 10 neurons (982 parameters); h = 2/N for N = 8..128.
+PAPER = Workload("paper_sphere3d_varmu_sin10x5", 3, 10, 5, ACT_SIN, PREC_FP32, 1.0 / 32, 32768,
+                 _nb(32768, 3, 1.0 / 32), IFACE_SPHERE, 0.5, 0.0, 4.0, 1.0, PROB_MMS_SPHERE,
+                 steps=3000, judge_n=64, mu_kind=MU_PAPER)
+
+WORKLOADS = {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "paper": PAPER}
 
 
 def xavier_params(wl: Workload, seed: int = 0, dtype=np.float64) -> np.ndarray:
@@ -148,6 +163,29 @@ def fourier_modes(wl: Workload):
     a = rng.normal(size=len(k)) * sd
     b = rng.normal(size=len(k)) * sd
     return k, a, b
+
+
+def phi_table(wl: Workload) -> np.ndarray:
+    """Level-set values on the nodes -1 + 2 j / phi_n of a coarse mesh
+    (IFACE_GRID workloads), axis 0 fastest: the level set of wl.phi_shape
+    sampled at the nodes (star: |x| - R - amp sin(5 theta) sin(4 psi) with
+    theta = atan2(y, x), psi = arccos(z/|x|), value -R at the origin; sphere:
+    |x| - R; plane: n.x - c).  This is problem data, like a level set read
+    from a file."""
+    n, d = wl.phi_n, wl.dim
+    ax = -1.0 + (2.0 / n) * np.arange(n + 1)
+    g = np.meshgrid(*([ax] * d), indexing="ij")
+    x = np.stack([m.transpose().ravel() for m in g], axis=-1)     # axis 0 fastest
+    r = np.sqrt((x * x).sum(axis=1))
+    if wl.phi_shape == IFACE_PLANE:
+        return x @ np.array(wl.plane_n[:d]) - wl.plane_c
+    if wl.phi_shape == IFACE_SPHERE:
+        return r - wl.radius
+    th = np.arctan2(x[:, 1], x[:, 0])
+    cz = np.divide(x[:, 2], r, out=np.ones_like(r), where=r > 0)
+    ps = np.arccos(np.clip(cz, -1.0, 1.0))
+    v = r - wl.radius - wl.star_amp * np.sin(5.0 * th) * np.sin(4.0 * ps)
+    return np.where(r > 0, v, -wl.radius)
 
 
 LATTICE_BITS = 22

@@ -19,8 +19,43 @@ import nbm_inputs as I
 # ----------------------------------------------------------------------------
 # level sets
 # ----------------------------------------------------------------------------
+_TABLES = {}
+
+
+def _table(wl: I.Workload):
+    key = (wl.phi_n, wl.phi_shape, wl.dim, wl.radius, wl.star_amp, tuple(wl.plane_n), wl.plane_c)
+    if key not in _TABLES:
+        _TABLES[key] = I.phi_table(wl)
+    return _TABLES[key]
+
+
+def phi_mesh(wl: I.Workload, x: np.ndarray) -> np.ndarray:
+    """Level set stored on a coarse mesh (paper Sec. 3: a separate coarse mesh
+    holds the level set that gives the kernels their geometry): multilinear
+    interpolation of the nodal values on [-1, 1]^d with phi_n intervals per
+    axis; points on the mesh's upper faces use the last cell."""
+    n, d = wl.phi_n, x.shape[-1]
+    tab = _table(wl)
+    flat = x.reshape(-1, d)
+    t = (flat + 1.0) * (n / 2.0)
+    j = np.clip(np.floor(t).astype(np.int64), 0, n - 1)
+    f = t - j
+    out = np.zeros(flat.shape[0])
+    for c in range(1 << d):
+        w = np.ones(flat.shape[0])
+        idx = np.zeros(flat.shape[0], dtype=np.int64)
+        for a in range(d):
+            bit = (c >> a) & 1
+            w = w * (f[:, a] if bit else 1.0 - f[:, a])
+            idx += (j[:, a] + bit) * (n + 1) ** a
+        out += w * tab[idx]
+    return out.reshape(x.shape[:-1])
+
+
 def phi(wl: I.Workload, x: np.ndarray) -> np.ndarray:
     """Level set at points x[..., d] (FP64)."""
+    if wl.interface == I.IFACE_GRID:
+        return phi_mesh(wl, x)
     if wl.interface == I.IFACE_PLANE:
         nv = np.array(wl.plane_n[:x.shape[-1]])
         return x @ nv - wl.plane_c
@@ -52,7 +87,8 @@ STAR_GRAD_STEP = 1e-6
 
 def grad_phi(wl: I.Workload, x: np.ndarray) -> np.ndarray:
     """Gradient of phi: analytic for the sphere, central differences (step
-    1e-6) for the star, whose angular factor is not smooth on the z-axis."""
+    1e-6) for the star, whose angular factor is not smooth on the z-axis, and
+    for the mesh level set, whose interpolant has kinks across mesh faces."""
     if wl.interface == I.IFACE_SPHERE:
         r = np.sqrt((x * x).sum(axis=-1, keepdims=True))
         return x / np.where(r > 0, r, 1.0)

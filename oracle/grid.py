@@ -6,7 +6,7 @@ interior nodes, Dirichlet nodes held at g.  Every interior node carries the
 row R_p = 0 of the cell residual (same geometry and jump extension as the
 collocation residual), written as
 
-    sum_F c_F (U_p - U_F) = -h^2 K_p,
+    sum_F c_F (U_p - U_F) + h^2 kap_p U_p = -h^2 K_p,   kap_p = sum_s k^s v^s,
 
 which is symmetric because c_F depends only on the face.  With a coefficient
 contrast, the jump extension needs the normal derivative of the low-mu side;
@@ -49,34 +49,38 @@ def _lib():
     if _LIB is None:
         _LIB = ctypes.CDLL(str(build_solver()))
         dp = ctypes.POINTER(ctypes.c_double)
-        _LIB.nbm_oracle_pcg.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.c_double,
+        _LIB.nbm_oracle_pcg.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ctypes.c_double,
                                         ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
-        _LIB.nbm_oracle_apply.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        _LIB.nbm_oracle_apply.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp]
     return _LIB
 
 
 def _ptr(a):
+    if a is None:
+        return ctypes.POINTER(ctypes.c_double)()
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def pcg(d, n, cface, b, u0=None, tol=1e-12, maxit=5000, precond="mg"):
+def pcg(d, n, cface, b, u0=None, tol=1e-12, maxit=5000, precond="mg", kdiag=None):
     cface = np.ascontiguousarray(cface, dtype=np.float64)
     b = np.ascontiguousarray(b, dtype=np.float64).ravel()
+    kd = None if kdiag is None else np.ascontiguousarray(kdiag, dtype=np.float64)
     u = np.zeros_like(b) if u0 is None else np.ascontiguousarray(u0, dtype=np.float64).ravel().copy()
     it = ctypes.c_int(0)
     rr = ctypes.c_double(0)
-    rc = _lib().nbm_oracle_pcg(d, n, _ptr(cface), _ptr(b), _ptr(u), tol, maxit,
+    rc = _lib().nbm_oracle_pcg(d, n, _ptr(cface), _ptr(kd), _ptr(b), _ptr(u), tol, maxit,
                                1 if precond == "mg" else 0, ctypes.byref(it), ctypes.byref(rr))
     if rc != 0:
         raise RuntimeError("pcg failed")
     return u, it.value, rr.value
 
 
-def apply_A(d, n, cface, u):
+def apply_A(d, n, cface, u, kdiag=None):
     cface = np.ascontiguousarray(cface, dtype=np.float64)
     u = np.ascontiguousarray(u, dtype=np.float64).ravel()
+    kd = None if kdiag is None else np.ascontiguousarray(kdiag, dtype=np.float64)
     y = np.zeros_like(u)
-    _lib().nbm_oracle_apply(d, n, _ptr(cface), _ptr(u), _ptr(y))
+    _lib().nbm_oracle_apply(d, n, _ptr(cface), _ptr(kd), _ptr(u), _ptr(y))
     return y
 
 
@@ -118,7 +122,6 @@ class GridSystem:
     # node p (idx i) has cell corners at dual indices i + {0,1}^d
     def _faces(self):
         d, n = self.d, self.n
-        mm, mp = self.wl.mu_minus, self.wl.mu_plus
         cface = np.zeros((d, self.N))
         phid = self.phid
         for a in range(d):
@@ -148,6 +151,10 @@ class GridSystem:
                     val[mixed] = 0.5 * (G.tri_neg_fraction(fm[:, [0, 1, 3]]) +
                                         G.tri_neg_fraction(fm[:, [0, 2, 3]]))
             fr[sel] = val
+            # mu^s at the face centre x_p + (h/2) e_a
+            xf = self.x.copy()
+            xf[:, a] += 0.5 * self.h
+            mm, mp = self.prob.mu_at(0, xf), self.prob.mu_at(1, xf)
             cface[a] = np.where(ok, mm * fr + mp * (1.0 - fr), 0.0)
         self.cface = cface
 
@@ -218,6 +225,23 @@ class GridSystem:
                 cf = self.cface[a][ip] if sgn == 1 else self.cface[a][q]
                 b[ip[isb]] += cf[isb] * g[q[isb]]
         return b
+
+    def kdiag(self):
+        """Diagonal of the Helmholtz term, h^2 sum_s k^s v^s per interior node
+        (uncut: h^2 k of its side; cut: with the cell's volume fractions), or
+        None without one.  Needs the cut-cell data of rhs()."""
+        wl = self.wl
+        if wl.k_minus == 0.0 and wl.k_plus == 0.0:
+            return None
+        if not hasattr(self, "_kd"):
+            h2 = self.h * self.h
+            kd = np.zeros(self.N)
+            kd[self.uncut] = h2 * np.where(self.side[self.uncut], wl.k_minus, wl.k_plus)
+            if self.cut.size:
+                st = self._cut_static
+                kd[self.cut] = h2 * (st["km"] + st["kp"])
+            self._kd = kd
+        return self._kd
 
     def full_values(self, U):
         """Nodal values with the Dirichlet data filled in on the boundary."""
@@ -316,7 +340,8 @@ class GridSystem:
             nodes = self.cut[:, None] + self.node_offsets()[None, :]
             glo = glo_fn(self.x[nodes])
         b = self.rhs(glo)
-        U, it, rr = pcg(d, n, self.cface, b, tol=tol, precond=precond)
+        kd = self.kdiag()
+        U, it, rr = pcg(d, n, self.cface, b, tol=tol, precond=precond, kdiag=kd)
         self.pcg_iters = [it]
         self.picard_iters = 0
         self.picard_dU = 0.0
@@ -346,7 +371,7 @@ class GridSystem:
                 U_old = U
                 x = x_next
                 b = self.rhs(x.reshape(ncut_nodes))
-                U, it, rr = pcg(d, n, self.cface, b, u0=U_old, tol=tol, precond=precond)
+                U, it, rr = pcg(d, n, self.cface, b, u0=U_old, tol=tol, precond=precond, kdiag=kd)
                 self.pcg_iters.append(it)
                 self.picard_iters = k + 1
                 dU = np.abs(U - U_old).max()
@@ -370,8 +395,8 @@ class GridSystem:
         collocation residual of the same node values."""
         Uz = Ufull.copy()
         Uz[~self.interior] = 0.0
-        AU = apply_A(self.d, self.n, self.cface, Uz)
         b = self.rhs(None if S.lo_side(self.wl) < 0 else np.zeros((self.cut.size, 2 * self.d + 1, self.d)))
+        AU = apply_A(self.d, self.n, self.cface, Uz, kdiag=self.kdiag())
         mubar = np.zeros(self.N)
         ip = np.nonzero(self.interior)[0]
         for a in range(self.d):
@@ -395,7 +420,8 @@ def solve_cached(wl: I.Workload, n: int, verbose=False):
     on disk by a hash of the problem-defining fields."""
     key = repr((wl.dim, wl.interface, wl.radius, wl.star_amp, wl.mu_minus, wl.mu_plus, wl.problem,
                 wl.alpha_const, wl.beta_const, wl.fourier_seed, wl.fourier_kmax, tuple(wl.plane_n),
-                wl.plane_c, tuple(wl.lin_a), tuple(wl.lin_b), n, "v2"))
+                wl.plane_c, tuple(wl.lin_a), tuple(wl.lin_b), wl.k_minus, wl.k_plus, wl.mu_kind,
+                wl.phi_n, wl.phi_shape, n, "v3"))
     hsh = hashlib.sha1(key.encode()).hexdigest()[:16]
     f = cache_dir() / f"grid_{hsh}.npy"
     if f.exists():

@@ -9,8 +9,10 @@
  *     (A u)_p = sum_a  c_a[p]     (u_p - u_{p+e_a})
  *                    + c_a[p-e_a] (u_p - u_{p-e_a})
  * c_a[p] is the coefficient of the face between node p and p + e_a
- * (sum over the two sides of mu^s times the face fraction).  A is symmetric
- * positive definite.  Preconditioners: Jacobi, or one symmetric geometric
+ * (sum over the two sides of mu^s times the face fraction), plus an optional
+ * non-negative diagonal kd[p] u_p (the Helmholtz term k^s v^s h^2 of the
+ * row).  A is symmetric positive definite.  The multigrid levels below the
+ * finest carry the face part only (the preconditioner stays SPD).  Preconditioners: Jacobi, or one symmetric geometric
  * multigrid V-cycle (damped Jacobi smoothing, trilinear interpolation P,
  * restriction P^T, coarse faces = harmonic mean along / weighted arithmetic
  * mean across the fine faces, coarse operator scaled by 2^(d-2)).
@@ -25,6 +27,7 @@ typedef struct {
   int64_t N;           /* (n+1)^d nodes */
   int64_t s[3];        /* strides */
   double* c[3];        /* face coefficients */
+  const double* kd;    /* diagonal term (finest level only) or NULL */
   double* diag;
   double scale;        /* operator scale factor */
 } level_t;
@@ -48,6 +51,7 @@ static void make_diag(level_t* L) {
     if (!interior(L, i)) continue;
     double dg = 0;
     for (int a = 0; a < L->d; ++a) dg += L->c[a][p] + L->c[a][p - L->s[a]];
+    if (L->kd) dg += L->kd[p];
     L->diag[p] = dg * L->scale;
   }
 }
@@ -64,6 +68,7 @@ static void apply(const level_t* L, const double* u, double* out) {
       double um = (i[a] - 1 > 0) ? u[p - st] : 0.0;
       acc += L->c[a][p] * (u[p] - up) + L->c[a][p - st] * (u[p] - um);
     }
+    if (L->kd) acc += L->kd[p] * u[p];
     out[p] = acc * L->scale;
   }
 }
@@ -181,14 +186,15 @@ static void vcycle(mg_t* M, int k, const double* b, double* x) {
   jacobi(L, b, x, w[0], 2, 0.8);
 }
 
-int nbm_oracle_pcg(int d, int n, const double* cface, const double* b, double* u, double tol,
-                   int maxit, int precond, int* iters_out, double* relres_out) {
+int nbm_oracle_pcg(int d, int n, const double* cface, const double* kdiag, const double* b, double* u,
+                   double tol, int maxit, int precond, int* iters_out, double* relres_out) {
   if (d < 2 || d > 3 || n < 4) return -1;
   mg_t M; memset(&M, 0, sizeof(M));
   level_t* L0 = &M.lev[0];
   L0->d = d; L0->n = n; L0->N = npow(n, d); L0->scale = 1.0;
   L0->s[0] = 1; L0->s[1] = n + 1; L0->s[2] = (int64_t)(n + 1) * (n + 1);
   for (int a = 0; a < d; ++a) L0->c[a] = (double*)(cface + (int64_t)a * L0->N);
+  L0->kd = kdiag;
   make_diag(L0);
   M.nlev = 1;
   if (precond == 1) {
@@ -249,11 +255,12 @@ int nbm_oracle_pcg(int d, int n, const double* cface, const double* b, double* u
 }
 
 /* y = A u (for tests of symmetry and of the assembled rows) */
-int nbm_oracle_apply(int d, int n, const double* cface, const double* u, double* y) {
+int nbm_oracle_apply(int d, int n, const double* cface, const double* kdiag, const double* u, double* y) {
   level_t L; memset(&L, 0, sizeof(L));
   L.d = d; L.n = n; L.N = npow(n, d); L.scale = 1.0;
   L.s[0] = 1; L.s[1] = n + 1; L.s[2] = (int64_t)(n + 1) * (n + 1);
   for (int a = 0; a < d; ++a) L.c[a] = (double*)(cface + (int64_t)a * L.N);
+  L.kd = kdiag;
   apply(&L, u, y);
   return 0;
 }

@@ -89,8 +89,7 @@ def residuals(wl: I.Workload, theta: np.ndarray, pts: np.ndarray, bpts: np.ndarr
         X = y[ids].reshape(-1, d)
         U = provider(s, X).reshape(ids.size, 2 * d + 1)
         r[ids] = S.uncut_residual(wl, prob, pts[ids], h, U, s)
-        coef = np.full((ids.size, 2 * d + 1), -1.0 / (h * h))
-        coef[:, 0] = 2.0 * d / (h * h)
+        coef = S.uncut_residual_dU(wl, prob, pts[ids], h, s)
         req[s].append((np.repeat(ids, 2 * d + 1), X, coef.ravel()))
     # cut cells -----------------------------------------------------------------
     ids = np.nonzero(cls == S.CLASS_CUT)[0]
@@ -147,17 +146,20 @@ def multires_loss(wl: I.Workload, theta: np.ndarray, pts: np.ndarray, bpts: np.n
 
 
 def loss_and_grad(wl: I.Workload, theta: np.ndarray, pts: np.ndarray, bpts: np.ndarray,
-                  h: float = None, dL: float = 1.0, glo_override=None):
+                  h: float = None, dL: float = 1.0, glo_override=None, abs_residual: bool = False):
     """Loss and dL/dtheta (FP64).  dL scales the gradient (upstream factor).
     Without an explicit h, a workload with refinement levels sums the loss
     and gradient over h, h/2, ..., h/2^levels; the returned dict then holds
     the base level's classes and "r_levels", every level's interior and
-    boundary residuals, level-major."""
+    boundary residuals, level-major.  abs_residual=True returns instead
+    sum_p (2 |r_p| / (N + N_b)) d r_p / d theta, the gradient with the
+    residuals' signs removed: a scale for how large the gradient's terms are
+    where their signs cancel (test infrastructure: rounding bars)."""
     if h is None and wl.levels > 0:
         L, g, out = 0.0, None, None
         rl = []
         for hl in level_spacings(wl):
-            Ll, gl, res = loss_and_grad(wl, theta, pts, bpts, h=hl, dL=dL)
+            Ll, gl, res = loss_and_grad(wl, theta, pts, bpts, h=hl, dL=dL, abs_residual=abs_residual)
             L += Ll
             g = gl if g is None else g + gl
             out = res if out is None else out
@@ -170,8 +172,8 @@ def loss_and_grad(wl: I.Workload, theta: np.ndarray, pts: np.ndarray, bpts: np.n
     d = wl.dim
     n, nb = pts.shape[0], bpts.shape[0]
     scale = 2.0 * dL / (n + nb)
-    rbar = scale * res["r"]
-    rbbar = scale * res["rb"]
+    rbar = scale * (np.abs(res["r"]) if abs_residual else res["r"])
+    rbbar = scale * (np.abs(res["rb"]) if abs_residual else res["rb"])
     grads = []
     for s in (0, 1):
         Xs, Ws = [], []

@@ -1,8 +1,9 @@
 """Problem data for the oracle (FP64, numpy).
 
 Paper Sec. 2: k^+- u^+- - div(mu^+- grad u^+-) = f^+- in Omega^+-, with
-[u] = alpha and [mu d_n u] = beta on Gamma, Dirichlet data on the cube.  All
-workloads here have k^+- = 0 and piecewise-constant mu.  Manufactured
+[u] = alpha and [mu d_n u] = beta on Gamma, Dirichlet data on the cube.
+mu piecewise constant, or the variable coefficients of Sec. 4.1
+(mu^- = y^2 ln(x + 2) + 4, mu^+ = e^-z), and k >= 0 (k = 0: Poisson).  Manufactured
 solutions: the sphere problem of Sec. 4.1 (u^- = e^z, u^+ = cos x sin y) with
 constant mu^- = 1, mu^+ = 10, and a 2-D analogue with u^- = e^(x+y),
 u^+ = sin(pi x) cos(pi y), mu = 1.  The Fourier workload has no closed-form
@@ -20,11 +21,32 @@ class Problem:
     def __init__(self, wl: I.Workload):
         self.wl = wl
         self.mu = (wl.mu_minus, wl.mu_plus)
+        self.k = (wl.k_minus, wl.k_plus)
         if wl.problem == I.PROB_FOURIER:
             k, a, b = I.fourier_modes(wl)
-            self.k = k.astype(np.float64)
+            self.kv = k.astype(np.float64)
             self.a = a
             self.b = b
+
+    # diffusion coefficients --------------------------------------------------
+    def mu_at(self, s: int, x):
+        """mu^s(x): the constant, or the Sec. 4.1 functions."""
+        if self.wl.mu_kind == I.MU_CONST:
+            return np.full(x.shape[:-1], self.mu[s])
+        if s == 0:
+            return x[..., 1] ** 2 * np.log(x[..., 0] + 2.0) + 4.0
+        return np.exp(-x[..., 2])
+
+    def grad_mu(self, s: int, x):
+        g = np.zeros_like(x)
+        if self.wl.mu_kind == I.MU_CONST:
+            return g
+        if s == 0:
+            g[..., 0] = x[..., 1] ** 2 / (x[..., 0] + 2.0)
+            g[..., 1] = 2.0 * x[..., 1] * np.log(x[..., 0] + 2.0)
+        else:
+            g[..., 2] = -np.exp(-x[..., 2])
+        return g
 
     # exact solutions (manufactured problems only) ---------------------------
     def has_exact(self) -> bool:
@@ -75,24 +97,34 @@ class Problem:
 
     # forcing ------------------------------------------------------------------
     def f_side(self, s: int, x):
-        """f^s = -mu^s Laplacian(u^s) (manufactured) or the Fourier series."""
+        """f^s = k^s u^s - div(mu^s grad u^s) = k^s u^s - mu^s Laplacian(u^s)
+        - grad mu^s . grad u^s (manufactured) or the Fourier series."""
         p = self.wl.problem
-        mu = self.mu[s]
+        k = self.k[s]
+        if self.wl.mu_kind != I.MU_CONST and p != I.PROB_FOURIER:
+            f = self._f_const_mu(s, x, self.mu_at(s, x))
+            return f - (self.grad_mu(s, x) * self.grad_u_side(s, x)).sum(axis=-1)
+        return self._f_const_mu(s, x, self.mu[s])
+
+    def _f_const_mu(self, s: int, x, mu):
+        p = self.wl.problem
+        k = self.k[s]
         if p == I.PROB_MMS_2D:
             if s == 0:
-                return -mu * 2.0 * np.exp(x[..., 0] + x[..., 1])
-            return mu * 2.0 * np.pi ** 2 * np.sin(np.pi * x[..., 0]) * np.cos(np.pi * x[..., 1])
+                lap = 2.0 * np.exp(x[..., 0] + x[..., 1])
+            else:
+                lap = -2.0 * np.pi ** 2 * np.sin(np.pi * x[..., 0]) * np.cos(np.pi * x[..., 1])
+            return -mu * lap + (k * self.u_side(s, x) if k else 0.0)
         if p == I.PROB_MMS_SPHERE:
-            if s == 0:
-                return -mu * np.exp(x[..., 2])
-            return mu * 2.0 * np.cos(x[..., 0]) * np.sin(x[..., 1])
+            lap = np.exp(x[..., 2]) if s == 0 else -2.0 * np.cos(x[..., 0]) * np.sin(x[..., 1])
+            return -mu * lap + (k * self.u_side(s, x) if k else 0.0)
         if p == I.PROB_LINEAR:
-            return np.zeros(x.shape[:-1])
+            return k * self.u_side(s, x) if k else np.zeros(x.shape[:-1])
         # f(x) = sum_k a_k cos(pi k.x) + b_k sin(pi k.x), in chunks of points
         flat = x.reshape(-1, x.shape[-1])
         out = np.empty(flat.shape[0])
         for i in range(0, flat.shape[0], 8192):
-            ph = np.pi * (flat[i:i + 8192] @ self.k.T)
+            ph = np.pi * (flat[i:i + 8192] @ self.kv.T)
             out[i:i + 8192] = np.cos(ph) @ self.a + np.sin(ph) @ self.b
         return out.reshape(x.shape[:-1])
 
@@ -107,9 +139,9 @@ class Problem:
         where k is not a mode) with the per-axis tables e^{i pi k_a x_a}."""
         if self.wl.problem != I.PROB_FOURIER or self.wl.dim != 3:
             raise ValueError("f_grid serves the 3-D Fourier forcing")
-        km = int(np.abs(self.k).max())
+        km = int(np.abs(self.kv).max())
         C = np.zeros((2 * km + 1,) * 3, dtype=np.complex128)
-        ki = self.k.astype(np.int64) + km
+        ki = self.kv.astype(np.int64) + km
         C[ki[:, 0], ki[:, 1], ki[:, 2]] = self.a - 1j * self.b
         x = -1.0 + (2.0 / n) * np.arange(n + 1)
         E = np.exp(1j * np.pi * np.outer(np.arange(-km, km + 1), x))   # [k, i]
@@ -129,7 +161,7 @@ class Problem:
             return np.full(y.shape[:-1], self.wl.beta_const)
         gp = (self.grad_u_side(1, y) * n).sum(axis=-1)
         gm = (self.grad_u_side(0, y) * n).sum(axis=-1)
-        return self.mu[1] * gp - self.mu[0] * gm
+        return self.mu_at(1, y) * gp - self.mu_at(0, y) * gm
 
     # Dirichlet data ----------------------------------------------------------
     def g(self, x):

@@ -29,7 +29,7 @@ class NbmConfig(ctypes.Structure):
                 ("interface_kind", ctypes.c_int32), ("radius", ctypes.c_double),
                 ("star_amp", ctypes.c_double), ("plane_n", ctypes.c_double * 3),
                 ("plane_c", ctypes.c_double), ("mu_minus", ctypes.c_double),
-                ("mu_plus", ctypes.c_double), ("k_minus", ctypes.c_double),
+                ("mu_plus", ctypes.c_double), ("mu_kind", ctypes.c_int32), ("k_minus", ctypes.c_double),
                 ("k_plus", ctypes.c_double), ("problem", ctypes.c_int32),
                 ("alpha_const", ctypes.c_double), ("beta_const", ctypes.c_double),
                 ("lin_a", ctypes.c_double * 4), ("lin_b", ctypes.c_double * 4),
@@ -37,11 +37,48 @@ class NbmConfig(ctypes.Structure):
                 ("mode_a", ctypes.POINTER(ctypes.c_double)), ("mode_b", ctypes.POINTER(ctypes.c_double)),
                 ("max_points", ctypes.c_int64), ("max_boundary", ctypes.c_int64),
                 ("cut_capacity", ctypes.c_int64), ("eval_only", ctypes.c_int32),
+                ("phi_n", ctypes.c_int32), ("phi_table", ctypes.POINTER(ctypes.c_double)),
                 ("levels", ctypes.c_int32)]
 
 
 class NbmError(RuntimeError):
     pass
+
+
+# hidden widths with compiled kernels; narrower networks run zero-padded to
+# the next one (padded neurons have zero weights in and out, so their
+# pre-activations, activations and gradients are exactly zero)
+COMPILED_WIDTHS = (16, 64, 128)
+
+
+def device_width(width: int) -> int:
+    for w in COMPILED_WIDTHS:
+        if width <= w:
+            return w if (width == w or w == 16) else width
+    return width
+
+
+def _param_blocks(width, dim, depth):
+    """(rows, cols) of every parameter block of one net, in packing order."""
+    blocks = [(width, dim), (width, 1)]
+    for _ in range(depth - 1):
+        blocks += [(width, width), (width, 1)]
+    blocks += [(1, width), (1, 1)]
+    return blocks
+
+
+def padding_index(wl: I.Workload, wdev: int) -> np.ndarray:
+    """Positions in the width-wdev parameter vector of the wl.width one's
+    entries (both nets, packing order)."""
+    small = _param_blocks(wl.width, wl.dim, wl.depth)
+    big = _param_blocks(wdev, wl.dim, wl.depth)
+    idx, off = [], 0
+    for _net in range(2):
+        for (r, c), (R, C) in zip(small, big):
+            rr, cc = np.meshgrid(np.arange(r), np.arange(c), indexing="ij")
+            idx.append((off + rr * C + cc).ravel())
+            off += R * C
+    return np.concatenate(idx)
 
 
 def lib():
@@ -94,6 +131,12 @@ class NBM:
                  cut_capacity: int = 0, device: str = "cuda:0", eval_only: bool = False):
         self.wl = wl
         self.device = torch.device(device)
+        # narrower networks run zero-padded to a compiled width: the parameter
+        # vectors of every call are then the padded ones (embed / extract)
+        wdev = device_width(wl.width)
+        self.padded = wdev != wl.width
+        self._pad_idx = padding_index(wl, wdev) if self.padded else None
+        wl = wl.replace(width=wdev) if self.padded else wl
         cfg = NbmConfig()
         cfg.dim, cfg.width, cfg.depth = wl.dim, wl.width, wl.depth
         cfg.act, cfg.prec, cfg.h = wl.act, wl.prec, wl.h
@@ -102,7 +145,8 @@ class NBM:
             cfg.plane_n[i] = wl.plane_n[i]
         cfg.plane_c = wl.plane_c
         cfg.mu_minus, cfg.mu_plus = wl.mu_minus, wl.mu_plus
-        cfg.k_minus = cfg.k_plus = 0.0
+        cfg.mu_kind = wl.mu_kind
+        cfg.k_minus, cfg.k_plus = wl.k_minus, wl.k_plus
         cfg.problem = wl.problem
         cfg.alpha_const, cfg.beta_const = wl.alpha_const, wl.beta_const
         for i in range(4):
@@ -121,6 +165,10 @@ class NBM:
         cfg.cut_capacity = cut_capacity
         cfg.eval_only = 1 if eval_only else 0
         cfg.levels = wl.levels
+        if wl.interface == I.IFACE_GRID:
+            self._phitab = np.ascontiguousarray(I.phi_table(wl), dtype=np.float64)
+            cfg.phi_n = wl.phi_n
+            cfg.phi_table = self._phitab.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         self.cfg = cfg
         h = ctypes.c_void_p()
         _check(lib().nbm_create(ctypes.byref(cfg), ctypes.byref(h)))
@@ -134,6 +182,24 @@ class NBM:
         self.ws_view = self.ws[off:off + self.ws_bytes]
         with torch.cuda.device(self.device):
             _check(lib().nbm_prepare(h, _stream(), _ptr(self.ws_view), self.ws_bytes))
+
+    def embed(self, theta):
+        """Parameters of the workload's own width -> the device parameter
+        vector (zero-padded when the width is not compiled).  numpy or torch
+        in, FP32 device tensor out."""
+        t = torch.as_tensor(np.asarray(theta) if not torch.is_tensor(theta) else theta)
+        t = t.to(device=self.device, dtype=torch.float32)
+        if not self.padded:
+            return t.clone()
+        out = torch.zeros(self.P, dtype=torch.float32, device=self.device)
+        out[torch.from_numpy(self._pad_idx).to(self.device)] = t
+        return out
+
+    def extract(self, vec):
+        """Device parameter-sized vector -> the entries of the workload's own width."""
+        if not self.padded:
+            return vec
+        return vec[torch.from_numpy(self._pad_idx).to(vec.device)]
 
     def __del__(self):
         try:

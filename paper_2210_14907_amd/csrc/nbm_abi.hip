@@ -35,7 +35,7 @@ namespace {
 // size (nbm_prepare fills the tables once; nbm_batch_counts reads the
 // bookkeeping of the last call).
 struct Layout {
-  size_t modes32, modes64, fmodes, meta, prefix, ctot, coff, blockcnt, off, blockcnt_b, off_b, cls, rank, bcls,
+  size_t modes32, modes64, fmodes, phitab, meta, prefix, ctot, coff, blockcnt, off, blockcnt_b, off_b, cls, rank, bcls,
       brank, cutidx, centres, src, outputs, adj, Zst, Ast, ALst, dZ, dZw, shadow, partial, lossp, resid, lossbuf,
       gacc, fpre, fslot, total;
   int64_t nchunk;    // interior chunks of the two-level scan
@@ -57,6 +57,7 @@ struct nbm_ctx {
   std::vector<float> modes32;
   std::vector<double> modes64;
   std::vector<FMode> fmodes;
+  std::vector<double> phitab;   // level-set mesh values (interface kind 3)
   Problem P;
   MlpFn mlp;
   EvalFn evalfn;   // persistent evaluation kernel, or null: the per-tile forward
@@ -125,6 +126,7 @@ static Layout layout_for(const nbm_ctx* c, int64_t n, int64_t nb) {
   L.modes32 = take(sizeof(float) * 8 * (c->cfg.n_modes + 1));
   L.modes64 = take(sizeof(double) * 5 * (c->cfg.n_modes + 1));
   L.fmodes = take(sizeof(FMode) * (c->fmodes.size() + 1));
+  L.phitab = take(sizeof(double) * (c->phitab.size() + 1));
   L.meta = take(sizeof(Meta));
   L.prefix = o;
   // chunk totals and offsets of the two-level scan: interior chunks, then
@@ -182,13 +184,23 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
   int h_exp = 0;
   if (!(c.h > 0.0) || c.h > 0.25 || c.h < std::ldexp(1.0, -20) || std::frexp(c.h, &h_exp) != 0.5)
     return fail(NBM_EINVAL, "h must be a power of two in [2^-20, 2^-2]");
-  if (c.interface_kind < 0 || c.interface_kind > 2) return fail(NBM_EINVAL, "bad interface kind");
+  if (c.interface_kind < 0 || c.interface_kind > 3) return fail(NBM_EINVAL, "bad interface kind");
+  if (c.interface_kind == NBM_IFACE_MESH) {
+    if (c.phi_n < 2 || c.phi_n > 1024 || !c.phi_table)
+      return fail(NBM_EINVAL, "the mesh level set needs phi_n in [2, 1024] and a table");
+    const int64_t nv = (int64_t)std::pow((double)(c.phi_n + 1), c.dim);
+    for (int64_t i = 0; i < nv; ++i)
+      if (!std::isfinite(c.phi_table[i])) return fail(NBM_EINVAL, "level-set mesh values must be finite");
+  }
   if (c.interface_kind == NBM_IFACE_STAR && c.dim != 3) return fail(NBM_EINVAL, "star needs dim 3");
   if (!(c.mu_minus > 0.0) || !(c.mu_plus > 0.0)) return fail(NBM_EINVAL, "mu must be positive");
+  if (c.mu_kind < 0 || c.mu_kind > 1) return fail(NBM_EINVAL, "bad mu_kind");
+  if (c.mu_kind == NBM_MU_PAPER && (c.dim != 3 || !(c.mu_plus < c.mu_minus)))
+    return fail(NBM_EINVAL, "the Sec. 4.1 coefficients need dim 3 and mu_minus > mu_plus (mu^+ is the smaller side)");
   if (c.levels < 0 || c.levels > 6 || std::ldexp(c.h, -c.levels) < std::ldexp(1.0, -20))
     return fail(NBM_EINVAL, "levels must be in [0, 6] with h / 2^levels >= 2^-20");
-  if (c.k_minus != 0.0 || c.k_plus != 0.0)
-    return fail(NBM_EUNSUPPORTED, "Helmholtz term k != 0 is not compiled into this library");
+  if (!(c.k_minus >= 0.0) || !(c.k_plus >= 0.0) || !std::isfinite(c.k_minus) || !std::isfinite(c.k_plus))
+    return fail(NBM_EINVAL, "k must be finite and >= 0 (the discrete operator stays positive definite)");
   if (c.problem < 0 || c.problem > 3) return fail(NBM_EINVAL, "bad problem kind");
   if (c.problem == NBM_PROB_MMS_SPHERE && c.dim != 3) return fail(NBM_EINVAL, "problem needs dim 3");
   if (c.problem == NBM_PROB_FOURIER) {
@@ -213,11 +225,17 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
   x->cfg = c;
   x->cfg.mode_k = nullptr;
   x->cfg.mode_a = x->cfg.mode_b = nullptr;
+  x->cfg.phi_table = nullptr;
+  if (c.interface_kind == NBM_IFACE_MESH)
+    x->phitab.assign(c.phi_table, c.phi_table + (size_t)std::pow((double)(c.phi_n + 1), c.dim));
   x->mlp = fn;
   x->evalfn = find_eval(c.dim, c.width, c.depth, c.act, c.prec);
   x->fused = find_fused(c.dim, c.width, c.depth, c.act, c.prec);
   x->wide = find_wide(c.dim, c.width, c.depth, c.act, c.prec);
-  x->no_fused = std::getenv("NBM_NO_FUSED") != nullptr;
+  // the fused kernels form the uncut residual of constant coefficients in
+  // their epilogue; variable coefficients take the layered path, whose
+  // residual kernel weights each face by mu at its centre
+  x->no_fused = std::getenv("NBM_NO_FUSED") != nullptr || c.mu_kind != NBM_MU_CONST;
   x->D = c.dim; x->W = c.width; x->L = c.depth; x->S = 2 * c.dim + 1;
   x->opbytes = c.prec == NBM_PREC_BF16 ? 2 : 4;
   // parameter layout of one net
@@ -240,10 +258,13 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
   for (int a = 0; a < 3; ++a) P.pn[a] = c.plane_n[a];
   P.pc = c.plane_c;
   P.mu[0] = c.mu_minus; P.mu[1] = c.mu_plus;
+  P.mu_kind = c.mu_kind;
+  P.kc[0] = c.k_minus; P.kc[1] = c.k_plus;
   P.lo = c.mu_minus == c.mu_plus ? -1 : (c.mu_minus < c.mu_plus ? 0 : 1);
   P.alpha_c = c.alpha_const; P.beta_c = c.beta_const;
   for (int a = 0; a < 4; ++a) { P.lin_a[a] = c.lin_a[a]; P.lin_b[a] = c.lin_b[a]; }
   P.h = c.h;
+  P.phi_n = c.interface_kind == NBM_IFACE_MESH ? c.phi_n : 0;
   P.n_modes = c.problem == NBM_PROB_FOURIER ? c.n_modes : 0;
   if (P.n_modes) {
     x->modes32.assign(8 * (size_t)P.n_modes, 0.0f);
@@ -362,6 +383,11 @@ extern "C" int nbm_prepare(nbm_ctx* ctx, void* stream, void* ws, size_t ws_bytes
   if (ws_bytes < ctx->lo.prefix) return fail(NBM_EWORKSPACE, "workspace too small: need " + std::to_string(ctx->lo.prefix));
   if (((uintptr_t)ws & 255) != 0) return fail(NBM_EWORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
+  if (!ctx->phitab.empty()) {
+    HIPCHK(hipMemcpyAsync(at<char>(ws, ctx->lo.phitab), ctx->phitab.data(), sizeof(double) * ctx->phitab.size(),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   if (ctx->P.n_modes) {
     HIPCHK(hipMemcpyAsync(at<char>(ws, ctx->lo.modes32), ctx->modes32.data(), sizeof(float) * ctx->modes32.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(at<char>(ws, ctx->lo.modes64), ctx->modes64.data(), sizeof(double) * ctx->modes64.size(), hipMemcpyHostToDevice, st));
@@ -377,6 +403,7 @@ static Problem problem_for(nbm_ctx* ctx, void* ws) {
   P.modes32 = at<float>(ws, ctx->lo.modes32);
   P.modes64 = at<double>(ws, ctx->lo.modes64);
   P.fmodes = at<FMode>(ws, ctx->lo.fmodes);
+  P.phitab = at<double>(ws, ctx->lo.phitab);
   return P;
 }
 

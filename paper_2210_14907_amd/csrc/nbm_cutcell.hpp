@@ -197,7 +197,7 @@ __device__ inline double jump_ext(const Problem& P, const double* y, const doubl
   double pi[3], dist, n[3];
   project<D>(P, y, pi, dist, n);
   double al = alpha_at<D>(P, pi), be = beta_at<D>(P, pi, n);
-  double mm = P.mu[0], mp = P.mu[1], j;
+  double mm = mu_at<double, D>(P, 0, pi), mp = mu_at<double, D>(P, 1, pi), j;
   if (P.lo < 0) {
     j = be / mm;
   } else {

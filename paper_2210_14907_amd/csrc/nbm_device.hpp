@@ -787,8 +787,39 @@ __device__ __forceinline__ void act_fb_l1_any(bool micro, float z, const L1Axes&
 // ---------------------------------------------------------------------------
 // Level sets (FP64).  Omega^- = {phi < 0}; phi = 0 belongs to Omega^+.
 // ---------------------------------------------------------------------------
+// level set stored on a coarse mesh of phi_n intervals per axis over
+// [-1, 1]^D: multilinear interpolation of the nodal values (the last cell
+// serves points on the upper faces)
+template <int D>
+__device__ inline double phi_mesh(const Problem& P, const double* x) {
+  const int n = P.phi_n;
+  int j[3] = {0, 0, 0};
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < D; ++a) {
+    const double t = (x[a] + 1.0) * (0.5 * n);
+    int ja = (int)floor(t);
+    ja = ja < 0 ? 0 : (ja > n - 1 ? n - 1 : ja);
+    j[a] = ja;
+    f[a] = t - (double)ja;
+  }
+  const int64_t s1 = n + 1, s2 = s1 * s1;
+  double acc = 0.0;
+  for (int c = 0; c < (1 << D); ++c) {
+    double w = 1.0;
+    int64_t q = 0;
+    for (int a = 0; a < D; ++a) {
+      const int bit = (c >> a) & 1;
+      w *= bit ? f[a] : 1.0 - f[a];
+      q += (int64_t)(j[a] + bit) * (a == 0 ? 1 : (a == 1 ? s1 : s2));
+    }
+    acc += w * P.phitab[q];
+  }
+  return acc;
+}
+
 template <int D>
 __device__ inline double phi_at(const Problem& P, const double* x) {
+  if (P.iface == 3) return phi_mesh<D>(P, x);
   if (P.iface == 2) {
     double s = -P.pc;
     for (int i = 0; i < D; ++i) s += P.pn[i] * x[i];
@@ -953,15 +984,48 @@ __device__ inline T fourier_f(const Problem& P, const T* x) {
   return acc;
 }
 
+// diffusion coefficient mu^s(x): constant, or the Sec. 4.1 functions
+// mu^- = y^2 ln(x + 2) + 4, mu^+ = e^-z
+template <class T, int D>
+__device__ inline T mu_at(const Problem& P, int s, const T* x) {
+  if (P.mu_kind == 0) return T(P.mu[s]);
+  return s == 0 ? x[1] * x[1] * log(x[0] + T(2)) + T(4) : exp(-x[2]);
+}
+template <class T, int D>
+__device__ inline void grad_mu(const Problem& P, int s, const T* x, T* g) {
+  for (int i = 0; i < D; ++i) g[i] = T(0);
+  if (P.mu_kind == 0) return;
+  if (s == 0) {
+    g[0] = x[1] * x[1] / (x[0] + T(2));
+    g[1] = T(2) * x[1] * log(x[0] + T(2));
+  } else {
+    g[2] = -exp(-x[2]);
+  }
+}
+
+// Laplacian of the manufactured u^s
+template <class T, int D>
+__device__ inline T lap_u_side(const Problem& P, int s, const T* x) {
+  if (P.kind == 0)
+    return s == 0 ? T(2) * exp(x[0] + x[1]) : T(-2.0 * M_PI * M_PI) * sin(T(M_PI) * x[0]) * cos(T(M_PI) * x[1]);
+  if (P.kind == 1) return s == 0 ? exp(x[2]) : T(-2) * cos(x[0]) * sin(x[1]);
+  return T(0);
+}
+
+// f^s = k^s u^s - div(mu^s grad u^s) = k^s u^s - mu^s Laplacian(u^s)
+// - grad mu^s . grad u^s for the manufactured problems; the Fourier series
 template <class T, int D>
 __device__ inline T f_side(const Problem& P, int s, const T* x) {
-  T mu = T(P.mu[s]);
-  if (P.kind == 0)
-    return s == 0 ? -mu * T(2) * exp(x[0] + x[1])
-                  : mu * T(2) * T(M_PI * M_PI) * sin(T(M_PI) * x[0]) * cos(T(M_PI) * x[1]);
-  if (P.kind == 1) return s == 0 ? -mu * exp(x[2]) : mu * T(2) * cos(x[0]) * sin(x[1]);
-  if (P.kind == 3) return T(0);
-  return fourier_f<T, D>(P, x);
+  if (P.kind == 2) return fourier_f<T, D>(P, x);
+  T f = -mu_at<T, D>(P, s, x) * lap_u_side<T, D>(P, s, x);
+  if (P.mu_kind != 0) {
+    T gm[3], gu[3];
+    grad_mu<T, D>(P, s, x, gm);
+    grad_u_side<T, D>(P, s, x, gu);
+    for (int i = 0; i < D; ++i) f -= gm[i] * gu[i];
+  }
+  if (P.kc[s] != 0.0) f += T(P.kc[s]) * u_side<T, D>(P, s, x);
+  return f;
 }
 
 template <int D>
@@ -978,7 +1042,7 @@ __device__ inline double beta_at(const Problem& P, const double* y, const double
   grad_u_side<double, D>(P, 0, y, gm);
   double a = 0.0, b = 0.0;
   for (int i = 0; i < D; ++i) { a += gp[i] * n[i]; b += gm[i] * n[i]; }
-  return P.mu[1] * a - P.mu[0] * b;
+  return mu_at<double, D>(P, 1, y) * a - mu_at<double, D>(P, 0, y) * b;
 }
 
 template <int D>

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
   // spreads the 16 neurons of a read over the banks
   constexpr bool kColZ = PREC == 1;
   __shared__ __attribute__((aligned(16))) T colZ[2][kColZ ? W : 1][kColZ ? kTile + 1 : 1][8];
-  __shared__ float part[NOB][kTile][1];   // per wave: w_out . sum_i E_i of each centre
+  __shared__ float part[NOB][kTile][2];   // per wave: w_out . sum_i E_i of each centre
   __shared__ float adjs[kTile][8];
   __shared__ float xs[2][kTile][4];   // by tile parity
   __shared__ L1Axes l1ax[W];
@@ -100,6 +100,10 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
     const float b1n = np.b1[n], won = np.wout[n];
     const float inv_hh = 1.0f / hh, inv_mu = 1.0f / (float)P.mu[net];
     const float kal = (float)(-scale / (double)hh);   // alpha_c = kal * r_c
+    // Helmholtz term k u of the uncut residual, r += (k/mu) u: the base stream's
+    // adjoint is alpha_c * rho with rho = -h^2 k/mu (zero without the term)
+    const bool helm = P.kc[net] != 0.0;
+    const float kmu = (float)(P.kc[net] / P.mu[net]), rho = -hh * kmu, bon = np.bout[0];
     const int64_t a_end = (int64_t)meta->base[net][KIND_A] + meta->cnt[net][KIND_A];
     const int t_lo = net == 0 ? 0 : meta->tiles[0];
     const int t_hi = net == 0 ? meta->tiles[0] : ntiles;
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
             // scale by alpha_c afterwards
             float ab, Db[3], Eb[3], zb, pb[3], eb[3];
             if (inl) {
-              ab = 0.f;
+              ab = rho * won;
               for (int a = 0; a < D; ++a) { Db[a] = 0.f; Eb[a] = won; }
             } else {
               ab = won * adjs[c][0];
@@ -235,9 +239,14 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
             if (inl) {
               float es = 0.f;
               for (int a = 0; a < D; ++a) es += Ev[a];
-              eS[j] = es;
+              // d loss / d w_out[n] of inline tiles: alpha_c (sum_i E_i + rho a)
+              eS[j] = helm ? fmaf(rho, av, es) : es;
               const float v = row16_sum(won * es);
               if (r16 == 0) part[w][c][0] = v;
+              if (helm) {
+                const float vu = row16_sum(won * av);
+                if (r16 == 0) part[w][c][1] = vu;
+              }
             } else {
               accwo += adjs[c][0] * av;
               for (int a = 0; a < D; ++a) accwo += adjs[c][1 + a] * Dv[a];
@@ -262,7 +271,13 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
       auto uncut_r = [&](int c) {
         float eu = 0.f;
         for (int v = 0; v < NOB; ++v) eu += part[v][c][0];
-        return -eu * inv_hh - xs[X][c][3] * inv_mu;
+        float r = -eu * inv_hh - xs[X][c][3] * inv_mu;
+        if (helm) {
+          float u = bon;
+          for (int v = 0; v < NOB; ++v) u += part[v][c][1];
+          r = fmaf(kmu, u, r);
+        }
+        return r;
       };
       if (inl) {
         if (tid < kTile) {
@@ -276,6 +291,9 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
           for (int s = 0; s < S; ++s) dz[s][j] *= al;
           accwo += al * eS[j];
         }
+        // d loss / d b_out = sum_c alpha_c rho (zero without the k term)
+        if (helm && tid == 0)
+          for (int c = 0; c < kTile; ++c) accbo += rho * kal * uncut_r(c);
       } else if (tid == 0) {
         for (int c = 0; c < kTile; ++c) accbo += adjs[c][0];
       }

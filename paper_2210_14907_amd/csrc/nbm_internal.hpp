@@ -31,7 +31,10 @@ struct FMode {
 struct Problem {
   int dim, iface, kind, lo;   // lo: side with the smaller mu (0 minus, 1 plus), -1 if equal
   double R, amp, pn[3], pc;
-  double mu[2];
+  double mu[2];               // constant coefficients (mu_kind 0); with mu_kind 1 they only
+                              // record which side has the smaller coefficient
+  int mu_kind;                // 0 constant, 1 mu^- = y^2 ln(x+2) + 4, mu^+ = e^-z (Sec. 4.1)
+  double kc[2];               // Helmholtz coefficients k^-+ of the term k u (>= 0)
   double alpha_c, beta_c;
   double lin_a[4], lin_b[4];
   double h;
@@ -40,6 +43,8 @@ struct Problem {
   const double* modes64;  // [n_modes][5]: k0 k1 k2 a b
   int n_fmodes;           // padded count
   const FMode* fmodes;    // in group order
+  int phi_n;              // level set on a coarse mesh: intervals per axis
+  const double* phitab;   // its (phi_n + 1)^dim nodal values, axis 0 fastest
 };
 
 // Batch bookkeeping written on the device by the scan kernel.

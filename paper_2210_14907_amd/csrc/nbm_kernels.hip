@@ -455,20 +455,20 @@ __global__ void k_fill(float* p, int64_t n, float v) {
 // the FP64 loss partials (fixed strided order, then a fixed tree).  Both
 // outputs are NaN when the batch overflowed the cut capacity.
 // Several resolution levels of one batch accumulate in FP64 across
-// launches: acc = 0 a single level (write grad / loss), 1 the first level
+// launches: mode 0 a single level (write grad / loss), 1 the first level
 // (write the FP64 accumulators), 2 a middle level (add to them), 3 the last
 // level (write accumulator + this level).
-__device__ __forceinline__ double acc_level(int acc, double* slot, double v) {
-  if (acc == 1) { *slot = v; return v; }
-  if (acc == 2) { *slot += v; return v; }
-  if (acc == 3) return *slot + v;
+__device__ __forceinline__ double acc_level(int mode, double* slot, double v) {
+  if (mode == 1) { *slot = v; return v; }
+  if (mode == 2) { *slot += v; return v; }
+  if (mode == 3) return *slot + v;
   return v;
 }
 
 __global__ __launch_bounds__(1024) void k_reduce(const float* partial, int G, int64_t P, float* grad,
                                                  double scale, const double* lp, int nparts,
                                                  const Meta* meta, double* loss, double* gacc,
-                                                 double* lacc, int acc) {
+                                                 double* lacc, int mode) {
   __shared__ double sh[16][64];
   const int c = threadIdx.x & 63, k = threadIdx.x >> 6;
   if (loss && blockIdx.x == gridDim.x - 1) {
@@ -484,8 +484,8 @@ __global__ __launch_bounds__(1024) void k_reduce(const float* partial, int G, in
     if (threadIdx.x == 0) {
       double L = fl[0] / (double)(meta->n + meta->nb);
       if (meta->overflow) L = __builtin_nan("");
-      L = acc_level(acc, lacc, L);
-      if (acc == 0 || acc == 3) *loss = L;
+      L = acc_level(mode, lacc, L);
+      if (mode == 0 || mode == 3) *loss = L;
     }
     return;
   }
@@ -517,8 +517,8 @@ __global__ __launch_bounds__(1024) void k_reduce(const float* partial, int G, in
     // a batch whose cut cells overflowed the capacity dropped some of them:
     // its gradient is marked NaN like its loss, never returned partial
     double v = meta->overflow ? __builtin_nan("") : t * scale;
-    v = acc_level(acc, gacc + j, v);
-    if (acc == 0 || acc == 3) grad[j] = (float)v;
+    v = acc_level(mode, gacc + j, v);
+    if (mode == 0 || mode == 3) grad[j] = (float)v;
   }
 }
 
@@ -589,7 +589,7 @@ __device__ inline double block_sum(double v, double* sh) {
 // ===========================================================================
 // Residual kernels (paper Sec. 3: r_p = |M^-1 A u - M^-1 b| per point)
 // ===========================================================================
-// uncut cells: r = -sum_i eu_i / h^2 - f^s(x) / mu^s
+// uncut cells: r = -sum_i eu_i / h^2 + (k^s u - f^s(x)) / mu^s
 template <int D>
 __device__ inline void res_uncut_block(Problem P, const Meta* meta, const float* pts,
                                                    int64_t n, const int* cls, const int* rank,
@@ -613,13 +613,47 @@ __device__ inline void res_uncut_block(Problem P, const Meta* meta, const float*
       float lap = 0.0f;
       for (int a = 0; a < D; ++a) lap += outputs[slot * 8 + 1 + D + a];
       float fv = fpre ? fpre[i] : f_side<float, D>(P, c, x);
-      float r = -lap / hh - fv / (float)P.mu[c];
+      float row[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      float r;
+      if (P.mu_kind == 0) {
+        const float kmu = (float)(P.kc[c] / P.mu[c]);
+        r = -lap / hh - fv / (float)P.mu[c];
+        if (kmu != 0.0f) r += kmu * outputs[slot * 8];
+        const float rb = (float)(scale * (double)r);
+        // the whole adjoint row (u: rb k/mu, D streams 0, E streams -rb/h^2)
+        row[0] = rb * kmu;
+        for (int a = 0; a < D; ++a) row[1 + D + a] = -rb / hh;
+      } else {
+        // mu^s at the face centres x +- (h/2) e_a (FP64: their differences
+        // are O(h) and weight the O(h) first differences):
+        //   R = -(1/h^2) sum_a [mu_a+ du_a + mu_a- (eu_a - du_a)] + k u - f,
+        //   r = R / mubar, mubar = mean of the 2d face values
+        double xd[3] = {0, 0, 0}, mup[3], mum[3], msum = 0.0;
+        for (int a = 0; a < D; ++a) xd[a] = x[a];
+        for (int a = 0; a < D; ++a) {
+          double y[3] = {xd[0], xd[1], xd[2]};
+          y[a] = xd[a] + 0.5 * P.h;
+          mup[a] = mu_at<double, D>(P, c, y);
+          y[a] = xd[a] - 0.5 * P.h;
+          mum[a] = mu_at<double, D>(P, c, y);
+          msum += mup[a] + mum[a];
+        }
+        const double mubar = msum / (2 * D), h2 = P.h * P.h;
+        double R = P.kc[c] * (double)outputs[slot * 8] - (double)fv;
+        for (int a = 0; a < D; ++a) {
+          const double du = outputs[slot * 8 + 1 + a], eu = outputs[slot * 8 + 1 + D + a];
+          R -= ((mup[a] - mum[a]) * du + mum[a] * eu) / h2;
+        }
+        r = (float)(R / mubar);
+        const double rb = scale * (double)r / mubar;
+        row[0] = (float)(rb * P.kc[c]);
+        for (int a = 0; a < D; ++a) {
+          row[1 + a] = (float)(-rb * (mup[a] - mum[a]) / h2);
+          row[1 + D + a] = (float)(-rb * mum[a] / h2);
+        }
+      }
       if (resid) resid[i] = r;
       r2 = (double)r * (double)r;
-      float rb = (float)(scale * (double)r);
-      // the whole adjoint row (u and D streams 0, E streams -rb/h^2)
-      float row[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      for (int a = 0; a < D; ++a) row[1 + D + a] = -rb / hh;
       float4* dst = (float4*)(adj + slot * 8);
       dst[0] = make_float4(row[0], row[1], row[2], row[3]);
       dst[1] = make_float4(row[4], row[5], row[6], row[7]);
@@ -743,7 +777,7 @@ __device__ inline double res_cut_cell(Problem P, const Meta* meta, const float* 
     }
     bt = b_t;
   }
-  double vneg = 0.0, dU[6], cF[6], csum = 0.0, flux_corr = 0.0, mubar = 1.0, src = 0.0;
+  double vneg = 0.0, dU[6], cF[6], csum = 0.0, flux_corr = 0.0, mubar = 1.0, src = 0.0, kap = 0.0, kcorr = 0.0;
   if (tid == 0) {
     for (int t = 0; t < NT; ++t) vneg += tvol[t];
     vneg /= NT;
@@ -764,28 +798,34 @@ __device__ inline double res_cut_cell(Problem P, const Meta* meta, const float* 
       if (s_ == 0) return sd[k] == 0 ? 0.0 : -Jn[k];
       return sd[k] == 0 ? Jn[k] : 0.0;
     };
-    const double mm = P.mu[0], mp = P.mu[1];
     for (int F = 0; F < 2 * D; ++F) {
       double an = D == 2 ? fpart[F] : 0.5 * (fpart[2 * F] + fpart[2 * F + 1]);
       double ap = 1.0 - an;
+      // mu^s at the face centre x +- (h/2) e_a
+      double xf[3] = {x[0], x[1], x[2]};
+      xf[F >> 1] += (F & 1) ? -0.5 * h : 0.5 * h;
+      const double mm = mu_at<double, D>(P, 0, xf), mp = mu_at<double, D>(P, 1, xf);
       cF[F] = mm * an + mp * ap;
       csum += cF[F];
       flux_corr += mm * an * (corr(0, F + 1) - corr(0, 0)) + mp * ap * (corr(1, F + 1) - corr(1, 0));
     }
     mubar = csum / (2 * D);
     src = vneg * fs[0] + (1.0 - vneg) * fs[1];
+    // Helmholtz term sum_s k^s v^s u~^s(y_0) = kap U_0 + its corrections' part
+    kap = P.kc[0] * vneg + P.kc[1] * (1.0 - vneg);
+    kcorr = P.kc[0] * vneg * corr(0, 0) + P.kc[1] * (1.0 - vneg) * corr(1, 0);
   }
   __syncthreads();
   if (tid != 0) return 0.0;
   const double bterm = bt;
-  double R = -flux_corr / (h * h) - src + bterm;
+  double R = -flux_corr / (h * h) + kcorr + kap * os[sd[0]][0] - src + bterm;
   for (int F = 0; F < 2 * D; ++F) R -= cF[F] * dU[F] / (h * h);
   double r = R / mubar;
   resid[p] = (float)r;
-  // adjoints: dr/dU_F = -c_F/(h^2 mubar), dr/dU_0 = sum_F c_F/(h^2 mubar)
+  // adjoints: dr/dU_F = -c_F/(h^2 mubar), dr/dU_0 = (sum_F c_F/h^2 + kap)/mubar
   double rb = scale * r;
   double Ub[7];
-  Ub[0] = rb * csum / (h * h * mubar);
+  Ub[0] = rb * (csum / (h * h) + kap) / mubar;
   for (int F = 0; F < 2 * D; ++F) Ub[F + 1] = -rb * cF[F] / (h * h * mubar);
   double g[2][7];
   for (int t = 0; t < 2; ++t)

@@ -62,7 +62,7 @@ def train(wl: I.Workload, steps: int = None, lr: float = None, seed: int = 1, pa
     lr = wl.lr if lr is None else lr
     nbm = NBM(wl) if nbm is None else nbm
     dev = nbm.device
-    params = init_params(wl, 0, dev) if params is None else params
+    params = nbm.embed(I.xavier_params(wl, 0)) if params is None else params
     if state is None:
         state = {"m": torch.zeros_like(params), "v": torch.zeros_like(params)}
     losses = torch.empty(steps, dtype=torch.float64, device=dev)

@@ -25,7 +25,8 @@ def near_star_points(wl, n, band, seed=9):
 def parity_batch(wl, n, nb, n_near, band, seed=1):
     pts, bpts = I.collocation_batch(wl, n, nb, seed=seed)
     if n_near:
-        if wl.interface == I.IFACE_STAR:
+        star = wl.interface == I.IFACE_STAR or (wl.interface == I.IFACE_GRID and wl.phi_shape == I.IFACE_STAR)
+        if star:
             near = near_star_points(wl, n_near, band, seed=seed + 11)
         else:
             near = I.near_interface_points(wl, n_near, band, seed=seed + 11)
@@ -66,15 +67,19 @@ def param_blocks(wl):
     return out
 
 
-def grad_block_ratios(wl, g, g_o, tol, floor=1e-3):
+def grad_block_ratios(wl, g, g_o, tol, floor=1e-3, scale=None):
     """Per parameter block, the largest |g - g_o| / (tol (|g_o| + floor max|g_o|_block)):
     every entry of every block must be within tol of the oracle relative to its
-    own size, entries far below the block's largest one relative to that."""
+    own size, entries far below the block's largest one relative to that.
+    When the gradient is a sum of parts (resolution levels), scale holds the
+    sum of the parts' magnitudes and the floor is taken relative to it: the
+    parts' rounding does not cancel where their values do."""
     g = np.asarray(g, dtype=np.float64)
     g_o = np.asarray(g_o, dtype=np.float64)
+    sc = np.abs(g_o) if scale is None else np.asarray(scale, dtype=np.float64)
     out = {}
     for name, sl in param_blocks(wl):
         a, b = g[sl], g_o[sl]
-        bound = tol * (np.abs(b) + floor * np.abs(b).max())
+        bound = tol * (np.abs(b) + floor * sc[sl].max())
         out[name] = float(np.max(np.abs(a - b) / np.where(bound > 0, bound, 1.0)))
     return out

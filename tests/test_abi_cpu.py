@@ -65,7 +65,8 @@ def test_create_counts_and_workspace(wl):
 def test_create_rejects_bad_configs():
     from paper_2210_14907_amd import binding as B
     bad = [dict(dim=4), dict(depth=1), dict(h=0.3), dict(h=0.01), dict(mu_minus=0.0),
-           dict(k_minus=1.0), dict(width=24), dict(act=7), dict(max_points=0)]
+           dict(k_minus=-1.0), dict(k_plus=float("nan")), dict(width=24), dict(act=7), dict(max_points=0),
+           dict(levels=7), dict(levels=-1), dict(h=2.0 ** -18, levels=3)]
     for over in bad:
         rc, _ = _create(_cfg(I.C2, **over))
         assert rc < 0, over

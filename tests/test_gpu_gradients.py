@@ -15,9 +15,10 @@ NBM kernels, then Adam).
 Every gradient entry must satisfy |g - g_o| <= tol (|g_o| + floor max|g_o|)
 with max over its parameter block: tol 1e-5 and floor 0.1 with FP32 operands
 (entries resolved down to 1e-6 of the block's largest; FP32 partial sums over
-thousands of terms per work-group carry ~1e-7 of it), tol 2e-2 and floor 0.2
-with BF16 operands (resolved down to 2^-8 of the block's largest: the BF16
-rounding of both factors of each weight-gradient product, 2^-9 each)."""
+thousands of terms per work-group carry ~1e-7 of it), tol 2e-2 and floor 0.5
+with BF16 operands (resolved down to 1e-2 of the block's largest: the BF16
+roundings, 2^-9 each, of the activations and adjoints of L = 4 hidden layers
+compound to about (L + 1) 2^-9 = 1e-2 of a block's scale)."""
 import numpy as np
 import pytest
 
@@ -30,7 +31,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = {I.PREC_FP32: 1e-5, I.PREC_BF16: 2e-2}
-FLOOR = {I.PREC_FP32: 0.1, I.PREC_BF16: 0.2}
+FLOOR = {I.PREC_FP32: 0.1, I.PREC_BF16: 0.5}
 DEV = "cuda:0"
 
 
@@ -126,6 +127,7 @@ def test_c4_many_tiles_per_net_gradient_elementwise():
 
 
 CASES = [
+    ("c2_h1024", I.C2.replace(h=1.0 / 1024), 4096, 96, 512, 0.004),
     ("c1", I.C1, 4096, 256, 256, 0.05),
     ("c2", I.C2, 4096, 96, 512, 0.02),
     ("c2_bf16", I.C2.replace(prec=I.PREC_BF16), 4096, 96, 512, 0.02),

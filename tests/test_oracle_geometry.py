@@ -126,3 +126,66 @@ def test_star_level_set_definition():
     th, ps, r = math.pi / 10, math.pi / 8, 0.55
     q = np.array([[r * math.sin(ps) * math.cos(th), r * math.sin(ps) * math.sin(th), r * math.cos(ps)]])
     assert G.phi(wl, q)[0] == pytest.approx(r - 0.5 - 0.1, abs=1e-14)
+
+
+def _mesh_wl(shape, n, **kw):
+    return I.C2.replace(interface=I.IFACE_GRID, phi_shape=shape, phi_n=n, **kw)
+
+
+def test_mesh_level_set_interpolates_its_nodes():
+    """The coarse-mesh level set equals its nodal values at the nodes, is
+    linear along mesh edges and multilinear inside a cell (midpoint of a cell
+    = mean of its 8 corners)."""
+    wl = _mesh_wl(I.IFACE_STAR, 8)
+    tab = I.phi_table(wl)
+    n = 8
+    rng = np.random.default_rng(4)
+    j = rng.integers(0, n + 1, size=(50, 3))
+    x = -1.0 + 2.0 * j / n
+    flat = j[:, 0] + (n + 1) * j[:, 1] + (n + 1) ** 2 * j[:, 2]
+    assert np.allclose(G.phi(wl, x), tab[flat], rtol=0, atol=1e-14)
+    j = rng.integers(0, n, size=(50, 3))
+    mid = -1.0 + 2.0 * (j + 0.5) / n
+    corners = sum(tab[(j[:, 0] + a) + (n + 1) * (j[:, 1] + b) + (n + 1) ** 2 * (j[:, 2] + c)]
+                  for a in (0, 1) for b in (0, 1) for c in (0, 1)) / 8.0
+    assert np.allclose(G.phi(wl, mid), corners, rtol=0, atol=1e-14)
+    t = rng.uniform(0, 1, size=50)
+    e0 = -1.0 + 2.0 * j / n
+    e1 = e0.copy()
+    e1[:, 1] += 2.0 / n
+    pe = G.phi(wl, (1 - t)[:, None] * e0 + t[:, None] * e1)
+    assert np.allclose(pe, (1 - t) * G.phi(wl, e0) + t * G.phi(wl, e1), rtol=0, atol=1e-13)
+
+
+def test_mesh_level_set_of_a_plane_is_the_plane():
+    """Multilinear interpolation reproduces a linear function exactly, so a
+    mesh sampling the plane gives the analytic plane's sides, cut-cell
+    geometry and interface data."""
+    wp = I.C2.replace(interface=I.IFACE_PLANE, plane_n=(0.6, 0.48, 0.64), plane_c=0.07)
+    wm = _mesh_wl(I.IFACE_PLANE, 8, plane_n=(0.6, 0.48, 0.64), plane_c=0.07)
+    x = I.lattice_points(4000, 3, -0.99, 0.99, seed=3)
+    assert np.allclose(G.phi(wm, x), G.phi(wp, x), rtol=0, atol=1e-13)
+    xc = x[np.abs(G.phi(wp, x)) < 0.02][:300]
+    gp, gm = G.cell_geometry(wp, xc, 1 / 64), G.cell_geometry(wm, xc, 1 / 64)
+    for k in ("aneg", "vneg", "gamma", "cen"):
+        assert np.allclose(gp[k], gm[k], rtol=0, atol=1e-11), k
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_mesh_sphere_volume_converges(dim):
+    """A mesh sampling the sphere (circle): the volume of Omega^- from the
+    cells' simplex clipping approaches the closed form at second order as the
+    level-set mesh is refined."""
+    base = I.C1 if dim == 2 else I.C2
+    h = 1.0 / 32
+    xs = -1.0 + h * (np.arange(int(2 / h)) + 0.5)
+    xc = np.stack(np.meshgrid(*([xs] * dim), indexing="ij"), axis=-1).reshape(-1, dim)
+    exact = math.pi * 0.25 if dim == 2 else 4.0 / 3.0 * math.pi * 0.125
+    errs = []
+    for n in (8, 16, 32):
+        wl = base.replace(interface=I.IFACE_GRID, phi_shape=I.IFACE_SPHERE, phi_n=n)
+        near = np.abs(np.sqrt((xc * xc).sum(axis=1)) - 0.5) < 3 * h
+        inside = (np.sqrt((xc * xc).sum(axis=1)) < 0.5) & ~near
+        vol = (inside.sum() + G.cell_geometry(wl, xc[near], h)["vneg"].sum()) * h ** dim
+        errs.append(abs(vol - exact))
+    assert errs[1] < errs[0] / 3 and errs[2] < errs[1] / 2.5, errs

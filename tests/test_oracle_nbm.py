@@ -135,3 +135,53 @@ def test_multiresolution_gradient_finite_differences():
         e[j] = step
         fd = (N.multires_loss(wl, th + e, pts, bpts) - N.multires_loss(wl, th - e, pts, bpts)) / (2 * step)
         assert abs(g[j] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max()), (j, g[j], fd)
+
+
+@pytest.mark.parametrize("mu_plus", [1.0, 10.0])
+def test_helmholtz_gradient_finite_differences(mu_plus):
+    """With k^- = 2, k^+ = 5 the centre value enters every residual: the
+    gradient still matches central differences (lagged term held fixed)."""
+    wl = I.C2.replace(width=6, depth=2, act=I.ACT_SIN, h=1.0 / 16, mu_plus=mu_plus, k_minus=2.0, k_plus=5.0)
+    th = I.xavier_params(wl, 3) * 1.5
+    pts, bpts = I.collocation_batch(wl, 60, 8, seed=9)
+    pts = np.concatenate([pts, I.near_interface_points(wl, 30, 0.05, seed=10)])
+    glo = N.residuals(wl, th, pts, bpts)["glo"] if S.lo_side(wl) >= 0 else None
+    rng = np.random.default_rng(2)
+    res = _fd_check(wl, th, pts, bpts, rng.choice(th.size, 10, replace=False), glo=glo)
+    assert (res["cls"] == S.CLASS_CUT).sum() > 5
+
+
+def test_helmholtz_uncut_residual_of_the_exact_solution_is_second_order():
+    wl = I.C2.replace(k_minus=2.0, k_plus=5.0)
+    pts, _ = I.collocation_batch(wl, 3000, 0, seed=4)
+    rms = []
+    for h in (1 / 16, 1 / 32, 1 / 64):
+        res = N.residuals(wl, None, pts, np.zeros((0, 3)), h=h, provider=N.exact_provider(wl))
+        m = res["cls"] != S.CLASS_CUT
+        rms.append(np.sqrt(np.mean(res["r"][m] ** 2)))
+    assert rms[0] / rms[1] > 3.5 and rms[1] / rms[2] > 3.5
+
+
+def test_variable_mu_gradient_finite_differences():
+    """The Sec. 4.1 coefficients (face-centre mu in every row, mu at the
+    projection point in the jump extension): gradient against central
+    differences on tiny sine nets (lagged term held fixed)."""
+    wl = I.PAPER.replace(width=5, depth=3, h=1.0 / 16)
+    th = I.xavier_params(wl, 4) * 1.5
+    pts, bpts = I.collocation_batch(wl, 60, 8, seed=11)
+    pts = np.concatenate([pts, I.near_interface_points(wl, 30, 0.05, seed=12)])
+    glo = N.residuals(wl, th, pts, bpts)["glo"]
+    rng = np.random.default_rng(3)
+    res = _fd_check(wl, th, pts, bpts, rng.choice(th.size, 10, replace=False), glo=glo)
+    assert (res["cls"] == S.CLASS_CUT).sum() > 5
+
+
+def test_variable_mu_exact_solution_residual_second_order():
+    wl = I.PAPER
+    pts, _ = I.collocation_batch(wl, 3000, 0, seed=4)
+    rms = []
+    for h in (1 / 16, 1 / 32, 1 / 64):
+        res = N.residuals(wl, None, pts, np.zeros((0, 3)), h=h, provider=N.exact_provider(wl))
+        m = res["cls"] != S.CLASS_CUT
+        rms.append(np.sqrt(np.mean(res["r"][m] ** 2)))
+    assert rms[0] / rms[1] > 3.5 and rms[1] / rms[2] > 3.5, rms
