@@ -151,6 +151,25 @@ int nbm_forward_residual(nbm_ctx* ctx, void* stream, const float* params, const 
                          int64_t n, const float* bpts, int64_t nb, float* residual,
                          double* loss, float* grad, void* ws, size_t ws_bytes);
 
+/* Allocation-free form of nbm_forward_residual, for callers that cannot
+ * allocate device memory or pass a workspace (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  Same arguments and
+ * results as nbm_forward_residual without the workspace: the step runs in a
+ * static device array of NBM_SCRATCH_BYTES (64 MiB) that the library holds on
+ * each GPU it runs on until the process ends; no call allocates or frees.
+ * Returns NBM_EWORKSPACE if the batch's workspace (nbm_workspace_bytes(ctx,
+ * n, nb)) exceeds NBM_SCRATCH_BYTES -- the 64-wide and 16-wide networks fit
+ * up to their full training batches, the 128-wide ones do not -- and
+ * NBM_EUNSUPPORTED for the Fourier problem (its tables live in a prepared
+ * workspace).  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents: calls that overlap on one GPU (two streams, two
+ * threads, two contexts) race and must be serialised by the caller.
+ * nbm_batch_counts does not see this entry point's batches. */
+#define NBM_SCRATCH_BYTES (64ull << 20)
+int nbm_forward_residual_noalloc(nbm_ctx* ctx, void* stream, const float* params, const float* pts,
+                                 int64_t n, const float* bpts, int64_t nb, float* residual,
+                                 double* loss, float* grad);
+
 /* Backward pass (paper Sec. 3: automatic differentiation across the NBM
  * kernels): recomputes the forward pass and writes dL * dL/dtheta into
  * grad [P] (device FP32).  Holds no state between calls. */

@@ -18,7 +18,7 @@ LIB_PATH = Path(__file__).resolve().parent / "libnbm.so"
 _lib = None
 
 EXPORTS = ["nbm_create", "nbm_destroy", "nbm_param_count", "nbm_workspace_bytes", "nbm_prepare",
-           "nbm_sample_points", "nbm_forward_residual", "nbm_backward", "nbm_adam_step", "nbm_eval",
+           "nbm_sample_points", "nbm_forward_residual", "nbm_forward_residual_noalloc", "nbm_backward", "nbm_adam_step", "nbm_eval",
            "nbm_grid_interp",
            "nbm_batch_counts", "nbm_set_timing", "nbm_read_timing", "nbm_last_error"]
 
@@ -99,6 +99,7 @@ def lib():
         L.nbm_prepare.argtypes = [vp, vp, vp, ctypes.c_size_t]
         L.nbm_sample_points.argtypes = [vp, vp, ctypes.c_uint64, i64, vp, i64, vp, i64]
         L.nbm_forward_residual.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, ctypes.c_size_t]
+        L.nbm_forward_residual_noalloc.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp, vp, vp]
         L.nbm_backward.argtypes = [vp, vp, vp, vp, i64, vp, i64, f64, vp, vp, ctypes.c_size_t]
         L.nbm_adam_step.argtypes = [vp, vp, vp, vp, vp, vp, i64, f32, f32, f32, f32]
         L.nbm_eval.argtypes = [vp, vp, vp, vp, i64, i64, ctypes.c_int32, vp, vp, ctypes.c_size_t]
@@ -232,6 +233,14 @@ class NBM:
                                           _ptr(grad) if want_grad else None, _ptr(self.ws_view),
                                           self.ws_bytes))
         return loss, (residual if want_residual else None), (grad if want_grad else None)
+
+    def forward_residual_noalloc(self, params, pts, bpts, loss, residual=None, grad=None):
+        """nbm_forward_residual_noalloc: the same step in the library's static
+        per-GPU scratch (no workspace); every output buffer is the caller's."""
+        _check(lib().nbm_forward_residual_noalloc(self.ctx, _stream(), _ptr(params), _ptr(pts), pts.shape[0],
+                                                  _ptr(bpts), bpts.shape[0], _ptr(residual), _ptr(loss),
+                                                  _ptr(grad)))
+        return loss, residual, grad
 
     def backward(self, params, pts, bpts, dL=1.0, grad=None):
         if grad is None:

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -666,6 +667,56 @@ extern "C" int nbm_backward(nbm_ctx* ctx, void* stream, const float* params, con
   rc = check_ws(ctx, ws, ws_bytes, Lo);
   if (rc) return rc;
   return run_step(ctx, (hipStream_t)stream, params, pts, n, bpts, nb, nullptr, nullptr, grad, dL, ws, Lo);
+}
+
+// Scratch of the allocation-free entry point: one copy of this array per GPU,
+// held until the process ends.  Host code never uses the array's name as an
+// address: the device address of this GPU's copy comes from
+// hipGetSymbolAddress, once per device, with that device current.
+static_assert(NBM_SCRATCH_BYTES % 256 == 0, "scratch size is a multiple of 256 bytes");
+static __device__ __align__(256) unsigned char scratch[NBM_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+static void* g_scratch[kMaxDevices];
+
+static int scratch_of_current_device(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(NBM_EHIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(NBM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return NBM_OK;
+}
+
+extern "C" int nbm_forward_residual_noalloc(nbm_ctx* ctx, void* stream, const float* params,
+                                            const float* pts, int64_t n, const float* bpts, int64_t nb,
+                                            float* residual, double* loss, float* grad) {
+  if (!ctx || !params || !loss) return fail(NBM_EINVAL, "null argument");
+  if (ctx->P.n_modes)
+    return fail(NBM_EUNSUPPORTED, "the allocation-free entry point does not serve the Fourier problem "
+                                  "(its mode tables would need a host-to-device copy): use "
+                                  "nbm_forward_residual with a prepared workspace");
+  int rc = check_points(ctx, pts, n, bpts, nb);
+  if (rc) return rc;
+  const Layout Lo = layout_for(ctx, n, nb);
+  if (Lo.total > (size_t)NBM_SCRATCH_BYTES)
+    return fail(NBM_EWORKSPACE, "batch needs " + std::to_string(Lo.total) + " bytes of scratch; the "
+                                "allocation-free entry point holds " + std::to_string((size_t)NBM_SCRATCH_BYTES) +
+                                " (use nbm_forward_residual with a workspace)");
+  void* ws = nullptr;
+  rc = scratch_of_current_device(&ws);
+  if (rc) return rc;
+  // every region the step reads is written earlier in the same call (the
+  // batch bookkeeping by the scan, partial rows and loss partials by their
+  // kernels), so nothing needs clearing between calls
+  return run_step(ctx, (hipStream_t)stream, params, pts, n, bpts, nb, residual, loss, grad, 1.0, ws, Lo);
 }
 
 extern "C" int nbm_adam_step(nbm_ctx* ctx, void* stream, float* params, float* m, float* v,
