@@ -90,13 +90,15 @@ def flops_per_point(wl):
 
 class Run:
     """One workload on the device: parameters, optimiser state, a step
-    function, and the step counter."""
+    function, and the step counter.  With lr_final the Adam step size
+    decays geometrically from the workload's rate to lr_final over
+    wl.steps steps."""
 
-    def __init__(self, wl, seed=1, cut_capacity=0):
+    def __init__(self, wl, seed=1, cut_capacity=0, lr_final=None):
         import torch
         import nbm_inputs as I
         from paper_2210_14907_amd import NBM
-        self.wl, self.seed = wl, seed
+        self.wl, self.seed, self.lr_final = wl, seed, lr_final
         self.nbm = NBM(wl, cut_capacity=cut_capacity)
         dev = self.nbm.device
         self.params = self.nbm.embed(I.xavier_params(wl, 0))
@@ -112,7 +114,10 @@ class Run:
         pts, bpts = self.nbm.sample_points(self.seed, k)
         self.nbm.forward_residual(self.params, pts, bpts, want_grad=True,
                                   loss=self.losses[k:k + 1], grad=self.grad)
-        self.nbm.adam_step(self.params, self.m, self.v, self.grad, k, lr=self.wl.lr)
+        lr = self.wl.lr
+        if self.lr_final is not None:
+            lr *= (self.lr_final / lr) ** (min(k - 1, self.wl.steps) / max(1, self.wl.steps - 1))
+        self.nbm.adam_step(self.params, self.m, self.v, self.grad, k, lr=lr)
 
     def train_to(self, steps):
         import torch
@@ -408,22 +413,24 @@ PAPER_TABLE1 = {8: (3.7e-2, 3.25e-1), 16: (7.1e-3, 1.10e-1), 32: (5.9e-3, 8.36e-
                 64: (4.1e-3, 6.44e-2), 128: (2.64e-3, 3.53e-2)}
 
 
-def paper_convergence(steps=4000, n_points=32768, Ns=(8, 16, 32, 64, 128)):
+def paper_convergence(steps=10000, n_points=32768, Ns=(8, 16, 32, 64, 128), lr=1e-3, lr_final=None):
     """The paper's convergence workload (Sec. 4.1): sphere r = 0.5,
     u^- = e^z, u^+ = cos x sin y, mu^- = y^2 ln(x+2) + 4, mu^+ = e^-z, two
     5 x 10 sine networks (982 parameters, run zero-padded to 16 wide).  For
     each N the cells have side h = 2/N, each step draws n_points interior
-    points, and after `steps` Adam steps the surrogate is compared with the
-    closed-form solution at the (N-1)^3 interior nodes of the N^3 grid."""
+    points, and after `steps` Adam steps (10,000 epochs in the paper's
+    table; step size lr, or decaying geometrically to lr_final) the
+    surrogate is compared with the closed-form solution at the (N-1)^3
+    interior nodes of the N^3 grid."""
     import torch
     import nbm_inputs as I
     out = []
     for N in Ns:
         h = 2.0 / N
-        wl = I.PAPER.replace(h=h, n_points=n_points, n_boundary=int(round(n_points * 3 * h)), steps=steps)
+        wl = I.PAPER.replace(h=h, n_points=n_points, n_boundary=int(round(n_points * 3 * h)), steps=steps, lr=lr)
         log(f"paper workload N = {N}: {steps} steps of {wl.n_points} + {wl.n_boundary} points")
         # coarse cells (h = 1/4, 1/8) cut a large share of the points
-        run = Run(wl, cut_capacity=wl.n_points)
+        run = Run(wl, cut_capacity=wl.n_points, lr_final=lr_final)
         torch.cuda.synchronize()
         t0 = time.time()
         loss = run.train_to(steps)
@@ -437,7 +444,7 @@ def paper_convergence(steps=4000, n_points=32768, Ns=(8, 16, 32, 64, 128)):
         u = np.concatenate([run.nbm.eval(run.params, q[i:i + cap]).cpu().numpy() for i in range(0, len(q), cap)])
         e = u - prob.u_exact(x)
         rm, li = PAPER_TABLE1[N]
-        out.append({"N": N, "h": h, "steps": steps, "seconds": round(dt, 2), "ms_per_step": round(1e3 * dt / steps, 3),
+        out.append({"N": N, "h": h, "steps": steps, "n_points": n_points, "lr": [lr, lr_final], "seconds": round(dt, 2), "ms_per_step": round(1e3 * dt / steps, 3),
                     "final_loss": loss, "rmse": float(np.sqrt(np.mean(e * e))), "linf": float(np.abs(e).max()),
                     "paper_table1_rmse_linf": [rm, li]})
         del run
