@@ -448,6 +448,19 @@ constexpr float kMicroX = 0.00390625f;   // 1/256
 // 1.4e-8) stay two orders of magnitude below the BF16 rounding of values of
 // the size of E there (2^-9 x^2 ~ 1.9e-6 at x = 1/32).
 constexpr float kMicroXBf16 = 0.03125f;  // 1/32
+// Series orders of the micro tier: f to k = F, the derivative series to
+// k = G.  Sine with BF16 operands stops one term earlier (f to k = 3, g to
+// k = 4): at |x| <= 1/32 the omitted terms are at most 2 x^4/24 and
+// 2 x^4/24 again (|c_4| <= 1/24, 5|c_5| <= 1/24), 7.9e-8, one to two orders
+// of magnitude below the BF16 rounding of the terms they sit next to
+// (2^-9 x^2 ~ 1.9e-6 for f, 2^-9 x^2/2 for g).  For tanh |c_4| reaches 0.17
+// and 5|c_5| 0.67, too close to that rounding, so tanh keeps the longer
+// series.
+template <int ACT, int MICRO>
+struct MicroOrder {
+  static constexpr int F = (MICRO == 2 && ACT == 1) ? 3 : 4;
+  static constexpr int G = F + 1;
+};
 struct Taylor { float a, c[8]; };   // c[1..K]
 
 template <int ACT, int K = 7>
@@ -586,9 +599,9 @@ template <int ACT, int D, int MICRO = 0>
 __device__ __forceinline__ void act_fwd(float z, const float* p, const float* e, float& a,
                                         float* Dv, float* Ev) {
   if (MICRO > 0 && __all(micro_args<D, MICRO>(p, e))) {
-    const Taylor T = taylor_at<ACT, 5>(z);
+    const Taylor T = taylor_at<ACT, MicroOrder<ACT, MICRO>::G>(z);
     a = T.a;
-    taylor_fwd<D, 4>(T, p, e, Dv, Ev);
+    taylor_fwd<D, MicroOrder<ACT, MICRO>::F>(T, p, e, Dv, Ev);
   } else if (__all(tiny_args<ACT, D>(p, e))) {
     const Taylor T = taylor_at<ACT>(z);
     a = T.a;
@@ -607,7 +620,8 @@ __device__ __forceinline__ void act_bwd(float z, const float* p, const float* e,
                                         const float* Db, const float* Eb, float& zb, float* pb,
                                         float* eb) {
   if (MICRO > 0 && __all(micro_args<D, MICRO>(p, e))) {
-    taylor_bwd<D, 5>(taylor_at<ACT, 5>(z), p, e, ab, Db, Eb, zb, pb, eb);
+    constexpr int KG = MicroOrder<ACT, MICRO>::G;
+    taylor_bwd<D, KG>(taylor_at<ACT, KG>(z), p, e, ab, Db, Eb, zb, pb, eb);
   } else if (__all(tiny_args<ACT, D>(p, e))) {
     taylor_bwd<D>(taylor_at<ACT>(z), p, e, ab, Db, Eb, zb, pb, eb);
   } else {
@@ -649,10 +663,10 @@ __device__ __forceinline__ void act_fb(float z, const float* p, const float* e, 
                                        const float* Db, const float* Eb, float& a, float* Dv,
                                        float* Ev, float& zb, float* pb, float* eb) {
   if (MICRO > 0 && __all(micro_args<D, MICRO>(p, e))) {
-    const Taylor T = taylor_at<ACT, 5>(z);
+    const Taylor T = taylor_at<ACT, MicroOrder<ACT, MICRO>::G>(z);
     a = T.a;
-    taylor_fwd<D, 4>(T, p, e, Dv, Ev);
-    taylor_bwd<D, 5>(T, p, e, ab, Db, Eb, zb, pb, eb);
+    taylor_fwd<D, MicroOrder<ACT, MICRO>::F>(T, p, e, Dv, Ev);
+    taylor_bwd<D, MicroOrder<ACT, MICRO>::G>(T, p, e, ab, Db, Eb, zb, pb, eb);
   } else if (__all(tiny_args<ACT, D>(p, e))) {
     const Taylor T = taylor_at<ACT>(z);
     a = T.a;
