@@ -52,6 +52,8 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
   T* dZout = (T*)dZout_;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r16 = lane & 15, g = lane >> 4;
   const int n = w * 16 + r16;
+  // byte offset of this lane's weight row segment in a W x W matrix
+  const uint32_t woff = (uint32_t)((n * W + g * KC) * (int)sizeof(T));
   const int G = gridDim.x;
   const int ntiles = meta->tiles[0] + meta->tiles[1];
   const float hh = h * h;
@@ -95,7 +97,19 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
         adjs[tid / 8][tid % 8] = slot < slot_end ? adj[slot0 * 8 + tid] : 0.f;
       }
       __syncthreads();
-      auto tofs = [&](int s, int nn) -> int64_t { return (((int64_t)t * S + s) * W + nn) * kTile + 4 * g; };
+      // Operand rows of this tile: a wave-uniform base (the tile's block)
+      // and a 32-bit per-lane offset, so the stores address memory as a
+      // scalar base plus a vector offset instead of holding a 64-bit address
+      // per lane and layer in registers
+      // (the empty asm statements keep the compiler from folding the offsets
+      // into per-lane 64-bit addresses hoisted out of the tile loop)
+      uint32_t roff = (uint32_t)((n * kTile + 4 * g) * (int)sizeof(T));
+      uint32_t wo = woff;
+      asm volatile("" : "+v"(roff), "+v"(wo));
+      auto rowp = [&](T* layer_base, int s) -> T* {
+        T* tb = layer_base + (int64_t)t * S * W * kTile;
+        return (T*)((char*)tb + (roff + (uint32_t)(s * W * kTile * (int)sizeof(T))));
+      };
 
       // ---- layer 1
       float z1[4];
@@ -116,9 +130,9 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
         for (int s = 0; s < S; ++s) {
           for (int j = 0; j < 4; ++j) bufR[0][s][4 * g + j][n] = from_f<T>(vals[s][j]);
           if constexpr (PREC == 0)
-            *(float4*)(Aout + tofs(s, n)) = make_float4(vals[s][0], vals[s][1], vals[s][2], vals[s][3]);
+            *(float4*)rowp(Aout, s) = make_float4(vals[s][0], vals[s][1], vals[s][2], vals[s][3]);
           else
-            *(bf4*)(Aout + tofs(s, n)) = bf4{(__bf16)vals[s][0], (__bf16)vals[s][1], (__bf16)vals[s][2], (__bf16)vals[s][3]};
+            *(bf4*)rowp(Aout, s) = bf4{(__bf16)vals[s][0], (__bf16)vals[s][1], (__bf16)vals[s][2], (__bf16)vals[s][3]};
         }
       }
       __syncthreads();
@@ -135,7 +149,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
         for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
         mfma_phase_begin();
         if constexpr (PREC == 0) {
-          const float4* wp = (const float4*)((const float*)np.Wl[l - 2] + (int64_t)n * W + g * KC);
+          const float4* wp = (const float4*)((const char*)np.Wl[l - 2] + wo);
           for (int q = 0; q < KC / 4; ++q) {
             float4 b4 = wp[q];
             for (int s = 0; s < S; ++s) {
@@ -147,7 +161,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
             }
           }
         } else {
-          const bf8* wp = (const bf8*)((const T*)np.Wl[l - 2] + (int64_t)n * W + g * KC);
+          const bf8* wp = (const bf8*)((const char*)np.Wl[l - 2] + wo);
           for (int q = 0; q < KC / 8; ++q) {
             bf8 bk = wp[q];
             for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[cur][s][r16][g * KC + 8 * q]), bk, acc[s]);
@@ -172,7 +186,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
               *(float4*)(&Zs[s][g][n][0]) = make_float4(Z[0][s][0], Z[0][s][1], Z[0][s][2], Z[0][s][3]);
           for (int s = 0; s < S; ++s) {
             for (int j = 0; j < 4; ++j) bufR[cur ^ 1][s][4 * g + j][n] = from_f<T>(vals[s][j]);
-            T* dst = Aout + (int64_t)(l - 1) * lstride + tofs(s, n);
+            T* dst = rowp(Aout + (int64_t)(l - 1) * lstride, s);
             if constexpr (PREC == 0)
               *(float4*)dst = make_float4(vals[s][0], vals[s][1], vals[s][2], vals[s][3]);
             else
@@ -265,7 +279,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
         for (int j = 0; j < 4; ++j) accb[l - 1] += dz[0][j];
         for (int s = 0; s < S; ++s) {
           for (int j = 0; j < 4; ++j) bufR[bb][s][4 * g + j][n] = from_f<T>(dz[s][j]);
-          T* dst = dZout + (int64_t)(l - 2) * lstride + tofs(s, n);
+          T* dst = rowp(dZout + (int64_t)(l - 2) * lstride, s);
           if constexpr (PREC == 0)
             *(float4*)dst = make_float4(dz[s][0], dz[s][1], dz[s][2], dz[s][3]);
           else
@@ -276,7 +290,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
         for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
         mfma_phase_begin();
         if constexpr (PREC == 0) {
-          const float4* wp = (const float4*)((const float*)np.WlT[l - 2] + (int64_t)n * W + g * KC);
+          const float4* wp = (const float4*)((const char*)np.WlT[l - 2] + wo);
           for (int q = 0; q < KC / 4; ++q) {
             float4 b4 = wp[q];
             for (int s = 0; s < S; ++s) {
@@ -288,7 +302,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
             }
           }
         } else {
-          const bf8* wp = (const bf8*)((const T*)np.WlT[l - 2] + (int64_t)n * W + g * KC);
+          const bf8* wp = (const bf8*)((const char*)np.WlT[l - 2] + wo);
           for (int q = 0; q < KC / 8; ++q) {
             bf8 bk = wp[q];
             for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[bb][s][r16][g * KC + 8 * q]), bk, acc[s]);
