@@ -68,16 +68,20 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
   // this lane's B operand of one layer: row n of W_l (forward) or W_l^T
   // (backward), K chunk g; loaded one phase ahead of its MFMAs
   struct WRow { float f[PREC == 0 ? KC : 1]; bf8 b[PREC == 1 ? KC / 8 : 1]; };
-  auto load_w = [&](const void* m) {
+  // wo: byte offset of the row segment, re-declared opaque on every tile so
+  // the loads address memory as a scalar base plus a 32-bit lane offset
+  // rather than through per-lane 64-bit addresses hoisted per matrix
+  const uint32_t woff = (uint32_t)((n * W + g * KC) * (int)sizeof(T));
+  auto load_w = [&](const void* m, uint32_t wo) {
     WRow r;
     if constexpr (PREC == 0) {
-      const float4* wp = (const float4*)((const float*)m + (int64_t)n * W + g * KC);
+      const float4* wp = (const float4*)((const char*)m + wo);
       for (int q = 0; q < KC / 4; ++q) {
         float4 v4 = wp[q];
         r.f[4 * q] = v4.x; r.f[4 * q + 1] = v4.y; r.f[4 * q + 2] = v4.z; r.f[4 * q + 3] = v4.w;
       }
     } else {
-      const bf8* wp = (const bf8*)((const T*)m + (int64_t)n * W + g * KC);
+      const bf8* wp = (const bf8*)((const char*)m + wo);
       for (int q = 0; q < KC / 8; ++q) r.b[q] = wp[q];
     }
     return r;
@@ -142,6 +146,8 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
       if (!inl && tid < kTile * 8) adjs[tid / 8][tid % 8] = na;
       const int scur = ns;   // point index of this lane's centre (inline tiles)
       fetch(t + G);
+      uint32_t wo = woff;
+      asm volatile("" : "+v"(wo));
       __syncthreads();
 
       // ---------------- forward, layer 1 (VALU, accumulator mapping)
@@ -159,7 +165,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
           bufR[0][1 + D + a][c][n] = from_f<T>(Ev[a]);
         }
       }
-      WRow wn = load_w(np.Wl[0]);
+      WRow wn = load_w(np.Wl[0], wo);
       __syncthreads();
 
       // ---------------- forward, hidden layers on MFMA
@@ -255,7 +261,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
           }
         }
         // next phase's weights: the following layer, or the first backward layer
-        wn = load_w(l < L ? np.Wl[l - 1] : np.WlT[L - 2]);
+        wn = load_w(l < L ? np.Wl[l - 1] : np.WlT[L - 2], wo);
         __syncthreads();
         if (kZlds && l == 2)
           for (int s = 0; s < S; ++s)
@@ -320,7 +326,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
         f4 acc[S];
         for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
         const WRow wcur = wn;
-        if (l > 2) wn = load_w(np.WlT[l - 3]);   // next backward layer's weights
+        if (l > 2) wn = load_w(np.WlT[l - 3], wo);   // next backward layer's weights
         mfma_phase_begin();
         if constexpr (PREC == 0) {
           for (int s = 0; s < S; ++s) {
