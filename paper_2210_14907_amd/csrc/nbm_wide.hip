@@ -432,10 +432,21 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
         const int t = tile_of(k) < t_hi ? tile_of(k) : t_hi - 1;
         return (const u4*)(A + (int64_t)t * TA);
       };
+      // this lane's dZ rows of a tile (out-blocks w + 4i, every stream), also
+      // one tile ahead; the offset within a tile block is a 32-bit lane value
+      bf4 dzr[OBW][S];
+      auto load_dz = [&](int k) {
+        const int t = tile_of(k) < t_hi ? tile_of(k) : t_hi - 1;
+        const char* tb = (const char*)(dZ + (int64_t)t * TA);
+        for (int i = 0; i < OBW; ++i)
+          for (int s = 0; s < S; ++s)
+            dzr[i][s] = *(const bf4*)(tb + (uint32_t)((((s * W + (w + 4 * i) * 16 + r16) * kTile) + 4 * g) * 2));
+      };
       if (niter > 0) {
         const u4* s4 = src_of(0);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) pre[q] = s4[q * 256 + hl];
+        load_dz(0);
         u4* d4 = (u4*)(stage + (half * 2) * TA);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) d4[q * 256 + hl] = pre[q];
@@ -444,20 +455,20 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
       const bf4 zero4 = bf4{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
       for (int k = 0; k < niter; ++k) {
         const int t = tile_of(k);
+        bf8 dzv[OBW][(S + 1) / 2];
+        for (int i = 0; i < OBW; ++i)
+          for (int s = 0; s < S; s += 2) {
+            const bf4 v0 = dzr[i][s];
+            const bf4 v1 = s + 1 < S ? dzr[i][s + 1] : zero4;
+            for (int j = 0; j < 4; ++j) { dzv[i][s / 2][j] = v0[j]; dzv[i][s / 2][4 + j] = v1[j]; }
+          }
         {
           const u4* s4 = src_of(k + 1);
 #pragma unroll
           for (int q = 0; q < NQ; ++q) pre[q] = s4[q * 256 + hl];
+          load_dz(k + 1);
         }
         if (t < t_hi) {
-          auto tofs = [&](int s, int nn) -> int64_t { return (((int64_t)t * S + s) * W + nn) * kTile + 4 * g; };
-          bf8 dzv[OBW][(S + 1) / 2];
-          for (int i = 0; i < OBW; ++i)
-            for (int s = 0; s < S; s += 2) {
-              bf4 v0 = *(const bf4*)(dZ + tofs(s, (w + 4 * i) * 16 + r16));
-              bf4 v1 = s + 1 < S ? *(const bf4*)(dZ + tofs(s + 1, (w + 4 * i) * 16 + r16)) : zero4;
-              for (int j = 0; j < 4; ++j) { dzv[i][s / 2][j] = v0[j]; dzv[i][s / 2][4 + j] = v1[j]; }
-            }
           const T* As = stage + (half * 2 + (k & 1)) * TA;
           for (int ib = 0; ib < NOB; ++ib)
             for (int s = 0; s < S; s += 2) {
