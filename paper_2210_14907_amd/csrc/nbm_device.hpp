@@ -553,6 +553,36 @@ __device__ __forceinline__ void taylor_bwd(const Taylor& T, const float* p, cons
   }
 }
 
+// Backward of the micro tier with BF16 operands, factored through
+// A = a'(z+p) - c_1 = d_2 p + g(p) and B = a'(z-m) - c_1 = -d_2 m + g(-m):
+//   dD/dz = A, dD/dp = c_1 + A, dE/dz = A + B, dE/dp = A - B, dE/de = c_1 + B,
+// so with U = A (D^ + E^) and V = E^ B the adjoints are
+//   z^ += U + V,  p^ = c_1 D^ + U - V,  e^ = c_1 E^ + V.
+// A + B ~ d_2 e + d_3 (p^2 + m^2) is formed by cancellation here: its FP32
+// rounding is at most 2^-24 |A| ~ 2^-24 |p|, relative 2^-24 |p| / |A + B|
+// (2^-16 for e ~ h p at h = 1/256), far below the 2^-9 rounding of the BF16
+// operands these adjoints feed.  The FP32 paths keep taylor_bwd's
+// cancellation-free forms.
+template <int D, int KG>
+__device__ __forceinline__ void taylor_bwd_bf16(const Taylor& T, const float* p, const float* e, float ab,
+                                                const float* Db, const float* Eb, float& zb, float* pb,
+                                                float* eb) {
+  float d[8];
+#pragma unroll
+  for (int k = 2; k <= KG; ++k) d[k] = (float)k * T.c[k];
+  zb = ab * T.c[1];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const float m = p[i] - e[i];
+    const float A = fmaf(d[2], p[i], taylor_g<KG>(d, p[i]));
+    const float B = fmaf(-d[2], m, taylor_g<KG>(d, -m));
+    const float U = A * (Db[i] + Eb[i]), V = Eb[i] * B;
+    zb += U + V;
+    pb[i] = fmaf(T.c[1], Db[i], U - V);
+    eb[i] = fmaf(T.c[1], Eb[i], V);
+  }
+}
+
 // Longer series and library paths kept out of line (each lane picks its
 // tier there): taken only when some lane of the wavefront has a difference
 // argument beyond the tiny tier, so the common path stays register-lean.
@@ -621,7 +651,8 @@ __device__ __forceinline__ void act_bwd(float z, const float* p, const float* e,
                                         float* eb) {
   if (MICRO > 0 && __all(micro_args<D, MICRO>(p, e))) {
     constexpr int KG = MicroOrder<ACT, MICRO>::G;
-    taylor_bwd<D, KG>(taylor_at<ACT, KG>(z), p, e, ab, Db, Eb, zb, pb, eb);
+    if constexpr (MICRO == 2) taylor_bwd_bf16<D, KG>(taylor_at<ACT, KG>(z), p, e, ab, Db, Eb, zb, pb, eb);
+    else taylor_bwd<D, KG>(taylor_at<ACT, KG>(z), p, e, ab, Db, Eb, zb, pb, eb);
   } else if (__all(tiny_args<ACT, D>(p, e))) {
     taylor_bwd<D>(taylor_at<ACT>(z), p, e, ab, Db, Eb, zb, pb, eb);
   } else {
@@ -666,7 +697,8 @@ __device__ __forceinline__ void act_fb(float z, const float* p, const float* e, 
     const Taylor T = taylor_at<ACT, MicroOrder<ACT, MICRO>::G>(z);
     a = T.a;
     taylor_fwd<D, MicroOrder<ACT, MICRO>::F>(T, p, e, Dv, Ev);
-    taylor_bwd<D, MicroOrder<ACT, MICRO>::G>(T, p, e, ab, Db, Eb, zb, pb, eb);
+    if constexpr (MICRO == 2) taylor_bwd_bf16<D, MicroOrder<ACT, MICRO>::G>(T, p, e, ab, Db, Eb, zb, pb, eb);
+    else taylor_bwd<D, MicroOrder<ACT, MICRO>::G>(T, p, e, ab, Db, Eb, zb, pb, eb);
   } else if (__all(tiny_args<ACT, D>(p, e))) {
     const Taylor T = taylor_at<ACT>(z);
     a = T.a;
