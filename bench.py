@@ -31,10 +31,33 @@ HBM_PEAK = 8.0e12
 
 # counter summaries (rocprofv3 FETCH_SIZE / WRITE_SIZE) per dominant kernel,
 # valid while the sources they were taken from are unchanged
+_WIDE_SRC = ["nbm_wide.hip", "nbm_device.hpp", "nbm_internal.hpp", "nbm_launch.hpp"]
+# committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries: (kernel, workload) -> (file, sources)
 COUNTERS = {
-    "k_fused": ("c2_k_fused_counters.md", ["nbm_fused.hip", "nbm_device.hpp", "nbm_internal.hpp", "nbm_launch.hpp"]),
-    "k_wide_fb": ("c3_k_wide_fb_counters.md", ["nbm_wide.hip", "nbm_device.hpp", "nbm_internal.hpp", "nbm_launch.hpp"]),
+    ("k_fused", "c2_sphere3d_tanh64x3_fp32"): ("c2_k_fused_counters.md", ["nbm_fused.hip", "nbm_device.hpp", "nbm_internal.hpp", "nbm_launch.hpp"]),
+    ("k_wide_fb", "c3_sphere3d_sin128x4_bf16"): ("c3_k_wide_fb_counters.md", _WIDE_SRC),
+    ("k_wide_fb", "c4_star3d_sin128x4_bf16"): ("c4_k_wide_fb_counters.md", _WIDE_SRC),
 }
+
+
+def _extensions():
+    """The widened rows of the hot path, timed beside the headline: implicit
+    refinement (Sec. 3), the Helmholtz term k u (Sec. 2), the interface as a
+    level set on a coarse mesh (Sec. 3) and the paper's variable-coefficient
+    workload (Sec. 4.1)."""
+    import nbm_inputs as I
+    c3l = I.C3.replace(name="c3_sphere3d_sin128x4_bf16_levels3", levels=3)
+    c3k = I.C3.replace(name="c3_sphere3d_sin128x4_bf16_helmholtz", k_minus=2.0, k_plus=5.0)
+    c4m = I.C4.replace(name="c4_star3d_sin128x4_bf16_mesh64", interface=I.IFACE_GRID,
+                       phi_shape=I.IFACE_STAR, phi_n=64)
+    return ((("c3_levels3_bf16", c3l), ("c3_helmholtz_bf16", c3k), ("c4_mesh64_bf16", c4m),
+             ("paper_varmu_fp32", I.PAPER)),
+            {"c3_levels3_bf16": "C3 with three levels of implicit refinement: every point's residual "
+                                "at cells of side h, h/2, h/4 and h/8, losses and gradients summed",
+             "c3_helmholtz_bf16": "C3 with the term k u, k- = 2, k+ = 5",
+             "c4_mesh64_bf16": "C4 with the star given as a level set on a 64^3 mesh (multilinear)",
+             "paper_varmu_fp32": "the paper's sphere with mu- = y^2 ln(x+2) + 4, mu+ = e^-z, two 5x10 sine "
+                                 "nets zero-padded to 16, h = 1/32, 32,768 points"})
 
 
 def log(msg):
@@ -49,13 +72,13 @@ def kernel_source_hash(files):
     return hsh.hexdigest()
 
 
-def recorded_traffic(kernel, prec_tag):
-    """HBM bytes per launch of a kernel from its committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources changed
-    since those counters were taken (or no summary exists)."""
-    if kernel not in COUNTERS:
+def recorded_traffic(kernel, workload, prec_tag):
+    """HBM bytes per launch of a kernel on a workload from its committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources
+    changed since those counters were taken (or no summary exists)."""
+    if (kernel, workload) not in COUNTERS:
         return None
-    summary, files = COUNTERS[kernel]
+    summary, files = COUNTERS[(kernel, workload)]
     try:
         with open(os.path.join(ROOT, "profiles", summary)) as fh:
             text = fh.read()
@@ -199,7 +222,7 @@ def roofline(wl, meas):
     achieved = per_launch / (avg * 1e-3)
     out = {"bound": "mfma", "kernel": name, "achieved": achieved / 1e12, "peak": PEAK[dtype] / 1e12,
            "unit": "TFLOP/s", "frac": achieved / PEAK[dtype],
-           "traffic": recorded_traffic(kern, dtype) if kern else None,
+           "traffic": recorded_traffic(kern, wl.name, dtype) if kern else None,
            "flop_per_launch": per_launch, "flop_per_point": flop, "points_per_launch": pts,
            "avg_launch_ms": avg, "launches_timed": b_n, "steps_timed": nt}
     w_ms, w_n = tm.get("weight_grad", (0.0, 0))
@@ -505,6 +528,8 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    global EXTENSIONS, EXTENSION_NOTES
+    EXTENSIONS, EXTENSION_NOTES = _extensions()
     twin_prec = I.PREC_FP32 if wl.prec == I.PREC_BF16 else I.PREC_BF16
     twin_tag = "fp32" if twin_prec == I.PREC_FP32 else "bf16"
     wl_twin = wl.replace(prec=twin_prec, name=wl.name.rsplit("_", 1)[0] + "_" + twin_tag)
@@ -552,7 +577,7 @@ def main():
         line["speedup_bf16_over_fp32"] = round(fp["ms_per_step"] / bf["ms_per_step"], 3)
     if not args.no_extra:
         extra = {}
-        for tag, w in (("c2_fp32", I.C2), ("c2_bf16", I.C2.replace(prec=I.PREC_BF16)), ("c4_bf16", I.C4)):
+        for tag, w in (("c2_fp32", I.C2), ("c2_bf16", I.C2.replace(prec=I.PREC_BF16)), ("c4_bf16", I.C4)) + EXTENSIONS:
             if w.name == wl.name:
                 continue
             log(f"timing {tag}")
@@ -560,6 +585,12 @@ def main():
             mm = measure(r, max(10, args.steps // 2), 3)
             extra[tag] = summary(w, mm)
             extra[tag]["roofline"] = roofline(w, mm)
+            if w.levels:
+                extra[tag]["levels"] = w.levels
+                extra[tag]["point_level_pairs_per_s"] = round(extra[tag]["pts_per_s"] * (w.levels + 1), 1)
+            if tag in EXTENSION_NOTES:
+                extra[tag]["workload"] = w.name
+                extra[tag]["what"] = EXTENSION_NOTES[tag]
             del r
             torch.cuda.empty_cache()
         line["other_workloads"] = extra
