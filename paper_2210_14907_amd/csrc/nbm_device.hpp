@@ -625,13 +625,53 @@ __device__ __forceinline__ bool micro_args(const float* p, const float* e) {
   return ok;
 }
 
+// The micro tier's forms without their check, for callers that have
+// established micro_args for every lane (and keep that decision for the
+// backward of the same arguments).
+template <int ACT, int D, int MICRO>
+__device__ __forceinline__ void act_fwd_micro(float z, const float* p, const float* e, float& a,
+                                              float* Dv, float* Ev) {
+  const Taylor T = taylor_at<ACT, MicroOrder<ACT, MICRO>::G>(z);
+  a = T.a;
+  taylor_fwd<D, MicroOrder<ACT, MICRO>::F>(T, p, e, Dv, Ev);
+}
+template <int ACT, int D, int MICRO>
+__device__ __forceinline__ void act_bwd_micro(float z, const float* p, const float* e, float ab,
+                                              const float* Db, const float* Eb, float& zb, float* pb,
+                                              float* eb) {
+  constexpr int KG = MicroOrder<ACT, MICRO>::G;
+  if constexpr (MICRO == 2) taylor_bwd_bf16<D, KG>(taylor_at<ACT, KG>(z), p, e, ab, Db, Eb, zb, pb, eb);
+  else taylor_bwd<D, KG>(taylor_at<ACT, KG>(z), p, e, ab, Db, Eb, zb, pb, eb);
+}
+template <int ACT, int D, int MICRO>
+__device__ __forceinline__ void act_fb_micro(float z, const float* p, const float* e, float ab,
+                                             const float* Db, const float* Eb, float& a, float* Dv,
+                                             float* Ev, float& zb, float* pb, float* eb) {
+  const Taylor T = taylor_at<ACT, MicroOrder<ACT, MICRO>::G>(z);
+  a = T.a;
+  taylor_fwd<D, MicroOrder<ACT, MICRO>::F>(T, p, e, Dv, Ev);
+  if constexpr (MICRO == 2) taylor_bwd_bf16<D, MicroOrder<ACT, MICRO>::G>(T, p, e, ab, Db, Eb, zb, pb, eb);
+  else taylor_bwd<D, MicroOrder<ACT, MICRO>::G>(T, p, e, ab, Db, Eb, zb, pb, eb);
+}
+
+// the largest micro argument of one element, max_i max(|p_i|, |p_i - e_i|):
+// micro_args holds iff it is <= the bound (a running maximum checks many
+// elements with one comparison)
+template <int D>
+__device__ __forceinline__ float micro_extent(const float* p, const float* e) {
+  float r = 0.f;
+#pragma unroll
+  for (int i = 0; i < D; ++i) r = fmaxf(r, fmaxf(fabsf(p[i]), fabsf(p[i] - e[i])));
+  return r;
+}
+template <int MICRO>
+constexpr float micro_bound() { return MICRO == 2 ? kMicroXBf16 : kMicroX; }
+
 template <int ACT, int D, int MICRO = 0>
 __device__ __forceinline__ void act_fwd(float z, const float* p, const float* e, float& a,
                                         float* Dv, float* Ev) {
   if (MICRO > 0 && __all(micro_args<D, MICRO>(p, e))) {
-    const Taylor T = taylor_at<ACT, MicroOrder<ACT, MICRO>::G>(z);
-    a = T.a;
-    taylor_fwd<D, MicroOrder<ACT, MICRO>::F>(T, p, e, Dv, Ev);
+    act_fwd_micro<ACT, D, MICRO>(z, p, e, a, Dv, Ev);
   } else if (__all(tiny_args<ACT, D>(p, e))) {
     const Taylor T = taylor_at<ACT>(z);
     a = T.a;
@@ -650,9 +690,7 @@ __device__ __forceinline__ void act_bwd(float z, const float* p, const float* e,
                                         const float* Db, const float* Eb, float& zb, float* pb,
                                         float* eb) {
   if (MICRO > 0 && __all(micro_args<D, MICRO>(p, e))) {
-    constexpr int KG = MicroOrder<ACT, MICRO>::G;
-    if constexpr (MICRO == 2) taylor_bwd_bf16<D, KG>(taylor_at<ACT, KG>(z), p, e, ab, Db, Eb, zb, pb, eb);
-    else taylor_bwd<D, KG>(taylor_at<ACT, KG>(z), p, e, ab, Db, Eb, zb, pb, eb);
+    act_bwd_micro<ACT, D, MICRO>(z, p, e, ab, Db, Eb, zb, pb, eb);
   } else if (__all(tiny_args<ACT, D>(p, e))) {
     taylor_bwd<D>(taylor_at<ACT>(z), p, e, ab, Db, Eb, zb, pb, eb);
   } else {
@@ -694,11 +732,7 @@ __device__ __forceinline__ void act_fb(float z, const float* p, const float* e, 
                                        const float* Db, const float* Eb, float& a, float* Dv,
                                        float* Ev, float& zb, float* pb, float* eb) {
   if (MICRO > 0 && __all(micro_args<D, MICRO>(p, e))) {
-    const Taylor T = taylor_at<ACT, MicroOrder<ACT, MICRO>::G>(z);
-    a = T.a;
-    taylor_fwd<D, MicroOrder<ACT, MICRO>::F>(T, p, e, Dv, Ev);
-    if constexpr (MICRO == 2) taylor_bwd_bf16<D, MicroOrder<ACT, MICRO>::G>(T, p, e, ab, Db, Eb, zb, pb, eb);
-    else taylor_bwd<D, MicroOrder<ACT, MICRO>::G>(T, p, e, ab, Db, Eb, zb, pb, eb);
+    act_fb_micro<ACT, D, MICRO>(z, p, e, ab, Db, Eb, a, Dv, Ev, zb, pb, eb);
   } else if (__all(tiny_args<ACT, D>(p, e))) {
     const Taylor T = taylor_at<ACT>(z);
     a = T.a;

@@ -59,6 +59,7 @@ struct Meta {
   int32_t nB;          // cut cells kept
   int32_t overflow;    // 1 if the cut capacity was exceeded
   int32_t n, nb;       // batch sizes
+  int32_t slow;        // 1 if the 128-wide fast pass met an argument beyond its tier
 };
 
 // Per-net parameter pointers (FP32 master copy) and operand shadows.

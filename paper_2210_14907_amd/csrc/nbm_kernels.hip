@@ -244,6 +244,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const int* bc_in, int nbl
       for (int k = 0; k < 4; ++k) { m.cnt[a][k] = 0; m.base[a][k] = 0; }
     m.n = n;
     m.nb = nb;
+    m.slow = 0;
     if (eval_mode) {
       m.ncls[0] = totals[0]; m.ncls[1] = totals[1]; m.ncls[2] = 0;
       m.nbside[0] = m.nbside[1] = 0;
@@ -559,7 +560,7 @@ __global__ void k_counts(const Meta* meta, int* counts) {
   if (threadIdx.x == 0) {
     counts[0] = meta->ncls[0]; counts[1] = meta->ncls[1]; counts[2] = meta->ncls[2];
     counts[3] = meta->nbside[0]; counts[4] = meta->nbside[1]; counts[5] = meta->overflow;
-    counts[6] = 0; counts[7] = 0;
+    counts[6] = meta->slow; counts[7] = 0;
   }
 }
 

@@ -10,6 +10,13 @@
 // the chip in the accumulator ("tile") layout [tile][stream][neuron][16];
 // the small gradients (biases, W_1, w_out) are accumulated per work-group.
 //
+// The forward/backward pass runs first in a fast form that takes the micro
+// tier of the activation streams for every element without branching
+// (checking the tier's bound per lane as it goes); if any argument lies
+// beyond that bound it raises meta->slow, and the general form, launched
+// right after and otherwise exiting at once, recomputes the whole pass with
+// per-element tiers, overwriting every output of the fast one.
+//
 // Pass 2 (k_wide_dw): dW_l = sum over (tile, stream, centre) of dZ_l^T A_{l-1}
 // read straight from the tile layout as MFMA operands (the K index runs over
 // stream pairs x 4 centres per lane group), split over persistent work-groups
@@ -22,14 +29,19 @@
 
 namespace nbm {
 
-template <int D, int W, int L, int ACT, int PREC>
+template <int D, int W, int L, int ACT, int PREC, bool FAST>
 __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float4* centres,
                                                    const int* src, Nets nets, Problem P, float h,
                                                    const float* adj, float* resid, void* Aout_,
                                                    void* dZout_, int64_t lstride, float* partial,
                                                    int64_t Ptot, NetLayout lay, int64_t net_off1,
-                                                   double* lossp, double scale, const float* fslot) {
+                                                   double* lossp, double scale, const float* fslot,
+                                                   int* slow) {
   typedef typename Op<PREC>::T T;
+  // the general form runs only when the fast form flagged an argument
+  if constexpr (!FAST)
+    if (*slow == 0) return;
+  float amax = 0.f;   // fast form: largest micro argument this lane met
   constexpr int S = 2 * D + 1;
   constexpr int LD = W + (PREC == 0 ? 4 : 8);
   constexpr int NW = W / 16;     // wavefronts; wave w owns neurons 16w .. 16w+15
@@ -175,7 +187,12 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
             float z = acc[0][j] + bias;
             float pp[3], ee[3], av, Dv[3], Ev[3];
             for (int a = 0; a < D; ++a) { pp[a] = acc[1 + a][j]; ee[a] = acc[1 + D + a][j]; }
-            act_fwd<ACT, D, kMicroW>(z, pp, ee, av, Dv, Ev);
+            if constexpr (FAST) {
+              amax = fmaxf(amax, micro_extent<D>(pp, ee));
+              act_fwd_micro<ACT, D, kMicroW>(z, pp, ee, av, Dv, Ev);
+            } else {
+              act_fwd<ACT, D, kMicroW>(z, pp, ee, av, Dv, Ev);
+            }
             Z[l - 2][0][j] = z;
             for (int s = 1; s < S; ++s) Z[l - 2][s][j] = acc[s][j];
             vals[0][j] = av;
@@ -208,7 +225,12 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
               ab = won * adjs[c][0];
               for (int a = 0; a < D; ++a) { Db[a] = won * adjs[c][1 + a]; Eb[a] = won * adjs[c][1 + D + a]; }
             }
-            act_fb<ACT, D, kMicroW>(z, pp, ee, ab, Db, Eb, av, Dv, Ev, zb, pb, eb);
+            if constexpr (FAST) {
+              amax = fmaxf(amax, micro_extent<D>(pp, ee));
+              act_fb_micro<ACT, D, kMicroW>(z, pp, ee, ab, Db, Eb, av, Dv, Ev, zb, pb, eb);
+            } else {
+              act_fb<ACT, D, kMicroW>(z, pp, ee, ab, Db, Eb, av, Dv, Ev, zb, pb, eb);
+            }
             dz[0][j] = zb;
             for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
             // output layer, u = sum_n w_out[n] a_L[n] (+ b_out) per stream: the
@@ -319,7 +341,9 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           for (int a = 0; a < D; ++a) { Db[a] = acc[1 + a][j]; Eb[a] = acc[1 + D + a][j]; }
           if (l > 2) {
             for (int a = 0; a < D; ++a) { pp[a] = Z[l - 3][1 + a][j]; ee[a] = Z[l - 3][1 + D + a][j]; }
-            act_bwd<ACT, D, kMicroW>(Z[l - 3][0][j], pp, ee, acc[0][j], Db, Eb, zb, pb, eb);
+            // (the same arguments as in the forward: the fast form checked them there)
+            if constexpr (FAST) act_bwd_micro<ACT, D, kMicroW>(Z[l - 3][0][j], pp, ee, acc[0][j], Db, Eb, zb, pb, eb);
+            else act_bwd<ACT, D, kMicroW>(Z[l - 3][0][j], pp, ee, acc[0][j], Db, Eb, zb, pb, eb);
             dz[0][j] = zb;
             for (int a = 0; a < D; ++a) { dz[1 + a][j] = pb[a]; dz[1 + D + a][j] = eb[a]; }
           } else {
@@ -361,6 +385,9 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
     for (int c = 0; c < kTile; ++c) s += lsum[c];
     lossp[blockIdx.x] = s;
   }
+  // (written so that a NaN argument also sends the pass to the general form)
+  if constexpr (FAST)
+    if (!(amax <= micro_bound<kMicroW>())) *slow = 1;
 }
 
 // dW_l partials.  A work-group of 8 wavefronts: waves w and w+4 (one SIMD)
@@ -510,10 +537,17 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
 
 template <int D, int W, int L, int ACT, int PREC>
 hipError_t wide_impl(const WideCall& c) {
-  hipLaunchKernelGGL((k_wide_fb<D, W, L, ACT, PREC>), dim3(c.grid), dim3(W * 4), 0, c.stream, c.meta,
-                     c.centres, c.src, *c.nets, c.P, c.h, c.adj, c.resid, c.A, c.dZ, c.lstride,
-                     c.partial, c.Ptot, *c.lay, c.off1, c.lossp, c.scale, c.fslot);
+  int* slow = const_cast<int*>(&c.meta->slow);   // device address inside the batch record
+  hipLaunchKernelGGL((k_wide_fb<D, W, L, ACT, PREC, true>), dim3(c.grid), dim3(W * 4), 0, c.stream,
+                     c.meta, c.centres, c.src, *c.nets, c.P, c.h, c.adj, c.resid, c.A, c.dZ, c.lstride,
+                     c.partial, c.Ptot, *c.lay, c.off1, c.lossp, c.scale, c.fslot, slow);
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL((k_wide_fb<D, W, L, ACT, PREC, false>), dim3(c.grid), dim3(W * 4), 0, c.stream,
+                       c.meta, c.centres, c.src, *c.nets, c.P, c.h, c.adj, c.resid, c.A, c.dZ, c.lstride,
+                       c.partial, c.Ptot, *c.lay, c.off1, c.lossp, c.scale, c.fslot, slow);
+    e = hipGetLastError();
+  }
   if (c.after_fb) c.after_fb(c.timer_ctx);
   if (e != hipSuccess) return e;
   for (int l = 2; l <= L; ++l) {
