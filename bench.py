@@ -398,6 +398,7 @@ def c4_end_to_end(steps, judge_n, grid_n=1024, tile_points=1 << 24, tau_factor=2
     t0 = time.time()
     loss_end = run.train_to(steps)
     train_s = time.time() - t0
+    fallback_last = int(run.nbm.batch_counts()[6].item())
     losses = run.losses[1:steps + 1].cpu().numpy()
     judge.join()
     if judge.error:
@@ -417,6 +418,7 @@ def c4_end_to_end(steps, judge_n, grid_n=1024, tile_points=1 << 24, tau_factor=2
            "ms_per_step_incl_host": round(1e3 * train_s / steps, 3),
            "loss_first_last": [float(losses[0]), float(loss_end)],
            "loss_min": float(np.min(losses)),
+           "fallback_last_step": fallback_last,
            "judge": {"n": judge_n, "seconds": round(t_judge, 1), "picard_iterations": gs.picard_iters,
                      "picard_converged": bool(gs.converged), "pcg_relres": float(gs.relres),
                      "max_abs_U": float(np.abs(U).max())},
@@ -604,6 +606,8 @@ def main():
         acc = {"judge_n": judge_n, "steps_trained": wl.steps}
         for tag, r in ((dtype if dtype == "bf16" else "fp32", main_run), (twin_tag, twin_run)):
             acc[f"final_loss_{tag}"] = r.train_to(wl.steps)
+            # 1 if the last step's 128-wide pass had to leave its fast form
+            acc[f"fallback_last_step_{tag}"] = int(r.nbm.batch_counts()[6].item())
             log(f"trained {r.wl.name} to step {r.step}")
         judge.join()
         if judge.error:

@@ -204,9 +204,10 @@ int nbm_grid_interp(nbm_ctx* ctx, void* stream, const double* U, int32_t judge_n
 /* Classes of the last batch seen by nbm_forward_residual / nbm_backward on
  * this workspace, written to counts[8] (device int32): interior A^-, A^+,
  * cut, boundary^-, boundary^+, overflow flag, fallback flag, 0.  The
- * fallback flag is 1 when the 128-wide forward/backward met an activation
- * argument beyond its fast (micro-series) form and recomputed the batch with
- * per-element series tiers (same results; the second pass costs time). */
+ * fallback flag is 1 when the 128-wide forward/backward with BF16 operands
+ * met an activation argument beyond its fast (micro-series) form and
+ * recomputed the batch with per-element series tiers (same results; the
+ * second pass costs time).  FP32 operands always take the per-element form. */
 int nbm_batch_counts(nbm_ctx* ctx, void* stream, int32_t* counts, void* ws, size_t ws_bytes);
 
 /* Measurement support.  With timing enabled, every later call records a

@@ -38,9 +38,10 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
                                                    double* lossp, double scale, const float* fslot,
                                                    int* slow) {
   typedef typename Op<PREC>::T T;
-  // the general form runs only when the fast form flagged an argument
+  // the general form runs only when the fast form flagged an argument (or
+  // unconditionally, with slow = null, where no fast form precedes it)
   if constexpr (!FAST)
-    if (*slow == 0) return;
+    if (slow != nullptr && *slow == 0) return;
   float amax = 0.f;   // fast form: largest micro argument this lane met
   constexpr int S = 2 * D + 1;
   constexpr int LD = W + (PREC == 0 ? 4 : 8);
@@ -537,11 +538,19 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
 
 template <int D, int W, int L, int ACT, int PREC>
 hipError_t wide_impl(const WideCall& c) {
-  int* slow = const_cast<int*>(&c.meta->slow);   // device address inside the batch record
-  hipLaunchKernelGGL((k_wide_fb<D, W, L, ACT, PREC, true>), dim3(c.grid), dim3(W * 4), 0, c.stream,
-                     c.meta, c.centres, c.src, *c.nets, c.P, c.h, c.adj, c.resid, c.A, c.dZ, c.lstride,
-                     c.partial, c.Ptot, *c.lay, c.off1, c.lossp, c.scale, c.fslot, slow);
-  hipError_t e = hipGetLastError();
+  // The fast form is used with BF16 operands, whose micro bound (1/32) the
+  // arguments of trained networks stay within; with FP32 operands the bound
+  // is 1/256, which trained weights leave, and a fast pass would then be
+  // repeated by the general one every step, so FP32 runs the general form
+  // alone.
+  int* slow = PREC == 1 ? const_cast<int*>(&c.meta->slow) : nullptr;   // inside the batch record
+  hipError_t e = hipSuccess;
+  if constexpr (PREC == 1) {
+    hipLaunchKernelGGL((k_wide_fb<D, W, L, ACT, PREC, true>), dim3(c.grid), dim3(W * 4), 0, c.stream,
+                       c.meta, c.centres, c.src, *c.nets, c.P, c.h, c.adj, c.resid, c.A, c.dZ, c.lstride,
+                       c.partial, c.Ptot, *c.lay, c.off1, c.lossp, c.scale, c.fslot, slow);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) {
     hipLaunchKernelGGL((k_wide_fb<D, W, L, ACT, PREC, false>), dim3(c.grid), dim3(W * 4), 0, c.stream,
                        c.meta, c.centres, c.src, *c.nets, c.P, c.h, c.adj, c.resid, c.A, c.dZ, c.lstride,
