@@ -142,10 +142,10 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
         }
         for (int s = 0; s < S; ++s) {
           for (int j = 0; j < 4; ++j) bufR[0][s][4 * g + j][n] = from_f<T>(vals[s][j]);
+          // first-layer operand rows: stored with FP32 operands; with BF16 the
+          // weight-gradient pass rebuilds them from the centres
           if constexpr (PREC == 0)
             *(float4*)rowp(Aout, s) = make_float4(vals[s][0], vals[s][1], vals[s][2], vals[s][3]);
-          else
-            *(bf4*)rowp(Aout, s) = bf4{(__bf16)vals[s][0], (__bf16)vals[s][1], (__bf16)vals[s][2], (__bf16)vals[s][3]};
         }
       }
       __syncthreads();
@@ -397,11 +397,17 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
 // halves' accumulators are added in a fixed order through LDS at the end.
 // BF16: each half stages the A block of its tile in LDS once (double-
 // buffered, the next tile's block in flight during the current MFMAs)
-// instead of every wave reading all of it from L2.
-template <int D, int W, int PREC>
+// instead of every wave reading all of it from L2.  For the first hidden
+// layer (A1) the block is not read at all: the first layer's activation
+// streams of the tile's centres are recomputed from the centres and W_1, b_1
+// (the same arithmetic as the forward pass, rounded to BF16 the same way),
+// which spares the forward pass their stores and this pass their reads.
+template <int D, int W, int PREC, int ACT, bool A1>
 __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A_, const void* dZ_,
                                                  float* partial, int64_t Ptot, int64_t woff,
-                                                 int64_t net_off1) {
+                                                 int64_t net_off1, const float4* centres, Nets nets,
+                                                 float h) {
+  static_assert(!A1 || PREC == 1, "the first layer's operand rows are rebuilt on the BF16 path");
   typedef typename Op<PREC>::T T;
   constexpr int S = 2 * D + 1;
   constexpr int NOB = W / 16;
@@ -455,7 +461,35 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
       auto tile_of = [&](int k) { return t_lo + (int)blockIdx.x + half * G + 2 * G * k; };
       // the next tile's A block travels through registers; a half past its
       // last tile re-reads the net's last tile (in bounds, never used)
-      u4 pre[NQ];
+      u4 pre[A1 ? 1 : NQ];
+      // A1: this thread rebuilds neuron an at centres ac0 .. ac0+7 of a tile
+      const int an = hl >> 1, ac0 = (hl & 1) * 8;
+      float aW1[3] = {0.f, 0.f, 0.f}, ab1 = 0.f;
+      L1Axes aax{};
+      if constexpr (A1) {
+        const NetPtrs& np = nets.net[net];
+        float p1[3] = {0.f, 0.f, 0.f};
+        for (int a = 0; a < D; ++a) { aW1[a] = np.W1[an * D + a]; p1[a] = h * aW1[a]; }
+        ab1 = np.b1[an];
+        aax = l1_axes<ACT, D>(p1);
+      }
+      const int64_t slot_end = (int64_t)meta->tile0[net] * kTile + meta->total[net];
+      auto build_A = [&](int t, T* dst) {
+        if (t >= t_hi) return;
+        const int64_t slot0 = (int64_t)t * kTile + ac0;
+        bf8 o[S];
+        for (int c = 0; c < 8; ++c) {
+          float4 cc = slot0 + c < slot_end ? centres[slot0 + c] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float xc[3] = {cc.x, cc.y, cc.z};
+          float z = ab1;
+          for (int a = 0; a < D; ++a) z += aW1[a] * xc[a];
+          float av, Dv[3], Ev[3];
+          act_fwd_l1<ACT, D>(z, aax, av, Dv, Ev);
+          o[0][c] = (__bf16)av;
+          for (int a = 0; a < D; ++a) { o[1 + a][c] = (__bf16)Dv[a]; o[1 + D + a][c] = (__bf16)Ev[a]; }
+        }
+        for (int s = 0; s < S; ++s) *(bf8*)(dst + (s * W + an) * kTile + ac0) = o[s];
+      };
       auto src_of = [&](int k) {
         const int t = tile_of(k) < t_hi ? tile_of(k) : t_hi - 1;
         return (const u4*)(A + (int64_t)t * TA);
@@ -471,13 +505,17 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
             dzr[i][s] = *(const bf4*)(tb + (uint32_t)((((s * W + (w + 4 * i) * 16 + r16) * kTile) + 4 * g) * 2));
       };
       if (niter > 0) {
-        const u4* s4 = src_of(0);
+        if constexpr (A1) {
+          build_A(tile_of(0), stage + (half * 2) * TA);
+        } else {
+          const u4* s4 = src_of(0);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) pre[q] = s4[q * 256 + hl];
+          for (int q = 0; q < NQ; ++q) pre[q] = s4[q * 256 + hl];
+          u4* d4 = (u4*)(stage + (half * 2) * TA);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) d4[q * 256 + hl] = pre[q];
+        }
         load_dz(0);
-        u4* d4 = (u4*)(stage + (half * 2) * TA);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) d4[q * 256 + hl] = pre[q];
       }
       __syncthreads();
       const bf4 zero4 = bf4{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
@@ -491,9 +529,11 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
             for (int j = 0; j < 4; ++j) { dzv[i][s / 2][j] = v0[j]; dzv[i][s / 2][4 + j] = v1[j]; }
           }
         {
-          const u4* s4 = src_of(k + 1);
+          if constexpr (!A1) {
+            const u4* s4 = src_of(k + 1);
 #pragma unroll
-          for (int q = 0; q < NQ; ++q) pre[q] = s4[q * 256 + hl];
+            for (int q = 0; q < NQ; ++q) pre[q] = s4[q * 256 + hl];
+          }
           load_dz(k + 1);
         }
         if (t < t_hi) {
@@ -508,7 +548,9 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
             }
         }
         // the other buffer was last read in iteration k-1, before its barrier
-        {
+        if constexpr (A1) {
+          build_A(tile_of(k + 1), stage + (half * 2 + ((k + 1) & 1)) * TA);
+        } else {
           u4* d4 = (u4*)(stage + (half * 2 + ((k + 1) & 1)) * TA);
 #pragma unroll
           for (int q = 0; q < NQ; ++q) d4[q * 256 + hl] = pre[q];
@@ -561,10 +603,14 @@ hipError_t wide_impl(const WideCall& c) {
   if (e != hipSuccess) return e;
   for (int l = 2; l <= L; ++l) {
     if (c.timer_begin) c.timer_begin(c.timer_ctx);
-    hipLaunchKernelGGL((k_wide_dw<D, W, PREC>), dim3(c.grid), dim3(512), 0, c.stream, c.meta,
-                       (const char*)c.A + (int64_t)(l - 2) * c.lstride * Op<PREC>::bytes,
-                       (const char*)c.dZ + (int64_t)(l - 2) * c.lstride * Op<PREC>::bytes, c.partial,
-                       c.Ptot, c.lay->Wl[l - 2], c.off1);
+    const char* Al = (const char*)c.A + (int64_t)(l - 2) * c.lstride * Op<PREC>::bytes;
+    const char* dZl = (const char*)c.dZ + (int64_t)(l - 2) * c.lstride * Op<PREC>::bytes;
+    if (PREC == 1 && l == 2)   // BF16: the first layer's rows are rebuilt from the centres
+      hipLaunchKernelGGL((k_wide_dw<D, W, PREC, ACT, PREC == 1>), dim3(c.grid), dim3(512), 0, c.stream,
+                         c.meta, Al, dZl, c.partial, c.Ptot, c.lay->Wl[l - 2], c.off1, c.centres, *c.nets, c.h);
+    else
+      hipLaunchKernelGGL((k_wide_dw<D, W, PREC, ACT, false>), dim3(c.grid), dim3(512), 0, c.stream,
+                         c.meta, Al, dZl, c.partial, c.Ptot, c.lay->Wl[l - 2], c.off1, c.centres, *c.nets, c.h);
     if (c.timer_end) c.timer_end(c.timer_ctx);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
