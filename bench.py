@@ -233,7 +233,10 @@ def roofline(wl, meas):
         nbr = 2 * wl.dim if wl.mu_minus != wl.mu_plus else 0
         centres = int(c[0] + c[1] + (2 + nbr) * c[2] + c[3] + c[4])
         opb = 2 if wl.prec == I.PREC_BF16 else 4
-        moved = 2 * centres * wl.n_streams * wl.width * opb   # A and dZ of one layer
+        # A_{l-1} and dZ_l of every hidden layer, averaged over the launches;
+        # with BF16 operands the first layer's A rows are rebuilt, not read
+        arrays = 2 * (wl.depth - 1) - (1 if wl.prec == I.PREC_BF16 else 0)
+        moved = arrays * centres * wl.n_streams * wl.width * opb / (wl.depth - 1)
         avg_w = w_ms / w_n
         out["weight_grad_pass"] = {
             "kernel": "k_wide_dw (one launch per hidden layer)", "avg_launch_ms": avg_w,
