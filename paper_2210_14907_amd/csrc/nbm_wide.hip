@@ -104,6 +104,10 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
         xs[tid][0] = cc.x; xs[tid][1] = cc.y; xs[tid][2] = cc.z;
         xs[tid][3] = inl ? fslot[slot0 + tid] : 0.f;
       }
+      // point index of an inline tile's centre, read here with the centres:
+      // a read at the residual would wait for the operand-row stores issued
+      // before it
+      const int scur = inl && tid < kTile ? src[slot0 + tid] : 0;
       if (!inl && tid < kTile * 8) {
         // output adjoints of a non-inline tile, written by the residual kernels
         const int64_t slot = slot0 + tid / 8;
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
       if (inl) {
         if (tid < kTile) {
           const float r = uncut_r(tid);
-          resid[src[slot0 + tid]] = r;
+          resid[scur] = r;
           lsum[tid] += (double)r * (double)r;
         }
         for (int j = 0; j < 4; ++j) {
