@@ -160,6 +160,20 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
       float dz[S][4];
       float eS[4];
       int cur = 0;
+      // BF16: this lane's weight operand of the next product, loaded just
+      // before the operand-row stores that precede it (loads and stores retire
+      // through one counter, so a load issued after the stores would wait for
+      // them to reach memory)
+      bf8 wk[PREC == 1 ? KC / 8 : 1];
+      float wbias = 0.f;   // and the forward product's bias
+      auto load_wk = [&](const void* m, const float* bias_row) {
+        if constexpr (PREC == 1) {
+          const bf8* wp = (const bf8*)((const char*)m + wo);
+          for (int q = 0; q < KC / 8; ++q) wk[q] = wp[q];
+          if (bias_row != nullptr) wbias = bias_row[n];
+        }
+      };
+      load_wk(np.Wl[0], np.bl[0]);
 #pragma unroll
       for (int l = 2; l <= L; ++l) {
         f4 acc[S];
@@ -178,14 +192,11 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
             }
           }
         } else {
-          const bf8* wp = (const bf8*)((const char*)np.Wl[l - 2] + wo);
-          for (int q = 0; q < KC / 8; ++q) {
-            bf8 bk = wp[q];
-            for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[cur][s][r16][g * KC + 8 * q]), bk, acc[s]);
-          }
+          for (int q = 0; q < KC / 8; ++q)
+            for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[cur][s][r16][g * KC + 8 * q]), wk[q], acc[s]);
         }
         mfma_phase_end();
-        const float bias = np.bl[l - 2][n];
+        const float bias = PREC == 1 ? wbias : np.bl[l - 2][n];
         if (l < L) {
           float vals[S][4];
           for (int j = 0; j < 4; ++j) {
@@ -206,6 +217,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           if (kZ0inLDS && l == 2)
             for (int s = 0; s < S; ++s)
               *(float4*)(&Zs[s][g][n][0]) = make_float4(Z[0][s][0], Z[0][s][1], Z[0][s][2], Z[0][s][3]);
+          load_wk(np.Wl[l - 1], np.bl[l - 1]);   // the next layer's product
           for (int s = 0; s < S; ++s) {
             for (int j = 0; j < 4; ++j) bufR[cur ^ 1][s][4 * g + j][n] = from_f<T>(vals[s][j]);
             T* dst = rowp(Aout + (int64_t)(l - 1) * lstride, s);
@@ -304,6 +316,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
 #pragma unroll
       for (int l = L; l >= 2; --l) {
         for (int j = 0; j < 4; ++j) accb[l - 1] += dz[0][j];
+        load_wk(np.WlT[l - 2], nullptr);   // this layer's transposed product, below
         for (int s = 0; s < S; ++s) {
           for (int j = 0; j < 4; ++j) bufR[bb][s][4 * g + j][n] = from_f<T>(dz[s][j]);
           T* dst = rowp(dZout + (int64_t)(l - 2) * lstride, s);
@@ -329,11 +342,8 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
             }
           }
         } else {
-          const bf8* wp = (const bf8*)((const char*)np.WlT[l - 2] + wo);
-          for (int q = 0; q < KC / 8; ++q) {
-            bf8 bk = wp[q];
-            for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[bb][s][r16][g * KC + 8 * q]), bk, acc[s]);
-          }
+          for (int q = 0; q < KC / 8; ++q)
+            for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[bb][s][r16][g * KC + 8 * q]), wk[q], acc[s]);
         }
         mfma_phase_end();
         if (kZ0inLDS && l == 3)
