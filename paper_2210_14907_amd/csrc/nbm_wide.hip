@@ -91,10 +91,13 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
     const int64_t a_end = (int64_t)meta->base[net][KIND_A] + meta->cnt[net][KIND_A];
     const int t_lo = net == 0 ? 0 : meta->tiles[0];
     const int t_hi = net == 0 ? meta->tiles[0] : ntiles;
+    // read once per net: inside the tile loop the batch record would be
+    // re-read after every tile's stores (which the compiler cannot rule out
+    // aliasing it), and that read would wait for them
+    const int64_t slot_end = (int64_t)meta->tile0[net] * kTile + meta->total[net];
 
     for (int t = t_lo + blockIdx.x; t < t_hi; t += G) {
       const int64_t slot0 = (int64_t)t * kTile;
-      const int64_t slot_end = (int64_t)meta->tile0[net] * kTile + meta->total[net];
       const bool inl = slot0 + kTile <= a_end;   // uniform over the work-group
       if (tid < kTile) {
         float4 cc = centres[slot0 + tid];
