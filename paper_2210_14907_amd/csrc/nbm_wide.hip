@@ -7,15 +7,19 @@
 // takes the adjoints written by the residual kernels for other tiles), and
 // walks backward computing dZ_l for every hidden layer.
 // The operands of the weight-gradient contraction, A_{l-1} and dZ_l, leave
-// the chip in the accumulator ("tile") layout [tile][stream][neuron][16];
+// the chip in the accumulator ("tile") layout [tile][stream][neuron][16]
+// (with BF16 operands except A_1, which pass 2 rebuilds from the centres);
 // the small gradients (biases, W_1, w_out) are accumulated per work-group.
+// Loads and stores retire through one counter, so loads are placed ahead of
+// the store bursts they would otherwise wait behind.
 //
-// The forward/backward pass runs first in a fast form that takes the micro
-// tier of the activation streams for every element without branching
-// (checking the tier's bound per lane as it goes); if any argument lies
-// beyond that bound it raises meta->slow, and the general form, launched
-// right after and otherwise exiting at once, recomputes the whole pass with
-// per-element tiers, overwriting every output of the fast one.
+// With BF16 operands the forward/backward pass runs first in a fast form
+// that takes the micro tier of the activation streams for every element
+// without branching (keeping the running maximum of the tier's arguments);
+// if any argument lies beyond the tier's bound it raises meta->slow, and the
+// general form, launched right after and otherwise exiting at once,
+// recomputes the whole pass with per-element tiers, overwriting every output
+// of the fast one.  FP32 operands run the general form alone.
 //
 // Pass 2 (k_wide_dw): dW_l = sum over (tile, stream, centre) of dZ_l^T A_{l-1}
 // read straight from the tile layout as MFMA operands (the K index runs over
