@@ -447,6 +447,12 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
   constexpr int kXchBytes = OBW * NOB * 256 * 16;
   __shared__ __attribute__((aligned(16))) char lds[kStageBytes > kXchBytes ? kStageBytes : kXchBytes];
   T* stage = reinterpret_cast<T*>(lds);
+  // Staged A block: a row (one stream and input neuron, 16 centres, 32 bytes)
+  // holds two 16-byte halves, swapped in rows whose index has bit 3 set.  A
+  // wavefront's operand read takes 8 bytes from each of 16 consecutive rows
+  // (two lane groups per half-wavefront); without the swap rows r and r + 8
+  // fall on the same banks.
+  auto stage_slot = [](int u) { const int row = u >> 1; return (row << 1) | ((u & 1) ^ ((row >> 3) & 1)); };
   f4 (*xch)[NOB][256] = reinterpret_cast<f4 (*)[NOB][256]>(lds);
   for (int net = 0; net < 2; ++net) {
     const int t_lo = net == 0 ? 0 : meta->tiles[0];
@@ -509,7 +515,10 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
           o[0][c] = (__bf16)av;
           for (int a = 0; a < D; ++a) { o[1 + a][c] = (__bf16)Dv[a]; o[1 + D + a][c] = (__bf16)Ev[a]; }
         }
-        for (int s = 0; s < S; ++s) *(bf8*)(dst + (s * W + an) * kTile + ac0) = o[s];
+        for (int s = 0; s < S; ++s) {
+          const int row = s * W + an;
+          *(bf8*)(dst + row * kTile + (((ac0 >> 3) ^ ((row >> 3) & 1)) << 3)) = o[s];
+        }
       };
       auto src_of = [&](int k) {
         const int t = tile_of(k) < t_hi ? tile_of(k) : t_hi - 1;
@@ -534,7 +543,7 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
           for (int q = 0; q < NQ; ++q) pre[q] = s4[q * 256 + hl];
           u4* d4 = (u4*)(stage + (half * 2) * TA);
 #pragma unroll
-          for (int q = 0; q < NQ; ++q) d4[q * 256 + hl] = pre[q];
+          for (int q = 0; q < NQ; ++q) d4[stage_slot(q * 256 + hl)] = pre[q];
         }
         load_dz(0);
       }
@@ -559,10 +568,12 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
         }
         if (t < t_hi) {
           const T* As = stage + (half * 2 + (k & 1)) * TA;
+          // centres 4g..4g+3 of a row: half (g >> 1) of it, swapped in rows with bit 3 set
+          const int cofs = ((((g >> 1) ^ (r16 >> 3)) << 3) | ((g & 1) << 2));
           for (int ib = 0; ib < NOB; ++ib)
             for (int s = 0; s < S; s += 2) {
-              bf4 v0 = *(const bf4*)(As + (s * W + ib * 16 + r16) * kTile + 4 * g);
-              bf4 v1 = s + 1 < S ? *(const bf4*)(As + ((s + 1) * W + ib * 16 + r16) * kTile + 4 * g) : zero4;
+              bf4 v0 = *(const bf4*)(As + (s * W + ib * 16 + r16) * kTile + cofs);
+              bf4 v1 = s + 1 < S ? *(const bf4*)(As + ((s + 1) * W + ib * 16 + r16) * kTile + cofs) : zero4;
               bf8 a;
               for (int j = 0; j < 4; ++j) { a[j] = v0[j]; a[4 + j] = v1[j]; }
               for (int i = 0; i < OBW; ++i) acc[i][ib] = mfma32(dzv[i][s / 2], a, acc[i][ib]);
@@ -574,7 +585,7 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
         } else {
           u4* d4 = (u4*)(stage + (half * 2 + ((k + 1) & 1)) * TA);
 #pragma unroll
-          for (int q = 0; q < NQ; ++q) d4[q * 256 + hl] = pre[q];
+          for (int q = 0; q < NQ; ++q) d4[stage_slot(q * 256 + hl)] = pre[q];
         }
         __syncthreads();
       }
