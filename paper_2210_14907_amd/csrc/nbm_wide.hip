@@ -48,12 +48,29 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
     if (slow != nullptr && *slow == 0) return;
   float amax = 0.f;   // fast form: largest micro argument this lane met
   constexpr int S = 2 * D + 1;
-  constexpr int LD = W + (PREC == 0 ? 4 : 8);
   constexpr int NW = W / 16;     // wavefronts; wave w owns neurons 16w .. 16w+15
   constexpr int KC = W / 4;
   // micro forms of the hidden layers: up to 1/256, or 1/32 with BF16 operands
   constexpr int kMicroW = PREC == 1 ? 2 : 1;
-  __shared__ __attribute__((aligned(16))) T bufR[2][S][kTile][LD];
+  // Row buffers of the 16 centres' activations (or adjoints), the A operand
+  // of every product, double-buffered per stream.  BF16: chunk-major, the
+  // 16-byte chunk k (neurons 8k .. 8k+7) of all 16 centres side by side, and
+  // lane group g takes chunk 4q + g at product step q, so a wavefront's
+  // operand read covers 1 KB in lane order (free of LDS bank conflicts,
+  // where padded rows cost extra cycles on every read).  FP32: centre rows
+  // padded to W + 4, lane group g taking neurons g W/4 + 4q .. + 3 at step q
+  // (the chunk-major order measured slower there: its 32-bit row writes
+  // conflict where the 16-bit ones of BF16 conflict less).
+  constexpr int EPC = 16 / (int)sizeof(T);   // values per 16-byte chunk
+  constexpr int kRowBuf = PREC == 1 ? kTile * W : kTile * (W + 4);
+  __shared__ __attribute__((aligned(16))) T bufR[2][S][kRowBuf];
+  // position of (centre c, neuron m) and of lane (r16, g)'s operand at step q
+  auto rpos = [](int c, int m) {
+    return PREC == 1 ? (m / EPC) * (kTile * EPC) + c * EPC + m % EPC : c * (W + 4) + m;
+  };
+  auto apos = [](int r, int gg, int q) {
+    return PREC == 1 ? (4 * q + gg) * (kTile * EPC) + r * EPC : r * (W + 4) + gg * KC + 4 * q;
+  };
   // BF16 operands leave room in LDS for the first hidden layer's
   // pre-activations [stream][neuron][centre] (each lane reads back only what
   // it wrote); FP32 operands keep them in registers
@@ -69,8 +86,9 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
   T* dZout = (T*)dZout_;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r16 = lane & 15, g = lane >> 4;
   const int n = w * 16 + r16;
-  // byte offset of this lane's weight row segment in a W x W matrix
-  const uint32_t woff = (uint32_t)((n * W + g * KC) * (int)sizeof(T));
+  // byte offset of this lane's first weight operand in a W x W matrix (row n;
+  // BF16: chunk g, then every fourth chunk, matching the row buffer's order)
+  const uint32_t woff = (uint32_t)((n * W + g * (PREC == 1 ? EPC : KC)) * (int)sizeof(T));
   const int G = gridDim.x;
   const int ntiles = meta->tiles[0] + meta->tiles[1];
   const float hh = h * h;
@@ -152,7 +170,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           for (int a = 0; a < D; ++a) { vals[1 + a][j] = Dv[a]; vals[1 + D + a][j] = Ev[a]; }
         }
         for (int s = 0; s < S; ++s) {
-          for (int j = 0; j < 4; ++j) bufR[0][s][4 * g + j][n] = from_f<T>(vals[s][j]);
+          for (int j = 0; j < 4; ++j) bufR[0][s][rpos(4 * g + j, n)] = from_f<T>(vals[s][j]);
           // first-layer operand rows: stored with FP32 operands; with BF16 the
           // weight-gradient pass rebuilds them from the centres
           if constexpr (PREC == 0)
@@ -176,7 +194,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
       auto load_wk = [&](const void* m, const float* bias_row) {
         if constexpr (PREC == 1) {
           const bf8* wp = (const bf8*)((const char*)m + wo);
-          for (int q = 0; q < KC / 8; ++q) wk[q] = wp[q];
+          for (int q = 0; q < KC / 8; ++q) wk[q] = wp[4 * q];
           if (bias_row != nullptr) wbias = bias_row[n];
         }
       };
@@ -191,7 +209,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           for (int q = 0; q < KC / 4; ++q) {
             float4 b4 = wp[q];
             for (int s = 0; s < S; ++s) {
-              float4 a4 = *(const float4*)(&bufR[cur][s][r16][g * KC + 4 * q]);
+              float4 a4 = *(const float4*)(&bufR[cur][s][apos(r16, g, q)]);
               acc[s] = mfma4(a4.x, b4.x, acc[s]);
               acc[s] = mfma4(a4.y, b4.y, acc[s]);
               acc[s] = mfma4(a4.z, b4.z, acc[s]);
@@ -200,7 +218,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           }
         } else {
           for (int q = 0; q < KC / 8; ++q)
-            for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[cur][s][r16][g * KC + 8 * q]), wk[q], acc[s]);
+            for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[cur][s][apos(r16, g, q)]), wk[q], acc[s]);
         }
         mfma_phase_end();
         const float bias = PREC == 1 ? wbias : np.bl[l - 2][n];
@@ -226,7 +244,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
               *(float4*)(&Zs[s][g][n][0]) = make_float4(Z[0][s][0], Z[0][s][1], Z[0][s][2], Z[0][s][3]);
           load_wk(np.Wl[l - 1], np.bl[l - 1]);   // the next layer's product
           for (int s = 0; s < S; ++s) {
-            for (int j = 0; j < 4; ++j) bufR[cur ^ 1][s][4 * g + j][n] = from_f<T>(vals[s][j]);
+            for (int j = 0; j < 4; ++j) bufR[cur ^ 1][s][rpos(4 * g + j, n)] = from_f<T>(vals[s][j]);
             T* dst = rowp(Aout + (int64_t)(l - 1) * lstride, s);
             if constexpr (PREC == 0)
               *(float4*)dst = make_float4(vals[s][0], vals[s][1], vals[s][2], vals[s][3]);
@@ -325,7 +343,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
         for (int j = 0; j < 4; ++j) accb[l - 1] += dz[0][j];
         load_wk(np.WlT[l - 2], nullptr);   // this layer's transposed product, below
         for (int s = 0; s < S; ++s) {
-          for (int j = 0; j < 4; ++j) bufR[bb][s][4 * g + j][n] = from_f<T>(dz[s][j]);
+          for (int j = 0; j < 4; ++j) bufR[bb][s][rpos(4 * g + j, n)] = from_f<T>(dz[s][j]);
           T* dst = rowp(dZout + (int64_t)(l - 2) * lstride, s);
           if constexpr (PREC == 0)
             *(float4*)dst = make_float4(dz[s][0], dz[s][1], dz[s][2], dz[s][3]);
@@ -341,7 +359,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           for (int q = 0; q < KC / 4; ++q) {
             float4 b4 = wp[q];
             for (int s = 0; s < S; ++s) {
-              float4 a4 = *(const float4*)(&bufR[bb][s][r16][g * KC + 4 * q]);
+              float4 a4 = *(const float4*)(&bufR[bb][s][apos(r16, g, q)]);
               acc[s] = mfma4(a4.x, b4.x, acc[s]);
               acc[s] = mfma4(a4.y, b4.y, acc[s]);
               acc[s] = mfma4(a4.z, b4.z, acc[s]);
@@ -350,7 +368,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           }
         } else {
           for (int q = 0; q < KC / 8; ++q)
-            for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[bb][s][r16][g * KC + 8 * q]), wk[q], acc[s]);
+            for (int s = 0; s < S; ++s) acc[s] = mfma32(*(const bf8*)(&bufR[bb][s][apos(r16, g, q)]), wk[q], acc[s]);
         }
         mfma_phase_end();
         if (kZ0inLDS && l == 3)
