@@ -45,10 +45,24 @@ __global__ __launch_bounds__((EvalShape<W, PREC>::NT), 2) void k_eval_mlp(const 
   constexpr int NT = EvalShape<W, PREC>::NT;
   constexpr int RB = kEvalTile / 16;      // MFMA row blocks per tile
   constexpr int KC = W / 4;               // K chunk per lane group
-  constexpr int LD = W + (PREC == 0 ? 4 : 8);
   constexpr int NB = PREC == 0 ? KC : KC / 8;   // operand registers per layer and block
   static_assert(kEvalTile <= NT, "one thread per centre for the tile's bookkeeping");
-  __shared__ __attribute__((aligned(16))) T buf[2][kEvalTile][LD];
+  // Activation tiles, the B operand of every product.  BF16: per 16-centre
+  // row block, the 16-byte chunk k (neurons 8k .. 8k+7) of its 16 centres
+  // side by side, and lane group g takes chunk 4q + g at step q, so one
+  // operand read covers 1 KB in lane order (padded centre rows cost extra
+  // LDS bank-conflict cycles on every read).  FP32: centre rows padded to
+  // W + 4, lane group g taking neurons g W/4 + 4q .. + 3.
+  constexpr int kBuf = PREC == 1 ? kEvalTile * W : kEvalTile * (W + 4);
+  __shared__ __attribute__((aligned(16))) T buf[2][kBuf];
+  // position of (centre c, neuron m), and of the operand of lane (r, gg) of
+  // row block rb at step q
+  auto bpos = [](int c, int m) {
+    return PREC == 1 ? (((c >> 4) * (W / 8) + (m >> 3)) * 16 + (c & 15)) * 8 + (m & 7) : c * (W + 4) + m;
+  };
+  auto opos = [](int rb, int r, int gg, int q) {
+    return PREC == 1 ? ((rb * (W / 8) + 4 * q + gg) * 16 + r) * 8 : (16 * rb + r) * (W + 4) + gg * KC + 4 * q;
+  };
   __shared__ float xs[kEvalTile][4];
   __shared__ int qs[kEvalTile];           // query index of each centre, -1 = padding
   __shared__ float part[NW][kEvalTile];
@@ -81,10 +95,13 @@ __global__ __launch_bounds__((EvalShape<W, PREC>::NT), 2) void k_eval_mlp(const 
     for (int l = 0; l < L - 1; ++l)
 #pragma unroll
       for (int k = 0; k < NBW; ++k) {
-        const float4* wp = (const float4*)(np.Wf[l] + (int64_t)(16 * blk(k) + r16) * W + g * KC);
+        // FP32: K values g W/4 + 4q + i; BF16: operand q takes the chunk
+        // 4q + g of the row (the activation tiles' order)
+        const float* wrow = np.Wf[l] + (int64_t)(16 * blk(k) + r16) * W;
 #pragma unroll
         for (int q = 0; q < KC / 4; ++q) {
-          const float4 v = wp[q];
+          const int e0 = PREC == 0 ? g * KC + 4 * q : 8 * (4 * (q / 2) + g) + 4 * (q & 1);
+          const float4 v = *(const float4*)(wrow + e0);
           const float e[4] = {ks * v.x, ks * v.y, ks * v.z, ks * v.w};
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
@@ -131,8 +148,8 @@ __global__ __launch_bounds__((EvalShape<W, PREC>::NT), 2) void k_eval_mlp(const 
       // stores of a lane's four consecutive neurons of block k at centre c
       auto put4 = [&](int b, int c, int k, const float* v) {
         const int n0 = 16 * blk(k) + 4 * g;
-        if constexpr (PREC == 0) *(float4*)(&buf[b][c][n0]) = make_float4(v[0], v[1], v[2], v[3]);
-        else *(bf4*)(&buf[b][c][n0]) = bf4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+        if constexpr (PREC == 0) *(float4*)(&buf[b][bpos(c, n0)]) = make_float4(v[0], v[1], v[2], v[3]);
+        else *(bf4*)(&buf[b][bpos(c, n0)]) = bf4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
       };
 
       // ---- layer 1 (VALU): centre 16 rb + r16, neurons 16 blk(k) + 4 g + j
@@ -166,7 +183,7 @@ __global__ __launch_bounds__((EvalShape<W, PREC>::NT), 2) void k_eval_mlp(const 
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           if constexpr (PREC == 0) {
-            const float4* bp = (const float4*)(&buf[cur][16 * rb + r16][g * KC]);
+            const float4* bp = (const float4*)(&buf[cur][opos(rb, r16, g, 0)]);
 #pragma unroll
             for (int q = 0; q < KC / 4; ++q) {
               const float4 b4 = bp[q];
@@ -179,10 +196,9 @@ __global__ __launch_bounds__((EvalShape<W, PREC>::NT), 2) void k_eval_mlp(const 
               }
             }
           } else {
-            const bf8* bp = (const bf8*)(&buf[cur][16 * rb + r16][g * KC]);
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
-              const bf8 b8 = bp[q];
+              const bf8 b8 = *(const bf8*)(&buf[cur][opos(rb, r16, g, q)]);
 #pragma unroll
               for (int k = 0; k < NBW; ++k) acc[k][rb] = mfma32(A.b[l][k][q], b8, acc[k][rb]);
             }
