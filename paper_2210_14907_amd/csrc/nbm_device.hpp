@@ -12,6 +12,21 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+
+// Streaming (non-temporal) accesses for data that crosses HBM exactly once
+// between two kernels: the weight-gradient operands, written by the forward/
+// backward pass and read once by the contraction.  They bypass the cache
+// retention the rest of the working set (weights, tables, centres) relies on.
+__device__ __forceinline__ void st_stream(bf4* p, bf4 v) {
+  __builtin_nontemporal_store(__builtin_bit_cast(u2, v), (u2*)p);
+}
+__device__ __forceinline__ void st_stream(float* p, f4 v) { __builtin_nontemporal_store(v, (f4*)p); }
+__device__ __forceinline__ bf4 ld_stream(const bf4* p) {
+  return __builtin_bit_cast(bf4, __builtin_nontemporal_load((const u2*)p));
+}
+__device__ __forceinline__ f4 ld_stream(const float* p) { return __builtin_nontemporal_load((const f4*)p); }
+__device__ __forceinline__ u4 ld_stream(const u4* p) { return __builtin_nontemporal_load(p); }
 
 // v_mfma_f32_16x16x4f32: lane l supplies A[l%16][k], B[k][l%16] with k = l/16;
 // result lane l holds C[4*(l/16)+r][l%16], r = 0..3.

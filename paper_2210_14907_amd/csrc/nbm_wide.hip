@@ -11,7 +11,9 @@
 // (with BF16 operands except A_1, which pass 2 rebuilds from the centres);
 // the small gradients (biases, W_1, w_out) are accumulated per work-group.
 // Loads and stores retire through one counter, so loads are placed ahead of
-// the store bursts they would otherwise wait behind.
+// the store bursts they would otherwise wait behind.  The operand rows cross
+// HBM once (written here, read once by pass 2), so both sides use streaming
+// (non-temporal) accesses and leave the caches to the reused data.
 //
 // With BF16 operands the forward/backward pass runs first in a fast form
 // that takes the micro tier of the activation streams for every element
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           // first-layer operand rows: stored with FP32 operands; with BF16 the
           // weight-gradient pass rebuilds them from the centres
           if constexpr (PREC == 0)
-            *(float4*)rowp(Aout, s) = make_float4(vals[s][0], vals[s][1], vals[s][2], vals[s][3]);
+            st_stream((float*)rowp(Aout, s), f4{vals[s][0], vals[s][1], vals[s][2], vals[s][3]});
         }
       }
       __syncthreads();
@@ -247,9 +249,9 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
             for (int j = 0; j < 4; ++j) bufR[cur ^ 1][s][rpos(4 * g + j, n)] = from_f<T>(vals[s][j]);
             T* dst = rowp(Aout + (int64_t)(l - 1) * lstride, s);
             if constexpr (PREC == 0)
-              *(float4*)dst = make_float4(vals[s][0], vals[s][1], vals[s][2], vals[s][3]);
+              st_stream((float*)dst, f4{vals[s][0], vals[s][1], vals[s][2], vals[s][3]});
             else
-              *(bf4*)dst = bf4{(__bf16)vals[s][0], (__bf16)vals[s][1], (__bf16)vals[s][2], (__bf16)vals[s][3]};
+              st_stream((bf4*)dst, bf4{(__bf16)vals[s][0], (__bf16)vals[s][1], (__bf16)vals[s][2], (__bf16)vals[s][3]});
           }
         } else {
           // output adjoints: known for non-inline tiles; inline tiles carry one
@@ -346,9 +348,9 @@ __global__ __launch_bounds__(W * 4) void k_wide_fb(const Meta* meta, const float
           for (int j = 0; j < 4; ++j) bufR[bb][s][rpos(4 * g + j, n)] = from_f<T>(dz[s][j]);
           T* dst = rowp(dZout + (int64_t)(l - 2) * lstride, s);
           if constexpr (PREC == 0)
-            *(float4*)dst = make_float4(dz[s][0], dz[s][1], dz[s][2], dz[s][3]);
+            st_stream((float*)dst, f4{dz[s][0], dz[s][1], dz[s][2], dz[s][3]});
           else
-            *(bf4*)dst = bf4{(__bf16)dz[s][0], (__bf16)dz[s][1], (__bf16)dz[s][2], (__bf16)dz[s][3]};
+            st_stream((bf4*)dst, bf4{(__bf16)dz[s][0], (__bf16)dz[s][1], (__bf16)dz[s][2], (__bf16)dz[s][3]});
         }
         __syncthreads();
         f4 acc[S];
@@ -484,12 +486,12 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
         float dzv[OBW][S][4];
         for (int i = 0; i < OBW; ++i)
           for (int s = 0; s < S; ++s) {
-            float4 v = *(const float4*)(dZ + tofs(s, (w + 4 * i) * 16 + r16));
+            const f4 v = ld_stream((const float*)(dZ + tofs(s, (w + 4 * i) * 16 + r16)));
             dzv[i][s][0] = v.x; dzv[i][s][1] = v.y; dzv[i][s][2] = v.z; dzv[i][s][3] = v.w;
           }
         for (int ib = 0; ib < NOB; ++ib)
           for (int s = 0; s < S; ++s) {
-            float4 a = *(const float4*)(A + tofs(s, ib * 16 + r16));
+            const f4 a = ld_stream((const float*)(A + tofs(s, ib * 16 + r16)));
             for (int i = 0; i < OBW; ++i) {
               acc[i][ib] = mfma4(dzv[i][s][0], a.x, acc[i][ib]);
               acc[i][ib] = mfma4(dzv[i][s][1], a.y, acc[i][ib]);
@@ -550,7 +552,7 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
         const char* tb = (const char*)(dZ + (int64_t)t * TA);
         for (int i = 0; i < OBW; ++i)
           for (int s = 0; s < S; ++s)
-            dzr[i][s] = *(const bf4*)(tb + (uint32_t)((((s * W + (w + 4 * i) * 16 + r16) * kTile) + 4 * g) * 2));
+            dzr[i][s] = ld_stream((const bf4*)(tb + (uint32_t)((((s * W + (w + 4 * i) * 16 + r16) * kTile) + 4 * g) * 2)));
       };
       if (niter > 0) {
         if constexpr (A1) {
@@ -558,7 +560,7 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
         } else {
           const u4* s4 = src_of(0);
 #pragma unroll
-          for (int q = 0; q < NQ; ++q) pre[q] = s4[q * 256 + hl];
+          for (int q = 0; q < NQ; ++q) pre[q] = ld_stream(&s4[q * 256 + hl]);
           u4* d4 = (u4*)(stage + (half * 2) * TA);
 #pragma unroll
           for (int q = 0; q < NQ; ++q) d4[stage_slot(q * 256 + hl)] = pre[q];
@@ -580,7 +582,7 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
           if constexpr (!A1) {
             const u4* s4 = src_of(k + 1);
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) pre[q] = s4[q * 256 + hl];
+            for (int q = 0; q < NQ; ++q) pre[q] = ld_stream(&s4[q * 256 + hl]);
           }
           load_dz(k + 1);
         }
