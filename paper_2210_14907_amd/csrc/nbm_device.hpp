@@ -16,12 +16,14 @@ typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 
 // Streaming (non-temporal) accesses for data that crosses HBM exactly once
 // between two kernels: the weight-gradient operands, written by the forward/
-// backward pass and read once by the contraction.  They bypass the cache
+// backward pass and read once by the contraction, and the per-work-group
+// weight-gradient partial rows, read once by the reduction.  They bypass the cache
 // retention the rest of the working set (weights, tables, centres) relies on.
 __device__ __forceinline__ void st_stream(bf4* p, bf4 v) {
   __builtin_nontemporal_store(__builtin_bit_cast(u2, v), (u2*)p);
 }
 __device__ __forceinline__ void st_stream(float* p, f4 v) { __builtin_nontemporal_store(v, (f4*)p); }
+__device__ __forceinline__ void st_stream(float* p, float v) { __builtin_nontemporal_store(v, p); }
 __device__ __forceinline__ bf4 ld_stream(const bf4* p) {
   return __builtin_bit_cast(bf4, __builtin_nontemporal_load((const u2*)p));
 }

@@ -622,7 +622,7 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
           const f4 o = xch[i][ib][hl];
           for (int r = 0; r < 4; ++r) {
             int row = (w + 4 * i) * 16 + 4 * g + r, col = ib * 16 + r16;
-            prow[(int64_t)row * W + col] = acc[i][ib][r] + o[r];
+            st_stream(&prow[(int64_t)row * W + col], acc[i][ib][r] + o[r]);
           }
         }
     }
