@@ -486,12 +486,13 @@ __global__ __launch_bounds__(512) void k_wide_dw(const Meta* meta, const void* A
         float dzv[OBW][S][4];
         for (int i = 0; i < OBW; ++i)
           for (int s = 0; s < S; ++s) {
-            const f4 v = ld_stream((const float*)(dZ + tofs(s, (w + 4 * i) * 16 + r16)));
+            // (plain loads: streaming ones measured slower on this FP32 path)
+            const f4 v = *(const f4*)(dZ + tofs(s, (w + 4 * i) * 16 + r16));
             dzv[i][s][0] = v.x; dzv[i][s][1] = v.y; dzv[i][s][2] = v.z; dzv[i][s][3] = v.w;
           }
         for (int ib = 0; ib < NOB; ++ib)
           for (int s = 0; s < S; ++s) {
-            const f4 a = ld_stream((const float*)(A + tofs(s, ib * 16 + r16)));
+            const f4 a = *(const f4*)(A + tofs(s, ib * 16 + r16));
             for (int i = 0; i < OBW; ++i) {
               acc[i][ib] = mfma4(dzv[i][s][0], a.x, acc[i][ib]);
               acc[i][ib] = mfma4(dzv[i][s][1], a.y, acc[i][ib]);
