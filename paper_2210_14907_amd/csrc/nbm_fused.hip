@@ -402,7 +402,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const Meta* meta, const float4
       for (int ob = 0; ob < NOB; ++ob)
         for (int r = 0; r < 4; ++r) {
           const int nin = w * 16 + 4 * g + r, nout = ob * 16 + r16;
-          st_stream(&prow[lay.Wl[l - 2] + (int64_t)nout * W + nin], accW[l - 2][ob][r]);
+          prow[lay.Wl[l - 2] + (int64_t)nout * W + nin] = accW[l - 2][ob][r];
         }
     for (int l = 0; l < L; ++l) {
       float v = accb[l];
