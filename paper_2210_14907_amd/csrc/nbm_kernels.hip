@@ -1425,7 +1425,9 @@ static void prep_impl(const PrepCall& c, int64_t nblk, int64_t nblkb) {
                        c.eval ? 1 : 0, c.tile_index, c.grid_n, c.cls, c.rank, c.blockcnt, (int)nblk,
                        c.bpts, c.nb, c.bcls, c.brank, c.blockcnt_b, (int)(nblk + nblkb), c.shadows,
                        c.prec, spm);
-  // up to 2048 point blocks one work-group scans the block counts; larger
+  // up to 2048 point blocks one work-group scans the block counts, 256 threads
+  // when each count array fits one chunk of 256, else kScanThreads (one or two
+  // chunks); larger
   // batches (evaluation tiles, the largest training batches) scan chunks of
   // kScanThreads counts in parallel, then the chunk totals
   const bool chunked = nblk + nblkb > 2048;
@@ -1436,7 +1438,8 @@ static void prep_impl(const PrepCall& c, int64_t nblk, int64_t nblkb) {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, st, c.ctot, (int)nci, c.ctot_b, (int)ncb, c.coff,
                        c.coff_b, c.meta, (int)c.n, (int)c.nb, c.cut_cap, D, c.P.lo, c.eval ? 1 : 0);
   } else {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, st, c.blockcnt, (int)nblk, c.blockcnt_b,
+    const int sthreads = nblk > 256 || nblkb > 256 ? kScanThreads : 256;
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(sthreads), 0, st, c.blockcnt, (int)nblk, c.blockcnt_b,
                        (int)nblkb, c.off, c.off_b, c.meta, (int)c.n, (int)c.nb, c.cut_cap, D, c.P.lo,
                        c.eval ? 1 : 0);
   }
