@@ -918,8 +918,12 @@ __device__ inline int tile_net(const Meta* m, int t) {
   return -1;
 }
 
+// wavefronts per block: one per 16-neuron block at W = 128 (the per-tile
+// chain is the launch's critical path: its tiles are few), else four
+template <int W> struct FwdWaves { static constexpr int v = W >= 128 ? 8 : 4; };
+
 template <int D, int W, int S, int ACT, int PREC, bool STORE>
-__global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4* centres, Nets nets,
+__global__ __launch_bounds__(FwdWaves<W>::v * 64) void k_forward(const Meta* meta, const float4* centres, Nets nets,
                                                  int L, float h, float* outputs, float* Zst,
                                                  void* Ast_, float* ALst, int64_t lstride,
                                                  int noninline) {
@@ -927,8 +931,20 @@ __global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4*
   constexpr int LD = W + Pad<PREC>::v;
   constexpr int NOB = W / 16;
   constexpr int KC = W / 4;  // K chunk per lane group
-  __shared__ __attribute__((aligned(16))) T buf[2][S][kTile][LD];
-  __shared__ float part[4][kTile][8];
+  constexpr int NWV = FwdWaves<W>::v, NT = 64 * NWV;
+  // Row buffers, the A operand of every product.  BF16: chunk-major, the
+  // 16-byte chunk k (neurons 8k .. 8k+7) of the 16 centres side by side, lane
+  // group g taking chunk 4q + g at step q (one operand read = 1 KB in lane
+  // order, free of LDS bank conflicts).  FP32: centre rows padded to LD.
+  constexpr int kRowBuf = PREC == 1 ? kTile * W : kTile * LD;
+  __shared__ __attribute__((aligned(16))) T buf[2][S][kRowBuf];
+  __shared__ float part[NWV][kTile][8];
+  auto rpos = [](int c, int m) {
+    return PREC == 1 ? (m / 8) * (kTile * 8) + c * 8 + m % 8 : c * LD + m;
+  };
+  auto apos = [](int r, int gg, int q) {
+    return PREC == 1 ? (4 * q + gg) * (kTile * 8) + r * 8 : r * LD + gg * KC + 4 * q;
+  };
   // all tiles: one per block.  noninline: only the tiles that are not 16
   // uncut centres (the fused kernel forms the residual of those itself),
   // walked with the grid as stride: their number is known only on the
@@ -954,7 +970,7 @@ __global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4*
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r16 = lane & 15, g = lane >> 4;
 
   // ---- layer 1 (K = d, VALU): z = W1 x + b1, p_i = h W1[:, i], e_i = 0
-  for (int it = tid; it < kTile * W; it += 256) {
+  for (int it = tid; it < kTile * W; it += NT) {
     int c = it & 15, n = it >> 4;
     float x[3] = {0, 0, 0};
     if (slot0 + c < slot_end) {
@@ -979,7 +995,7 @@ __global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4*
         pre[1 + a] = p[a]; pre[1 + D + a] = 0.0f;
       }
     for (int s = 0; s < S; ++s) {
-      buf[0][s][c][n] = from_f<T>(vals[s]);
+      buf[0][s][rpos(c, n)] = from_f<T>(vals[s]);
       if (STORE) {
         int64_t o = (((int64_t)t * S + s) * W + n) * kTile + c;
         Zst[o] = pre[s];
@@ -993,8 +1009,9 @@ __global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4*
   float vout[S][4];
   for (int s = 0; s < S; ++s)
     for (int j = 0; j < 4; ++j) vout[s][j] = 0.0f;
-  // this lane's B operand (row ob*16+r16 of W_l, K chunk g); the first neuron
-  // block's rows of the next layer are fetched one layer ahead
+  // this lane's B operand (row ob*16+r16 of W_l, K chunk g; BF16: the 16-byte
+  // chunks 4q + g, the row buffers' order); the first neuron block's rows of
+  // the next layer are fetched one layer ahead
   struct BRow { float f[PREC == 0 ? KC : 1]; bf8 b[PREC == 1 ? KC / 8 : 1]; };
   auto load_b = [&](int l, int ob) {
     BRow r;
@@ -1006,26 +1023,27 @@ __global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4*
         r.f[4 * q] = v4.x; r.f[4 * q + 1] = v4.y; r.f[4 * q + 2] = v4.z; r.f[4 * q + 3] = v4.w;
       }
     } else {
-      const bf8* wp = (const bf8*)((const T*)np.Wl[l - 2] + (int64_t)nrow * W + g * KC);
-      for (int q = 0; q < KC / 8; ++q) r.b[q] = wp[q];
+      const bf8* wp = (const bf8*)((const T*)np.Wl[l - 2] + (int64_t)nrow * W + 8 * g);
+      for (int q = 0; q < KC / 8; ++q) r.b[q] = wp[4 * q];
     }
     return r;
   };
-  BRow bnext = load_b(2, w);
+  // (wavefronts without a neuron block, W < 16 NWV, load nothing)
+  BRow bnext = w < NOB ? load_b(2, w) : BRow{};
   int cur = 0;
   for (int l = 2; l <= L; ++l) {
     const float* bl = np.bl[l - 2];
     const bool last = (l == L);
-    for (int ob = w; ob < NOB; ob += 4) {
+    for (int ob = w; ob < NOB; ob += NWV) {
       const int nrow = ob * 16 + r16;
       f4 acc[S];
       for (int s = 0; s < S; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
       const BRow bcur = ob == w ? bnext : load_b(l, ob);
-      if (ob + 4 >= NOB && l < L) bnext = load_b(l + 1, w);
+      if (ob + NWV >= NOB && l < L) bnext = load_b(l + 1, w);
       if constexpr (PREC == 0) {
         const float* bk = bcur.f;
         for (int s = 0; s < S; ++s) {
-          const float4* ap = (const float4*)(&buf[cur][s][r16][g * KC]);
+          const float4* ap = (const float4*)(&buf[cur][s][apos(r16, g, 0)]);
           for (int q = 0; q < KC / 4; ++q) {
             float4 a4 = ap[q];
             acc[s] = mfma4(a4.x, bk[4 * q], acc[s]);
@@ -1036,10 +1054,9 @@ __global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4*
         }
       } else {
         const bf8* bk = bcur.b;
-        for (int s = 0; s < S; ++s) {
-          const bf8* ap = (const bf8*)(&buf[cur][s][r16][g * KC]);
-          for (int q = 0; q < KC / 8; ++q) acc[s] = mfma32(ap[q], bk[q], acc[s]);
-        }
+        for (int s = 0; s < S; ++s)
+          for (int q = 0; q < KC / 8; ++q)
+            acc[s] = mfma32(*(const bf8*)(&buf[cur][s][apos(r16, g, q)]), bk[q], acc[s]);
       }
       // epilogue: bias, activation streams; lane holds centres 4g+j of neuron nrow
       float bias = bl[nrow];
@@ -1059,7 +1076,7 @@ __global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4*
         }
         acc[0][j] = z;
         for (int s = 0; s < S; ++s) {
-          if (!last) buf[cur ^ 1][s][4 * g + j][nrow] = from_f<T>(vals[s]);
+          if (!last) buf[cur ^ 1][s][rpos(4 * g + j, nrow)] = from_f<T>(vals[s]);
           else vout[s][j] += wo * vals[s];
         }
         if (STORE) {
@@ -1097,7 +1114,8 @@ __global__ __launch_bounds__(256) void k_forward(const Meta* meta, const float4*
   __syncthreads();
   if (tid < kTile * S) {
     int c = tid / S, s = tid % S;
-    float v = part[0][c][s] + part[1][c][s] + part[2][c][s] + part[3][c][s];
+    float v = part[0][c][s];
+    for (int q = 1; q < NWV; ++q) v += part[q][c][s];
     if (s == 0) v += np.bout[0];
     if (slot0 + c < slot_end) outputs[(slot0 + c) * 8 + s] = v;
   }
@@ -1353,13 +1371,13 @@ struct Launch {
                             const Nets& nets, int L, float h, float* outputs, float* Zst, void* Ast,
                             float* ALst, int64_t lstride, bool store, bool streams, int noninline) {
     if (streams && store)
-      hipLaunchKernelGGL((k_forward<D, W, 2 * D + 1, ACT, PREC, true>), dim3(grid), dim3(256), 0, st,
+      hipLaunchKernelGGL((k_forward<D, W, 2 * D + 1, ACT, PREC, true>), dim3(grid), dim3(64 * FwdWaves<W>::v), 0, st,
                          meta, centres, nets, L, h, outputs, Zst, Ast, ALst, lstride, noninline);
     else if (streams)
-      hipLaunchKernelGGL((k_forward<D, W, 2 * D + 1, ACT, PREC, false>), dim3(grid), dim3(256), 0, st,
+      hipLaunchKernelGGL((k_forward<D, W, 2 * D + 1, ACT, PREC, false>), dim3(grid), dim3(64 * FwdWaves<W>::v), 0, st,
                          meta, centres, nets, L, h, outputs, Zst, Ast, ALst, lstride, noninline);
     else
-      hipLaunchKernelGGL((k_forward<D, W, 1, ACT, PREC, false>), dim3(grid), dim3(256), 0, st, meta,
+      hipLaunchKernelGGL((k_forward<D, W, 1, ACT, PREC, false>), dim3(grid), dim3(64 * FwdWaves<W>::v), 0, st, meta,
                          centres, nets, L, h, outputs, Zst, Ast, ALst, lstride, noninline);
     return hipGetLastError();
   }
