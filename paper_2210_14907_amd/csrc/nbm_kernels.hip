@@ -380,29 +380,31 @@ __global__ __launch_bounds__(256) void k_scatter(Problem P, const Meta* meta, co
 
 // ===========================================================================
 // Fourier forcing of every interior point (one thread per point).  Each
-// thread keeps its phase factors exp(i pi k x_a), k = 0..8, in LDS (rows
-// [a*9+k][thread], conflict-free); the modes come grouped by (k_y, k_z):
+// thread keeps its phase factors exp(i pi k x_a), k = 1..8, in LDS (rows
+// [1 + 8a + k - 1][thread], conflict-free; row 0 holds 1, the factor of
+// k = 0 on every axis); the modes come grouped by (k_y, k_z):
 //   f = Re sum_groups e^{i pi (k_y y + k_z z)} sum_{k_x in group} c e^{i pi k_x x},
 // one complex multiply-add per mode and one complex product per group; the
 // mode records are read eight at a time.
-// 128-thread blocks: the phase rows take 27 KB of LDS per block, so five
+// 128-thread blocks: the 25 phase rows take 25 KB of LDS per block, so six
 // blocks share a compute unit and hide the mode-record and LDS latencies.
 // ===========================================================================
 template <int D>
 __global__ __launch_bounds__(kForcingThreads) void k_forcing(Problem P, const float* pts, int64_t n,
                                                              float* fout, const Meta* meta, const int* cls,
                                                              const int* rank, float* fslot) {
-  __shared__ float2 ph[27][kForcingThreads];
+  __shared__ float2 ph[25][kForcingThreads];
   const int64_t i = (int64_t)blockIdx.x * kForcingThreads + threadIdx.x;
   const int t = threadIdx.x;
   float x[3] = {0.f, 0.f, 0.f};
   if (i < n)
     for (int a = 0; a < D; ++a) x[a] = pts[i * D + a];
+  ph[0][t] = make_float2(1.f, 0.f);
   for (int a = 0; a < 3; ++a)
-    for (int k = 0; k <= 8; ++k) {
+    for (int k = 1; k <= 8; ++k) {
       float sv, cv;
       sincospif((float)k * x[a], &sv, &cv);   // axes beyond D: x = 0, phase 1
-      ph[a * 9 + k][t] = make_float2(cv, sv);
+      ph[1 + 8 * a + k - 1][t] = make_float2(cv, sv);
     }
   // each thread reads only its own column: no barrier
   const char* col = reinterpret_cast<const char*>(&ph[0][t]);
