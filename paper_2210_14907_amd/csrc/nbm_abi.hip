@@ -285,20 +285,25 @@ extern "C" int nbm_create(const nbm_config* cfg, nbm_ctx** out) {
     std::map<std::pair<int, int>, std::vector<int>> byyz;
     for (int m = 0; m < P.n_modes; ++m) byyz[{c.mode_k[3 * m + 1], c.mode_k[3 * m + 2]}].push_back(m);
     constexpr int kRow = kForcingThreads * 8;   // bytes per phase row (one float2 per thread)
-    // the forcing kernel's phase rows: 0 holds 1 (k = 0 on any axis), then
-    // k = 1..8 of axis a at rows 1 + 8a + k - 1
-    auto row = [](int a, int k) { return k == 0 ? 0 : 1 + 8 * a + k - 1; };
+    // the forcing kernel's phase rows: 0 holds 1 (k = 0 on any axis), 1..8
+    // k_x = 1..8, 9..12 k_y = 1..4, 13..16 k_z = 1..4; a y or z offset with
+    // bit 1 set names the row of |k| - 4, to be multiplied by that of 4;
+    // bit 0 marks a negative wave number
+    auto yz_off = [](int a, int k) {
+      const int m = std::abs(k), r = m == 0 ? 0 : 4 * a + 4 + (m > 4 ? m - 4 : m);
+      return r * kRow + (m > 4 ? 2 : 0) + (k < 0 ? 1 : 0);
+    };
     for (const auto& kv : byyz) {
       const int ky = kv.first.first, kz = kv.first.second;
-      const int oy = row(1, std::abs(ky)) * kRow + (ky < 0 ? 1 : 0);
-      const int oz = row(2, std::abs(kz)) * kRow + (kz < 0 ? 1 : 0);
+      const int oy = yz_off(1, ky);
+      const int oz = yz_off(2, kz);
       for (size_t q = 0; q < kv.second.size(); ++q) {
         const int m = kv.second[q];
         FMode M;
         std::memset(&M, 0, sizeof(M));
         const int kx = c.mode_k[3 * m];
         const float sx = kx < 0 ? -1.0f : 1.0f;
-        M.ox = row(0, std::abs(kx)) * kRow;
+        M.ox = std::abs(kx) * kRow;
         M.cr = (float)c.mode_a[m];
         M.ci = (float)(-c.mode_b[m]);
         M.crs = M.cr * sx;

@@ -380,20 +380,22 @@ __global__ __launch_bounds__(256) void k_scatter(Problem P, const Meta* meta, co
 
 // ===========================================================================
 // Fourier forcing of every interior point (one thread per point).  Each
-// thread keeps its phase factors exp(i pi k x_a), k = 1..8, in LDS (rows
-// [1 + 8a + k - 1][thread], conflict-free; row 0 holds 1, the factor of
-// k = 0 on every axis); the modes come grouped by (k_y, k_z):
+// thread keeps its phase factors exp(i pi k x_a) in LDS (rows [row][thread],
+// conflict-free): row 0 holds 1 (k = 0 on any axis), rows 1..8 k_x = 1..8,
+// rows 9..12 k_y = 1..4 and rows 13..16 k_z = 1..4; |k_y|, |k_z| = 5..8 are
+// formed at their group's end as the factor of |k| - 4 times that of 4
+// (bit 1 of the group's offset).  The modes come grouped by (k_y, k_z):
 //   f = Re sum_groups e^{i pi (k_y y + k_z z)} sum_{k_x in group} c e^{i pi k_x x},
 // one complex multiply-add per mode and one complex product per group; the
 // mode records are read eight at a time.
-// 128-thread blocks: the 25 phase rows take 25 KB of LDS per block, so six
+// 128-thread blocks: the 17 phase rows take 17 KB of LDS per block, so nine
 // blocks share a compute unit and hide the mode-record and LDS latencies.
 // ===========================================================================
 template <int D>
 __global__ __launch_bounds__(kForcingThreads) void k_forcing(Problem P, const float* pts, int64_t n,
                                                              float* fout, const Meta* meta, const int* cls,
                                                              const int* rank, float* fslot) {
-  __shared__ float2 ph[25][kForcingThreads];
+  __shared__ float2 ph[17][kForcingThreads];
   const int64_t i = (int64_t)blockIdx.x * kForcingThreads + threadIdx.x;
   const int t = threadIdx.x;
   float x[3] = {0.f, 0.f, 0.f};
@@ -401,10 +403,10 @@ __global__ __launch_bounds__(kForcingThreads) void k_forcing(Problem P, const fl
     for (int a = 0; a < D; ++a) x[a] = pts[i * D + a];
   ph[0][t] = make_float2(1.f, 0.f);
   for (int a = 0; a < 3; ++a)
-    for (int k = 1; k <= 8; ++k) {
+    for (int k = 1; k <= (a == 0 ? 8 : 4); ++k) {
       float sv, cv;
       sincospif((float)k * x[a], &sv, &cv);   // axes beyond D: x = 0, phase 1
-      ph[1 + 8 * a + k - 1][t] = make_float2(cv, sv);
+      ph[a == 0 ? k : 4 * a + 4 + k][t] = make_float2(cv, sv);
     }
   // each thread reads only its own column: no barrier
   const char* col = reinterpret_cast<const char*>(&ph[0][t]);
@@ -424,8 +426,12 @@ __global__ __launch_bounds__(kForcingThreads) void k_forcing(Problem P, const fl
       sim += M[u].ci * e[u].x + M[u].crs * e[u].y;
       if (M[u].end) {
         // close the (k_y, k_z) group: times e^{i pi (k_y y + k_z z)}
-        const float2 ey = *reinterpret_cast<const float2*>(col + (M[u].oy & ~1));
-        const float2 ez = *reinterpret_cast<const float2*>(col + (M[u].oz & ~1));
+        float2 ey = *reinterpret_cast<const float2*>(col + (M[u].oy & ~3));
+        float2 ez = *reinterpret_cast<const float2*>(col + (M[u].oz & ~3));
+        // |k| = 5..8: times the factor of 4 (rows 12 and 16)
+        auto cmul = [](float2 p, float2 q) { return make_float2(p.x * q.x - p.y * q.y, p.x * q.y + p.y * q.x); };
+        if (M[u].oy & 2) ey = cmul(ey, *reinterpret_cast<const float2*>(col + 12 * kForcingThreads * 8));
+        if (M[u].oz & 2) ez = cmul(ez, *reinterpret_cast<const float2*>(col + 16 * kForcingThreads * 8));
         const float yi = (M[u].oy & 1) ? -ey.y : ey.y, zi = (M[u].oz & 1) ? -ez.y : ez.y;
         const float er = ey.x * ez.x - yi * zi, ei = yi * ez.x + ey.x * zi;
         acc += sre * er - sim * ei;
