@@ -31,7 +31,7 @@ HBM_PEAK = 8.0e12
 
 # counter summaries (rocprofv3 FETCH_SIZE / WRITE_SIZE) per dominant kernel,
 # valid while the sources they were taken from are unchanged
-_WIDE_SRC = ["nbm_wide.hip", "nbm_device.hpp", "nbm_internal.hpp", "nbm_launch.hpp"]
+_WIDE_SRC = ["nbm_wide.hip", "nbm_wide_dw.hip", "nbm_device.hpp", "nbm_internal.hpp", "nbm_launch.hpp"]
 # committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries: (kernel, workload) -> (file, sources)
 COUNTERS = {
     ("k_fused", "c2_sphere3d_tanh64x3_fp32"): ("c2_k_fused_counters.md", ["nbm_fused.hip", "nbm_device.hpp", "nbm_internal.hpp", "nbm_launch.hpp"]),

@@ -10,15 +10,20 @@ HERE = Path(__file__).resolve().parent
 CSRC = HERE / "csrc"
 BUILD = HERE / "_build"
 LIB = HERE / "libnbm.so"
-SOURCES = ["nbm_kernels.hip", "nbm_fused.hip", "nbm_wide.hip", "nbm_eval.hip", "nbm_abi.hip"]
+SOURCES = ["nbm_kernels.hip", "nbm_fused.hip", "nbm_wide.hip", "nbm_wide_dw.hip", "nbm_eval.hip",
+           "nbm_abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# per-source additions: the weight-gradient contraction schedules for
+# instruction-level parallelism (no register spills that way; the
+# forward/backward kernel, slower under this strategy, keeps the default)
+EXTRA = {"nbm_wide_dw.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 
 
 def _compile(src: str) -> Path:
     obj = BUILD / (Path(src).stem + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", str(CSRC / src), "-o", str(obj)]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", str(CSRC / src), "-o", str(obj)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
